@@ -1,0 +1,188 @@
+/*
+ * prior_ls.h -- C ABI of the MI355X (gfx950) Priori L+S reconstruction library.
+ *
+ * The library computes the iteration of Algorithm 1 of Zonoobi, Faghih Roohi and
+ * Kassim, "Low-Rank and Sparse Matrix Decomposition with a-priori knowledge for
+ * Dynamic 3D MRI reconstruction" (arXiv 1411.6206):
+ *
+ *   (0) X_0 = A^H(d), S_0 = 0                         (initialisation)
+ *   (1) L = SVT(X - S, lambda_L)                      (singular-value soft threshold)
+ *   (2) L: sigma <- sigma - lambda_p (sigma - sigma_prev)   (singular-value prior)
+ *   (3) S = T^{-1} soft(T(X - L_prev), lambda_S (1 - w))    (support-aware shrink)
+ *   (4) X = L + S - A^H(A(L + S) - d)                 (data consistency)
+ *
+ * where A is the undersampled multi-coil Cartesian Fourier operator of Section 2
+ * (frame-by-frame k-space undersampling with a mask, coil sensitivities C_c), the
+ * adjoint is written A^{-1} in the paper's Notations, the Casorati matrix has the
+ * voxels of one volume as rows and the nt time frames as columns, T is an
+ * orthonormal Haar wavelet (nonstandard pyramid over the spatial axes of size > 1,
+ * J levels), and the a-priori support of T(S^(t-1)) enters as per-coefficient
+ * weights w = q/255 (w = 1 on the support: the coefficient is not shrunk; w = 0:
+ * plain L+S threshold).
+ *
+ * Memory.  Every array argument is DEVICE memory owned by the caller, except
+ * `sigma_prev` (host memory, nt doubles, copied during the call).  Complex
+ * arrays are interleaved complex64 (float re, float im), C order, x fastest:
+ *     images (L0, S0, L, S, X, M)   [nt][nz][ny][nx]
+ *     k-space                       [nc][nt][nz][ny][nx]  (kz, ky, kx; unshifted, DC at 0)
+ *     mask                          uint8 [nt][nz][ny], nonzero = that (kz, ky) phase-encode
+ *                                   line is sampled for every kx (readout fully sampled)
+ *     coil sensitivities            [nc][nz][ny][nx]; NULL means nc == 1 with unit coil
+ *     prior weights                 uint8 [nt][nz][ny][nx] in canonical (Mallat) Haar
+ *                                   coefficient layout, weight q/255; NULL means all zero
+ * The DFT is unitary (1/sqrt(n) on each axis).  k-space entries off the mask are ignored.
+ *
+ * Streams and threads.  All device work is enqueued on the hipStream_t given to
+ * prior_ls_create (NULL = the default stream).  solve/step return after that stream
+ * has completed the requested work (they read the convergence statistics).  A handle
+ * is used by one host thread at a time; distinct handles are independent.
+ *
+ * Errors.  Functions return 0 (PRIOR_LS_OK) or a negative status.  The handle keeps
+ * a message for the last error (prior_ls_last_error).  Non-convergence is not an
+ * error (stats.converged = 0).
+ */
+#ifndef PRIOR_LS_H
+#define PRIOR_LS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PRIOR_LS_OK          0
+#define PRIOR_LS_EINVAL     -1  /* NULL required pointer, host pointer where device memory is
+                                   required, lambda < 0, lambda_p outside [0,1], struct_size
+                                   mismatch, L0 without S0, n_iter < 0, step before solve */
+#define PRIOR_LS_ESHAPE     -2  /* unsupported shape: see prior_ls_dims */
+#define PRIOR_LS_ENOMEM     -3  /* device allocation failed or plan exceeds hbm_budget */
+#define PRIOR_LS_EHIP       -4  /* HIP runtime error (no device, launch failure, ...) */
+#define PRIOR_LS_ENONFINITE -5  /* NaN/Inf reached the iterate (stats.nonfinite = 1) */
+
+#define PRIOR_LS_GRAM_FP64   0  /* Casorati Gram on FP64 MFMA from FP32 data: exact products,
+                                   FP64 sums (default) */
+#define PRIOR_LS_GRAM_FP32   1  /* Gram on FP32 MFMA, FP64 across blocks */
+#define PRIOR_LS_GRAM_BF16X3 2  /* Gram on BF16 MFMA with hi+lo split (3 products), FP32
+                                   accumulate, FP64 across blocks */
+
+#define PRIOR_LS_MAX_NT 32
+
+typedef struct prior_ls_handle prior_ls_handle;   /* opaque; owns all device state */
+
+/* Problem geometry, fixed for the life of a handle.
+ * Supported: ny in {16,24,32,48,64,96,128,192,256}, nz in {1,4,8,16,32} (nz = 1 is the 2D
+ * case), nx in {16,24,32,48,64,96,128,192,256}, 1 <= nt <= 32, 1 <= nc <= 64,
+ * wavelet_levels J in [0,3] with every spatial axis of size > 1 divisible by 2^J
+ * (J = 0 means T is the identity).  Anything else returns PRIOR_LS_ESHAPE. */
+typedef struct {
+    size_t   struct_size;       /* = sizeof(prior_ls_dims) */
+    int32_t  nx, ny, nz, nt, nc;
+    int32_t  wavelet_levels;    /* J */
+    int32_t  gram_mode;         /* PRIOR_LS_GRAM_* */
+    int32_t  reserved;          /* must be 0 */
+    uint64_t hbm_budget;        /* bytes of device memory the handle may own; 0 = unlimited */
+} prior_ls_dims;
+
+/* Per-solve settings (Algorithm 1 inputs lambda_L (= the paper's lambda_T), lambda_S, and
+ * the step size lambda_p of step (2); stopping rule of Section 3). */
+typedef struct {
+    size_t  struct_size;        /* = sizeof(prior_ls_params) */
+    double  lambda_L;           /* >= 0; relative to sigma_1 of the current X - S if
+                                   lambda_L_relative != 0, else absolute */
+    double  lambda_S;           /* >= 0, absolute, in transform-domain units */
+    double  lambda_p;           /* in [0,1]; 0 switches step (2) off */
+    double  tol;                /* stop when ||Y_k - Y_{k-1}|| / ||Y_{k-1}|| < tol, Y = L + S,
+                                   tested at the end of every chunk of check_every
+                                   iterations; 0 = run exactly max_iter iterations */
+    int32_t lambda_L_relative;
+    int32_t max_iter;           /* >= 0; 0 only loads the problem and forms X_0 */
+    int32_t check_every;        /* >= 1; iterations per device chunk (one hipGraph) */
+    int32_t use_graph;          /* nonzero: replay chunks as captured hipGraphs */
+} prior_ls_params;
+
+typedef struct {
+    const void    *kspace;      /* complex64 [nc][nt][nz][ny][nx], required */
+    const uint8_t *mask;        /* uint8 [nt][nz][ny], required */
+    const void    *sens;        /* complex64 [nc][nz][ny][nx]; NULL only when nc == 1 */
+    const uint8_t *prior_w;     /* uint8 [nt][nz][ny][nx] canonical Haar layout, or NULL */
+    const double  *sigma_prev;  /* HOST, nt doubles (singular values of L^(t-1), any order);
+                                   required when lambda_p > 0, else ignored */
+    const void    *L0, *S0;     /* complex64 [nt][nz][ny][nx] warm start: both or neither.
+                                   Cold: L = X_0 = A^H d, S = 0.  Warm: L = L0, S = S0 and
+                                   X_0 = Y - A^H(A Y - d) with Y = L0 + S0 */
+} prior_ls_inputs;
+
+/* Output buffers, complex64 [nt][nz][ny][nx] device memory; any may be NULL (skipped).
+ * X = L + S (the reconstructed image), M = the data-consistent iterate X_it of step (4). */
+typedef struct {
+    void *L, *S, *X, *M;
+} prior_ls_outputs;
+
+typedef struct {
+    size_t  struct_size;        /* = sizeof(prior_ls_stats), set by the caller */
+    int32_t iters;              /* iterations run since the last solve (cumulative with step) */
+    int32_t converged;          /* rel_change < tol at the last check */
+    int32_t nonfinite;
+    int32_t sigma_count;        /* = nt */
+    double  rel_change;         /* ||Y_k - Y_{k-1}|| / ||Y_{k-1}|| at the last iteration */
+    double  resid_norm;         /* ||A(L_k + S_k) - d|| over the sampled entries (FP64) */
+    double  nuclear_norm;       /* sum of the singular values of L_k */
+    double  l1_weighted;        /* sum over coefficients of (1 - w) |T(S_k)| */
+    double  objective;          /* 0.5 resid^2 + tau_L nuclear + lambda_S l1_weighted */
+    double  tau_L;              /* singular-value threshold used at the last iteration */
+    double  sigma[PRIOR_LS_MAX_NT];  /* singular values of X_{k-1} - S_{k-1}, descending */
+    double  ms;                 /* wall time of the call, milliseconds */
+} prior_ls_stats;
+
+/* Create a handle for one problem geometry; allocates the device state on the current
+ * HIP device.  On failure *out is set to NULL.  `stream` is a hipStream_t (NULL = default). */
+int prior_ls_create(const prior_ls_dims *dims, void *stream, prior_ls_handle **out);
+
+/* Load the problem (k-space, mask, sensitivities, prior weights, sigma_prev, optional warm
+ * start), form X_0 (step (0)), then run up to params->max_iter iterations of Algorithm 1
+ * (steps (1)-(4)).  Writes the requested outputs and, if stats != NULL, the statistics.
+ * Inputs may be freed after the call returns. */
+int prior_ls_solve(prior_ls_handle *h, const prior_ls_inputs *in, const prior_ls_params *params,
+                   const prior_ls_outputs *out, prior_ls_stats *stats);
+
+/* Continue the resident iteration for n_iter more iterations (same parameters as the last
+ * solve; n_iter = 0 only writes outputs).  solve(K1) followed by step(K2) computes exactly
+ * what solve(K1 + K2) computes. */
+int prior_ls_step(prior_ls_handle *h, int32_t n_iter, const prior_ls_outputs *out,
+                  prior_ls_stats *stats);
+
+/* Release every resource of the handle.  NULL is a no-op. */
+void prior_ls_destroy(prior_ls_handle *h);
+
+/* Static description of a status code. */
+const char *prior_ls_strerror(int status);
+
+/* Message of the last error on this handle ("" if none); NULL handle -> the last error of
+ * a failed prior_ls_create on this thread. */
+const char *prior_ls_last_error(const prior_ls_handle *h);
+
+/* Device bytes a handle of these dimensions allocates at create time (excluding the
+ * compact k-space, which is sized at solve from the mask).  0 for invalid dims. */
+uint64_t prior_ls_plan_bytes(const prior_ls_dims *dims);
+
+/* ---- Step-level entry points.  They act on the problem loaded by the last solve and do
+ * not change the resident iterate.  Arrays are complex64 device memory in image layout
+ * [nt][nz][ny][nx]. ---- */
+
+/* Step (4), data consistency: M = Y - A^H(A(Y) - d).  *resid_norm (host, may be NULL)
+ * receives ||A(Y) - d||. */
+int prior_ls_op_dc(prior_ls_handle *h, const void *Y, void *M, double *resid_norm);
+
+/* Steps (1)-(2) on the Casorati matrix of C (voxels x frames): L = U diag(sigma_tilde) V^H
+ * with the handle's lambda_L / lambda_p / sigma_prev.  sigma (host, nt doubles, may be
+ * NULL) receives the singular values of C, descending. */
+int prior_ls_op_svt(prior_ls_handle *h, const void *C, void *L, double *sigma);
+
+/* Step (3): S = T^{-1} soft(T(Xm - Lp), lambda_S (1 - w)) with the handle's weights. */
+int prior_ls_op_sparse(prior_ls_handle *h, const void *Xm, const void *Lp, void *S);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRIOR_LS_H */

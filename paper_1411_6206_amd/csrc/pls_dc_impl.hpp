@@ -1,0 +1,237 @@
+// Data consistency, step (4) of Algorithm 1, and the set-up kx inverse DFT.
+//
+// For a Cartesian mask that is constant along kx, F^H m F = F_yz^H m F_yz per x plane,
+// so with the data taken once through the unitary kx-IDFT (dh, see pls_xifft) the
+// normal operator needs only 2D (y, z) FFTs.  One block owns PB (t, x) planes and, for
+// every coil c, forms C_c Y, transforms it, replaces the sampled entries by the residual
+// F(C_c Y) - dh and zeroes the rest, transforms back and accumulates conj(C_c) times the
+// result.  It writes C = L - sum_c conj(C_c) F^H(m F(C_c Y) - dh) = M - S.
+#pragma once
+
+#include "pls_fft.hpp"
+#include "pls_kernels.hpp"
+
+namespace pls {
+
+template <int NY, int NZ>
+struct DcCfg {
+    static constexpr int P = NY * NZ;
+    static constexpr bool kHas3 = (NY % 3 == 0);
+    static constexpr int Q0 = kHas3 ? 24 : 16;
+    static constexpr int Q = (P / Q0 > 256) ? P / 256 : Q0;
+    static constexpr int PB = (P / Q >= 64) ? 1 : (64 * Q) / P;
+    using G = Geom<NY, NZ, PB, Q, 5>;
+};
+
+template <class G, bool STATS>
+__global__ void __launch_bounds__(G::T) pls_dc_kernel(DcArgs a) {
+    constexpr int Q = G::Q, P = G::P, NY = G::NY, NZ = G::NZ, PB = G::PB;
+    constexpr int R0 = radix_in<G>();
+    constexpr int RL = radix_out<G>();
+    __shared__ float2 lds[G::LDS_ELEMS];
+    __shared__ float2 twy[NY];
+    __shared__ float2 twz[NZ];
+    __shared__ double red[G::T / kWave];
+    const int tid = threadIdx.x;
+    for (int m = tid; m < NY; m += G::T) twy[m] = a.twy[m];
+    for (int m = tid; m < NZ; m += G::T) twz[m] = a.twz[m];
+
+    const int t = blockIdx.x % a.nt;
+    const int x0 = (blockIdx.x / a.nt) * PB;
+    const size_t frame = (size_t)t * a.nx * P;
+    const bool has_y = (a.L != nullptr);
+
+    float2 Y[Q], acc[Q], v[Q];
+    double dy2 = 0.0, y2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q / R0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            int pb, z, y;
+            pos_in<G>(tid, i, r, pb, z, y);
+            const int q = i * R0 + r;
+            float2 yv = make_float2(0.f, 0.f);
+            if (has_y && x0 + pb < a.nx) {
+                const size_t gi = frame + (size_t)(x0 + pb) * P + z * NY + y;
+                yv = a.S ? cadd(a.L[gi], a.S[gi]) : a.L[gi];
+                if constexpr (STATS) {
+                    const float2 yo = cadd(a.Lold[gi], a.Sold[gi]);
+                    const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
+                    dy2 += dx * dx + dyy * dyy;
+                    y2 += (double)yo.x * yo.x + (double)yo.y * yo.y;
+                }
+            }
+            Y[q] = yv;
+            acc[q] = make_float2(0.f, 0.f);
+        }
+
+    const int nst = a.ns[t];
+    const int off = a.dh_off[t];
+    double res2 = 0.0;
+    for (int c = 0; c < a.nc; ++c) {
+        const float2* sc = a.sens ? a.sens + (size_t)c * a.nx * P : nullptr;
+#pragma unroll
+        for (int i = 0; i < Q / R0; ++i)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                int pb, z, y;
+                pos_in<G>(tid, i, r, pb, z, y);
+                const int q = i * R0 + r;
+                float2 sv = make_float2(1.f, 0.f);
+                if (sc && x0 + pb < a.nx) sv = sc[(size_t)(x0 + pb) * P + z * NY + y];
+                v[q] = cmul(sv, Y[q]);
+            }
+        __syncthreads();  // twiddle tables visible; previous LDS reads finished
+        fft2_fwd<G>(v, lds, twy, twz);
+#pragma unroll
+        for (int i = 0; i < Q / RL; ++i)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                int pb, z, y;
+                pos_out<G>(tid, i, r, pb, z, y);
+                const int q = i * RL + r;
+                const int s = a.sidx[(size_t)t * P + z * NY + y];
+                float2 rv = make_float2(0.f, 0.f);
+                if (s >= 0 && x0 + pb < a.nx) {
+                    const float2 d = a.dh[off + ((size_t)(x0 + pb) * a.nc + c) * nst + s];
+                    rv = make_float2(fmaf(v[q].x, a.inv_p, -d.x), fmaf(v[q].y, a.inv_p, -d.y));
+                    res2 += (double)rv.x * rv.x + (double)rv.y * rv.y;
+                }
+                v[q] = rv;
+            }
+        fft2_inv<G>(v, lds, twy, twz);
+#pragma unroll
+        for (int i = 0; i < Q / R0; ++i)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                int pb, z, y;
+                pos_in<G>(tid, i, r, pb, z, y);
+                const int q = i * R0 + r;
+                float2 sv = make_float2(1.f, 0.f);
+                if (sc && x0 + pb < a.nx) sv = sc[(size_t)(x0 + pb) * P + z * NY + y];
+                acc[q] = cadd(acc[q], cmulc(v[q], sv));
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < Q / R0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            int pb, z, y;
+            pos_in<G>(tid, i, r, pb, z, y);
+            const int q = i * R0 + r;
+            if (x0 + pb < a.nx) {
+                const size_t gi = frame + (size_t)(x0 + pb) * P + z * NY + y;
+                const float2 l = has_y ? a.L[gi] : make_float2(0.f, 0.f);
+                a.C[gi] = csub(l, acc[q]);
+            }
+        }
+    const double s0 = block_sum<G::T>(res2, red);
+    double s1 = 0.0, s2 = 0.0;
+    if constexpr (STATS) {
+        s1 = block_sum<G::T>(dy2, red);
+        s2 = block_sum<G::T>(y2, red);
+    }
+    if (tid == 0) {
+        a.part[blockIdx.x * 4 + 0] = s0;
+        a.part[blockIdx.x * 4 + 1] = s1;
+        a.part[blockIdx.x * 4 + 2] = s2;
+        a.part[blockIdx.x * 4 + 3] = 0.0;
+    }
+}
+
+// Unitary inverse DFT along kx of every sampled (c, t, kz, ky) line, scaled by 1/sqrt(P),
+// scattered into the compact hybrid layout.
+template <class G>
+__global__ void __launch_bounds__(G::T) pls_xifft_kernel(XiArgs a) {
+    constexpr int Q = G::Q, NX = G::NY, PB = G::PB;
+    constexpr int R0 = radix_in<G>();
+    constexpr int RL = radix_out<G>();
+    __shared__ float2 lds[G::LDS_ELEMS];
+    __shared__ float2 twx[NX];
+    const int tid = threadIdx.x;
+    for (int m = tid; m < NX; m += G::T) twx[m] = a.twx[m];
+    __syncthreads();
+    float2 v[Q];
+#pragma unroll
+    for (int i = 0; i < Q / R0; ++i)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            int pb, z, x;
+            pos_in<G>(tid, i, r, pb, z, x);
+            const int line = blockIdx.x * PB + pb;
+            float2 val = make_float2(0.f, 0.f);
+            if (line < a.total_lines) {
+                int t = 0;
+                while (line >= a.line_off[t + 1]) ++t;
+                const int rem = line - a.line_off[t];
+                const int c = rem / a.ns[t];
+                const int s = rem % a.ns[t];
+                const int pos = a.plist[(size_t)t * a.P + s];
+                val = a.kspace[((size_t)(c * a.nt + t) * a.P + pos) * NX + x];
+            }
+            v[i * R0 + r] = val;
+        }
+    // inverse transform; the plane machinery with NZ = 1 runs only y (= x here) passes
+    {
+        constexpr int NP = G::NPY;
+        sfor<NP>([&](auto pI) {
+            constexpr int p = decltype(pI)::value;
+            constexpr int R = G::PY.r[p];
+            constexpr int LS = plan_prod(G::PY, p);
+            fft_pass<G, 0, R, LS, true, p == 0, p == NP - 1>(v, lds, twx);
+        });
+    }
+#pragma unroll
+    for (int i = 0; i < Q / RL; ++i)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            int pb, z, x;
+            pass_pos<G, 0, RL>(tid, i, r, pb, z, x);
+            const int line = blockIdx.x * PB + pb;
+            if (line < a.total_lines) {
+                int t = 0;
+                while (line >= a.line_off[t + 1]) ++t;
+                const int rem = line - a.line_off[t];
+                const int c = rem / a.ns[t];
+                const int s = rem % a.ns[t];
+                a.dh[a.dh_off[t] + ((size_t)x * a.nc + c) * a.ns[t] + s] =
+                    cscale(v[i * RL + r], a.scale);
+            }
+        }
+}
+
+template <int NY, int NZ>
+inline int dc_grid(int nx, int nt) {
+    using C = DcCfg<NY, NZ>;
+    return ((nx + C::PB - 1) / C::PB) * nt;
+}
+
+template <int NY, int NZ>
+inline int dc_launch_t(bool stats, const DcArgs& a, hipStream_t s) {
+    using G = typename DcCfg<NY, NZ>::G;
+    const int grid = dc_grid<NY, NZ>(a.nx, a.nt);
+    if (stats)
+        hipLaunchKernelGGL((pls_dc_kernel<G, true>), dim3(grid), dim3(G::T), 0, s, a);
+    else
+        hipLaunchKernelGGL((pls_dc_kernel<G, false>), dim3(grid), dim3(G::T), 0, s, a);
+    return grid;
+}
+
+template <int NX>
+inline void xifft_launch_t(const XiArgs& a, hipStream_t s) {
+    using G = typename DcCfg<NX, 1>::G;
+    const int grid = (a.total_lines + G::PB - 1) / G::PB;
+    if (grid > 0) hipLaunchKernelGGL((pls_xifft_kernel<G>), dim3(grid), dim3(G::T), 0, s, a);
+}
+
+// Per-nz translation units (pls_dc_nz*.hip) instantiate the kernels; these return -1 when
+// the shape is not theirs.
+int dc_launch_nz1(int ny, bool stats, const DcArgs& a, hipStream_t s);
+int dc_launch_nz4(int ny, bool stats, const DcArgs& a, hipStream_t s);
+int dc_launch_nz8(int ny, bool stats, const DcArgs& a, hipStream_t s);
+int dc_launch_nz16(int ny, bool stats, const DcArgs& a, hipStream_t s);
+int dc_launch_nz32(int ny, bool stats, const DcArgs& a, hipStream_t s);
+bool xifft_launch_any(int nx, const XiArgs& a, hipStream_t s);
+
+}  // namespace pls
+

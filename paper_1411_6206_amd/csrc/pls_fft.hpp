@@ -1,0 +1,300 @@
+// LDS-staged mixed-radix Stockham FFT over (y, z) planes, wave64 / gfx950.
+//
+// A block owns PB planes of NY x NZ complex points (y fastest).  Every thread keeps
+// Q points in registers.  A 1D FFT along one axis is a sequence of radix-R passes; in
+// pass p (stage length Ls = product of the earlier radices on that axis) butterfly j
+// of a line reads the points j + r*N/R, multiplies point r by exp(-+2 pi i k r/(Ls R))
+// with k = j mod Ls, takes an R-point DFT in registers and writes point r to
+// (j / Ls) Ls R + (j mod Ls) + r Ls (Stockham autosort: natural order in and out).
+// Between passes the plane goes through LDS; the first pass of a transform reads the
+// thread's registers and the last one leaves its result in registers.  Because the
+// last pass of a transform writes exactly the positions that a first pass of the same
+// radix reads, a forward transform whose last radix is the inverse transform's first
+// radix hands its registers straight to the inverse (no LDS round trip), and the
+// inverse's last pass returns the data in the distribution the forward pass read.
+#pragma once
+
+#include "pls_common.hpp"
+
+namespace pls {
+
+// ---------------------------------------------------------------- in-register DFTs
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* x) {
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) {
+        const float2 a = x[0], b = x[1];
+        x[0] = cadd(a, b);
+        x[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        constexpr float kS3 = 0.866025403784438646763723170752936183f;  // sqrt(3)/2
+        const float2 t1 = cadd(x[1], x[2]);
+        const float2 t2 = csub(x[1], x[2]);
+        const float2 m1 = make_float2(fmaf(-0.5f, t1.x, x[0].x), fmaf(-0.5f, t1.y, x[0].y));
+        // forward: -i * sqrt(3)/2 * t2, inverse: +i * sqrt(3)/2 * t2
+        const float2 m2 = INV ? make_float2(-kS3 * t2.y, kS3 * t2.x)
+                              : make_float2(kS3 * t2.y, -kS3 * t2.x);
+        x[0] = cadd(x[0], t1);
+        x[1] = cadd(m1, m2);
+        x[2] = csub(m1, m2);
+    } else if constexpr (R == 4) {
+        const float2 a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+        const float2 c = cadd(x[1], x[3]), d = csub(x[1], x[3]);
+        const float2 e = INV ? cmul_pi(d) : cmul_mi(d);
+        x[0] = cadd(a, c);
+        x[2] = csub(a, c);
+        x[1] = cadd(b, e);
+        x[3] = csub(b, e);
+    } else {
+        // R = A B:  X[c + A d] = sum_b w_B^{bd} w_R^{bc} sum_a x[B a + b] w_A^{ac}
+        constexpr int A = (R % 4 == 0) ? 4 : ((R % 2 == 0) ? 2 : 3);
+        constexpr int B = R / A;
+        float2 t[R];
+        sfor<B>([&](auto bI) {
+            constexpr int b = decltype(bI)::value;
+            float2 y[A];
+            sfor<A>([&](auto aI) { y[decltype(aI)::value] = x[B * decltype(aI)::value + b]; });
+            dft<A, INV>(y);
+            sfor<A>([&](auto cI) {
+                constexpr int c = decltype(cI)::value;
+                t[c * B + b] = ctw<b * c, R, INV>(y[c]);
+            });
+        });
+        sfor<A>([&](auto cI) {
+            constexpr int c = decltype(cI)::value;
+            float2 z[B];
+            sfor<B>([&](auto bI) { z[decltype(bI)::value] = t[c * B + decltype(bI)::value]; });
+            dft<B, INV>(z);
+            sfor<B>([&](auto dI) { x[c + A * decltype(dI)::value] = z[decltype(dI)::value]; });
+        });
+    }
+}
+
+// ---------------------------------------------------------------- radix planning
+struct RadixPlan {
+    int n;
+    int r[8];
+};
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+// Factor N into radices that each divide Q (so every thread holds whole butterflies),
+// each <= 32, sorted ascending.  n = -1 when impossible.
+constexpr RadixPlan plan_axis(int N, int Q) {
+    RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    int rem = N;
+    while (rem > 1) {
+        int g = cgcd(rem, Q);
+        while (g > 32) {
+            int d = 32;
+            while (d > 1 && g % d != 0) --d;
+            g = d;
+        }
+        if (g <= 1 || p.n >= 8) {
+            p.n = -1;
+            return p;
+        }
+        p.r[p.n++] = g;
+        rem /= g;
+    }
+    for (int i = 0; i < p.n; ++i)
+        for (int j = i + 1; j < p.n; ++j)
+            if (p.r[j] < p.r[i]) {
+                int t = p.r[i];
+                p.r[i] = p.r[j];
+                p.r[j] = t;
+            }
+    return p;
+}
+
+constexpr int plan_prod(const RadixPlan& p, int upto) {
+    int s = 1;
+    for (int i = 0; i < upto; ++i) s *= p.r[i];
+    return s;
+}
+
+// ---------------------------------------------------------------- plane geometry
+template <int NY_, int NZ_, int PB_, int Q_, int PADSH_>
+struct Geom {
+    static constexpr int NY = NY_, NZ = NZ_, PB = PB_, Q = Q_;
+    static constexpr int P = NY * NZ;
+    static constexpr int T = PB * P / Q;
+    // LDS address of linear plane index e = (pb * NZ + z) * NY + y: one pad element
+    // every 2^PADSH elements spreads strided Stockham accesses over the LDS banks.
+    static constexpr int PADSH = PADSH_;
+    static constexpr int LDS_ELEMS = PB * P + (PADSH > 0 ? ((PB * P) >> PADSH) : 0) + 1;
+    static constexpr RadixPlan PY = plan_axis(NY, Q);
+    static constexpr RadixPlan PZ = plan_axis(NZ, Q);
+    static constexpr int NPY = PY.n;
+    static constexpr int NPZ = PZ.n;
+    static_assert(PB * P % Q == 0, "Q must divide the block's points");
+    static_assert(T % 64 == 0 && T <= 1024, "threads must be whole waves");
+    static_assert(NPY >= 1 && NPZ >= 0, "axis not factorable with this Q");
+    __device__ static __forceinline__ int lds_addr(int e) {
+        if constexpr (PADSH > 0) return e + (e >> PADSH);
+        else return e;
+    }
+};
+
+// Position (plane, z, y) of element (i, r) of a thread's registers in the distribution
+// that a first pass of radix R along axis AX (0 = y, 1 = z) reads.
+template <class G, int AX, int R>
+__device__ __forceinline__ void pass_pos(int tid, int i, int r, int& pb, int& z, int& y) {
+    const int b = tid + i * G::T;
+    if constexpr (AX == 0) {
+        constexpr int JN = G::NY / R;
+        const int j = b % JN;
+        const int line = b / JN;
+        z = line % G::NZ;
+        pb = line / G::NZ;
+        y = j + r * JN;
+    } else {
+        constexpr int JN = G::NZ / R;
+        y = b % G::NY;
+        const int rest = b / G::NY;
+        const int j = rest % JN;
+        pb = rest / JN;
+        z = j + r * JN;
+    }
+}
+
+// One Stockham pass.  tw = exp(-2 pi i m / N), m in [0, N), for this axis' length N.
+template <class G, int AX, int R, int LS, bool INV, bool IN_REG, bool OUT_REG>
+__device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const float2* tw) {
+    constexpr int N = (AX == 0) ? G::NY : G::NZ;
+    constexpr int JN = N / R;
+    constexpr int NB = G::Q / R;
+    constexpr int STRIDE = (AX == 0) ? 1 : G::NY;
+    static_assert(G::Q % R == 0 && N % (R * LS) == 0, "bad pass");
+    const int tid = threadIdx.x;
+    int base[NB], jj[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * G::T;
+        if constexpr (AX == 0) {
+            jj[i] = b % JN;
+            base[i] = (b / JN) * G::NY;           // line = pb * NZ + z
+        } else {
+            const int y = b % G::NY;
+            const int rest = b / G::NY;
+            jj[i] = rest % JN;
+            base[i] = (rest / JN) * G::P + y;
+        }
+    }
+    if constexpr (!IN_REG) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[i * R + r] = lds[G::lds_addr(base[i] + (jj[i] + r * JN) * STRIDE)];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if constexpr (LS > 1) {
+            const int k = jj[i] % LS;
+            constexpr int step = N / (LS * R);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[k * r * step];
+                if (INV) w.y = -w.y;
+                v[i * R + r] = cmul(v[i * R + r], w);
+            }
+        }
+        dft<R, INV>(&v[i * R]);
+    }
+    if constexpr (!OUT_REG) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = jj[i];
+            const int o = (j / LS) * LS * R + (j % LS);
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[G::lds_addr(base[i] + (o + r * LS) * STRIDE)] = v[i * R + r];
+        }
+        __syncthreads();
+    }
+}
+
+// Forward 2D transform: y passes (ascending radices) then z passes (ascending).
+// Input: registers in the distribution of the first y pass; output: registers in the
+// distribution of a first pass of radix (last z radix) along z (or y when NZ == 1).
+template <class G>
+__device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const float2* twy,
+                                         const float2* twz) {
+    constexpr int NPY = G::NPY, NPZ = G::NPZ, NP = NPY + NPZ;
+    sfor<NP>([&](auto pI) {
+        constexpr int p = decltype(pI)::value;
+        constexpr bool IN_REG = (p == 0);
+        constexpr bool OUT_REG = (p == NP - 1);
+        if constexpr (p < NPY) {
+            constexpr int R = G::PY.r[p];
+            constexpr int LS = plan_prod(G::PY, p);
+            fft_pass<G, 0, R, LS, false, IN_REG, OUT_REG>(v, lds, twy);
+        } else {
+            constexpr int q = p - NPY;
+            constexpr int R = G::PZ.r[q];
+            constexpr int LS = plan_prod(G::PZ, q);
+            fft_pass<G, 1, R, LS, false, IN_REG, OUT_REG>(v, lds, twz);
+        }
+    });
+}
+
+// Inverse 2D transform (unnormalised): z passes in descending radix order, then y passes
+// in descending order.  Reads the registers fft2_fwd left and returns them in the
+// distribution fft2_fwd read.
+template <class G>
+__device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const float2* twy,
+                                         const float2* twz) {
+    constexpr int NPY = G::NPY, NPZ = G::NPZ, NP = NPY + NPZ;
+    sfor<NP>([&](auto pI) {
+        constexpr int p = decltype(pI)::value;
+        constexpr bool IN_REG = (p == 0);
+        constexpr bool OUT_REG = (p == NP - 1);
+        if constexpr (p < NPZ) {
+            constexpr int idx = NPZ - 1 - p;          // radices reversed
+            constexpr int R = G::PZ.r[idx];
+            constexpr int LS = [] {
+                int s = 1;
+                for (int u = NPZ - 1; u > idx; --u) s *= G::PZ.r[u];
+                return s;
+            }();
+            fft_pass<G, 1, R, LS, true, IN_REG, OUT_REG>(v, lds, twz);
+        } else {
+            constexpr int q = p - NPZ;
+            constexpr int idx = NPY - 1 - q;
+            constexpr int R = G::PY.r[idx];
+            constexpr int LS = [] {
+                int s = 1;
+                for (int u = NPY - 1; u > idx; --u) s *= G::PY.r[u];
+                return s;
+            }();
+            fft_pass<G, 0, R, LS, true, IN_REG, OUT_REG>(v, lds, twy);
+        }
+    });
+}
+
+// Input distribution of fft2_fwd (= output distribution of fft2_inv).
+template <class G>
+__device__ __forceinline__ void pos_in(int tid, int i, int r, int& pb, int& z, int& y) {
+    constexpr int R0 = G::PY.r[0];
+    pass_pos<G, 0, R0>(tid, i, r, pb, z, y);
+}
+// Output distribution of fft2_fwd (= input distribution of fft2_inv).
+template <class G>
+__device__ __forceinline__ void pos_out(int tid, int i, int r, int& pb, int& z, int& y) {
+    if constexpr (G::NPZ > 0) {
+        constexpr int RL = G::PZ.r[G::NPZ - 1];
+        pass_pos<G, 1, RL>(tid, i, r, pb, z, y);
+    } else {
+        constexpr int RL = G::PY.r[G::NPY - 1];
+        pass_pos<G, 0, RL>(tid, i, r, pb, z, y);
+    }
+}
+
+// Radix of the element-grouping used by pos_in / pos_out.
+template <class G>
+constexpr int radix_in() { return G::PY.r[0]; }
+template <class G>
+constexpr int radix_out() { return G::NPZ > 0 ? G::PZ.r[G::NPZ - 1] : G::PY.r[G::NPY - 1]; }
+
+}  // namespace pls

@@ -1,0 +1,406 @@
+// Step (1) of Algorithm 1, first half: the Gram matrix G = C^H C of the Casorati matrix
+// C = X - S (voxels x frames), its Hermitian eigendecomposition G = V diag(sigma^2) V^H,
+// and the frame-space operator W = V diag(sigma_tilde / sigma) V^H that turns the
+// singular-value soft threshold (step 1) and the singular-value prior (step 2) into one
+// product L = C W.
+//
+// The Gram is accumulated on the real-expanded matrix R = [Re C | Im C] (N x 2*16*NB) with
+// MFMA: G_R = R^T R holds Re G = A^T A + B^T B and Im G = A^T B - B^T A (A = Re C,
+// B = Im C).  Only the tiles on and above the diagonal are formed.
+#include "pls_common.hpp"
+#include "pls_kernels.hpp"
+
+namespace pls {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGramBlocks = 512;
+
+template <int NB>
+constexpr int npair() { return (2 * NB) * (2 * NB + 1) / 2; }
+
+int gram_tiles(int nt) { return nt <= 16 ? npair<1>() : npair<2>(); }
+
+int gram_blocks(int N) {
+    int vpb = (N + kGramBlocks - 1) / kGramBlocks;
+    vpb = (vpb + 63) / 64 * 64;
+    return (N + vpb - 1) / vpb;
+}
+
+// ---------------------------------------------------------------- FP64 MFMA Gram
+// Lane (i, g) = (lane % 16, lane / 16).  A wave takes chunks of 16 voxels; lane group g
+// covers voxels 4g..4g+3 of the chunk, one per K step of v_mfma_f64_16x16x4.  The lane
+// loads frames i and 16 + i of those voxels (32 contiguous bytes per frame).
+template <int NB>
+__global__ void __launch_bounds__(256) pls_gram_f64_kernel(GramArgs a) {
+    constexpr int NT4 = 2 * NB;
+    constexpr int NP = npair<NB>();
+    __shared__ double red[2][NP * 256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, g = lane >> 4;
+    const size_t vb = (size_t)blockIdx.x * a.vox_per_block;
+    const size_t ve = min((size_t)a.N, vb + a.vox_per_block);
+    d4 acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (size_t cb = vb + wave * 16; cb < ve; cb += 64) {
+        const size_t v = cb + 4 * g;
+        float2 x[NB][4];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int f = nb * 16 + i16;
+            if (f < a.nt && v < ve) {
+                const float4* src = reinterpret_cast<const float4*>(a.C + (size_t)f * a.N + v);
+                const float4 u0 = src[0], u1 = src[1];
+                x[nb][0] = make_float2(u0.x, u0.y);
+                x[nb][1] = make_float2(u0.z, u0.w);
+                x[nb][2] = make_float2(u1.x, u1.y);
+                x[nb][3] = make_float2(u1.z, u1.w);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) x[nb][s] = make_float2(0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double op[NT4];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                op[nb] = (double)x[nb][s].x;
+                op[NB + nb] = (double)x[nb][s].y;
+            }
+            int p = 0;
+#pragma unroll
+            for (int I = 0; I < NT4; ++I)
+#pragma unroll
+                for (int J = I; J < NT4; ++J, ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], acc[p], 0, 0, 0);
+        }
+    }
+    // fixed-order reduction over the 4 waves: (w0 + w2) + (w1 + w3)
+    const int slot = lane;  // acc[p][r] -> red[.][p * 256 + r * 64 + lane]
+    if (wave >= 2) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave - 2][p * 256 + r * 64 + slot] = acc[p][r];
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[p][r] += red[wave][p * 256 + r * 64 + slot];
+    }
+    __syncthreads();
+    if (wave == 1) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[0][p * 256 + r * 64 + slot] = acc[p][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double* out = a.part + (size_t)blockIdx.x * NP * 256;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                // MFMA 16x16 output: lane holds row 4 * (lane / 16) + r, column lane % 16
+                const int row = 4 * g + r, col = i16;
+                out[p * 256 + row * 16 + col] = acc[p][r] + red[0][p * 256 + r * 64 + slot];
+            }
+    }
+}
+
+int launch_gram(int mode, const GramArgs& a0, hipStream_t s) {
+    (void)mode;
+    GramArgs a = a0;
+    int vpb = (a.N + kGramBlocks - 1) / kGramBlocks;
+    vpb = (vpb + 63) / 64 * 64;
+    a.vox_per_block = vpb;
+    const int grid = (a.N + vpb - 1) / vpb;
+    if (a.nt <= 16)
+        hipLaunchKernelGGL(pls_gram_f64_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(pls_gram_f64_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+    return grid;
+}
+
+// out[e] = sum_b part[b * entries + e], b ascending
+__global__ void __launch_bounds__(256) pls_gram_reduce_kernel(const double* part, int blocks,
+                                                              int entries, double* out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= entries) return;
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += part[(size_t)b * entries + e];
+    out[e] = s;
+}
+
+void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(pls_gram_reduce_kernel, dim3((entries + 255) / 256), dim3(256), 0, s, part,
+                       blocks, entries, out);
+}
+
+// ---------------------------------------------------------------- Hermitian eigensolver
+// Cyclic complex Jacobi in FP64 with round-robin pair ordering (all n/2 disjoint
+// rotations of a round applied at once), warm-started from the previous iteration's
+// eigenvectors: A = V^H G V is then nearly diagonal and one or two sweeps suffice.
+constexpr int kNMax = 32;
+constexpr int kMaxSweeps = 30;
+
+__device__ __forceinline__ double gram_real(const double* red, int NB, int c1, int c2) {
+    int I = c1 / 16, J = c2 / 16, i = c1 % 16, j = c2 % 16;
+    if (I > J) {
+        int t = I; I = J; J = t;
+        t = i; i = j; j = t;
+    }
+    const int NT4 = 2 * NB;
+    const int p = I * NT4 - I * (I - 1) / 2 + (J - I);
+    return red[p * 256 + i * 16 + j];
+}
+
+__device__ __forceinline__ void rr_pair(int n, int r, int k, int& p, int& q) {
+    if (k == 0) {
+        p = n - 1;
+        q = r;
+    } else {
+        p = (r + k) % (n - 1);
+        q = (r - k + n - 1) % (n - 1);
+    }
+}
+
+__global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
+    __shared__ double Ar[kNMax][kNMax + 1], Ai[kNMax][kNMax + 1];
+    __shared__ double Vr[kNMax][kNMax + 1], Vi[kNMax][kNMax + 1];
+    __shared__ double Tr[kNMax][kNMax + 1], Ti[kNMax][kNMax + 1];
+    __shared__ double rc[kNMax / 2], rs[kNMax / 2], rer[kNMax / 2], rei[kNMax / 2];
+    __shared__ int rp[kNMax / 2], rq[kNMax / 2];
+    __shared__ double red[4];
+    __shared__ double sig[kNMax], phi[kNMax];
+    __shared__ int rank_of[kNMax];
+    const int tid = threadIdx.x;
+    const int n = a.nt;
+    const int ne = n + (n & 1);
+    const int NB = n <= 16 ? 1 : 2;
+    const int NTP = 16 * NB;
+
+    // G (complex Hermitian, n x n; padded index decoupled)
+    for (int idx = tid; idx < ne * ne; idx += 256) {
+        const int i = idx / ne, j = idx % ne;
+        double gr = 0.0, gi = 0.0;
+        if (i < n && j < n) {
+            gr = gram_real(a.gram, NB, i, j) + gram_real(a.gram, NB, NTP + i, NTP + j);
+            gi = gram_real(a.gram, NB, i, NTP + j) - gram_real(a.gram, NB, j, NTP + i);
+        }
+        Tr[i][j] = gr;
+        Ti[i][j] = gi;
+        double vr = (i == j) ? 1.0 : 0.0, vi = 0.0;
+        if (a.warm && i < n && j < n) {
+            vr = a.V[2 * (i * n + j)];
+            vi = a.V[2 * (i * n + j) + 1];
+        }
+        Vr[i][j] = vr;
+        Vi[i][j] = vi;
+    }
+    __syncthreads();
+    if (a.warm) {
+        // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
+        for (int idx = tid; idx < ne * ne; idx += 256) {
+            const int i = idx / ne, j = idx % ne;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < ne; ++k) {
+                sr += Tr[i][k] * Vr[k][j] - Ti[i][k] * Vi[k][j];
+                si += Tr[i][k] * Vi[k][j] + Ti[i][k] * Vr[k][j];
+            }
+            Ar[i][j] = sr;
+            Ai[i][j] = si;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < ne * ne; idx += 256) {
+            const int i = idx / ne, j = idx % ne;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < ne; ++k) {
+                // conj(V[k][i]) * (GV)[k][j]
+                sr += Vr[k][i] * Ar[k][j] + Vi[k][i] * Ai[k][j];
+                si += Vr[k][i] * Ai[k][j] - Vi[k][i] * Ar[k][j];
+            }
+            Tr[i][j] = sr;
+            Ti[i][j] = si;
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < ne * ne; idx += 256) {
+        const int i = idx / ne, j = idx % ne;
+        // symmetrise: A = (T + T^H) / 2
+        Ar[i][j] = 0.5 * (Tr[i][j] + Tr[j][i]);
+        Ai[i][j] = (i == j) ? 0.0 : 0.5 * (Ti[i][j] - Ti[j][i]);
+    }
+    __syncthreads();
+
+    const int half = ne / 2;
+    int sweeps = 0;
+    for (; sweeps < kMaxSweeps && ne > 1; ++sweeps) {
+        double off = 0.0, dg = 0.0;
+        for (int idx = tid; idx < ne * ne; idx += 256) {
+            const int i = idx / ne, j = idx % ne;
+            if (i == j) dg += Ar[i][i] * Ar[i][i];
+            else off += Ar[i][j] * Ar[i][j] + Ai[i][j] * Ai[i][j];
+        }
+        off = block_sum<256>(off, red);
+        dg = block_sum<256>(dg, red);
+        if (!(off > 1e-28 * dg)) break;   // also stops on NaN
+        for (int r = 0; r < ne - 1; ++r) {
+            if (tid < half) {
+                int p, q;
+                rr_pair(ne, r, tid, p, q);
+                const double app = Ar[p][p], aqq = Ar[q][q];
+                const double cr = Ar[p][q], ci = Ai[p][q];
+                const double ac = hypot(cr, ci);
+                double cs = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
+                if (ac > 1e-300) {
+                    const double th = (aqq - app) / (2.0 * ac);
+                    double t;
+                    if (fabs(th) > 1e150) t = 0.5 / th;
+                    else t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                    cs = 1.0 / sqrt(t * t + 1.0);
+                    sn = t * cs;
+                    er = cr / ac;
+                    ei = ci / ac;
+                }
+                rc[tid] = cs;
+                rs[tid] = sn;
+                rer[tid] = er;
+                rei[tid] = ei;
+                rp[tid] = p;
+                rq[tid] = q;
+            }
+            __syncthreads();
+            // A <- J^H A J on every 2x2 block; J = [[cs, sn e], [-sn conj(e), cs]]
+            for (int idx = tid; idx < half * half; idx += 256) {
+                const int al = idx / half, be = idx % half;
+                const int p = rp[al], q = rq[al], u = rp[be], w = rq[be];
+                const double c1 = rc[al], s1 = rs[al], e1r = rer[al], e1i = rei[al];
+                const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
+                // J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
+                const double b00r = Ar[p][u], b00i = Ai[p][u], b01r = Ar[p][w], b01i = Ai[p][w];
+                const double b10r = Ar[q][u], b10i = Ai[q][u], b11r = Ar[q][w], b11i = Ai[q][w];
+                // X = J1^H B
+                const double x00r = c1 * b00r - s1 * (e1r * b10r - e1i * b10i);
+                const double x00i = c1 * b00i - s1 * (e1r * b10i + e1i * b10r);
+                const double x01r = c1 * b01r - s1 * (e1r * b11r - e1i * b11i);
+                const double x01i = c1 * b01i - s1 * (e1r * b11i + e1i * b11r);
+                const double x10r = s1 * (e1r * b00r + e1i * b00i) + c1 * b10r;
+                const double x10i = s1 * (e1r * b00i - e1i * b00r) + c1 * b10i;
+                const double x11r = s1 * (e1r * b01r + e1i * b01i) + c1 * b11r;
+                const double x11i = s1 * (e1r * b01i - e1i * b01r) + c1 * b11i;
+                // Y = X J2, J2 = [[c2, s2 e2], [-s2 conj(e2), c2]]
+                // Y[:,0] = X[:,0] c2 - X[:,1] s2 conj(e2);  Y[:,1] = X[:,0] s2 e2 + X[:,1] c2
+                double y00r = c2 * x00r - s2 * (x01r * e2r + x01i * e2i);
+                double y00i = c2 * x00i - s2 * (x01i * e2r - x01r * e2i);
+                double y10r = c2 * x10r - s2 * (x11r * e2r + x11i * e2i);
+                double y10i = c2 * x10i - s2 * (x11i * e2r - x11r * e2i);
+                double y01r = s2 * (x00r * e2r - x00i * e2i) + c2 * x01r;
+                double y01i = s2 * (x00r * e2i + x00i * e2r) + c2 * x01i;
+                double y11r = s2 * (x10r * e2r - x10i * e2i) + c2 * x11r;
+                double y11i = s2 * (x10r * e2i + x10i * e2r) + c2 * x11i;
+                if (al == be) {
+                    y01r = y01i = y10r = y10i = 0.0;
+                    y00i = y11i = 0.0;
+                }
+                Ar[p][u] = y00r; Ai[p][u] = y00i;
+                Ar[p][w] = y01r; Ai[p][w] = y01i;
+                Ar[q][u] = y10r; Ai[q][u] = y10i;
+                Ar[q][w] = y11r; Ai[q][w] = y11i;
+            }
+            // V <- V J
+            for (int idx = tid; idx < ne * half; idx += 256) {
+                const int i = idx / half, be = idx % half;
+                const int u = rp[be], w = rq[be];
+                const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
+                const double v0r = Vr[i][u], v0i = Vi[i][u], v1r = Vr[i][w], v1i = Vi[i][w];
+                Vr[i][u] = c2 * v0r - s2 * (v1r * e2r + v1i * e2i);
+                Vi[i][u] = c2 * v0i - s2 * (v1i * e2r - v1r * e2i);
+                Vr[i][w] = s2 * (v0r * e2r - v0i * e2i) + c2 * v1r;
+                Vi[i][w] = s2 * (v0r * e2i + v0i * e2r) + c2 * v1i;
+            }
+            __syncthreads();
+        }
+    }
+
+    // spectrum, descending ranks (ties broken by index), thresholds
+    if (tid < n) sig[tid] = sqrt(fmax(Ar[tid][tid], 0.0));
+    __syncthreads();
+    if (tid < n) {
+        int rk = 0;
+        const double si = sig[tid];
+        for (int j = 0; j < n; ++j) rk += (sig[j] > si) || (sig[j] == si && j < tid);
+        rank_of[tid] = rk;
+    }
+    __syncthreads();
+    double s1 = 0.0;
+    for (int j = 0; j < n; ++j) s1 = fmax(s1, sig[j]);
+    const double tau = a.relative ? a.lambda_L * s1 : a.lambda_L;
+    double nuc_part = 0.0;
+    if (tid < n) {
+        const double sg = sig[tid];
+        const double hat = fmax(sg - tau, 0.0);
+        const double prev = a.sigma_prev ? a.sigma_prev[rank_of[tid]] : 0.0;
+        double tgt = hat - a.lambda_p * (hat - prev);
+        if (sg <= 1e-3 * s1) tgt = 0.0;
+        phi[tid] = sg > 0.0 ? tgt / sg : 0.0;
+        nuc_part = tgt;
+        a.stat[16 + rank_of[tid]] = sg;
+    }
+    __syncthreads();
+    // nuclear norm summed in rank order for determinism
+    if (tid == 0) {
+        double nuc = 0.0;
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                if (rank_of[j] == k) {
+                    const double sg = sig[j];
+                    nuc += phi[j] * sg;
+                }
+        a.stat[4] = nuc;
+        a.stat[5] = tau;
+        a.stat[6] = (double)sweeps;
+    }
+    (void)nuc_part;
+    // W = V diag(phi) V^H and its real-expanded MFMA operand
+    const int K2 = 2 * NTP;
+    for (int idx = tid; idx < NTP * NTP; idx += 256) {
+        const int t = idx / NTP, j = idx % NTP;
+        double wr = 0.0, wi = 0.0;
+        if (t < n && j < n) {
+            for (int k = 0; k < n; ++k) {
+                // V[t][k] phi_k conj(V[j][k])
+                const double pr = Vr[t][k] * phi[k], pi = Vi[t][k] * phi[k];
+                wr += pr * Vr[j][k] + pi * Vi[j][k];
+                wi += pi * Vr[j][k] - pr * Vi[j][k];
+            }
+            a.Wd[2 * (t * n + j)] = wr;
+            a.Wd[2 * (t * n + j) + 1] = wi;
+        }
+        // Wr[k][o]: k = input (Re frames 0..NTP-1, Im frames NTP..), o = output likewise.
+        // A operand = Wr^T: Aop[o][k]
+        const float fr = (float)wr, fi = (float)wi;
+        a.Wop[(j)*K2 + t] = fr;               // Wr[t][j]         =  Re W
+        a.Wop[(j)*K2 + NTP + t] = -fi;        // Wr[NTP+t][j]     = -Im W
+        a.Wop[(NTP + j) * K2 + t] = fi;       // Wr[t][NTP+j]     =  Im W
+        a.Wop[(NTP + j) * K2 + NTP + t] = fr; // Wr[NTP+t][NTP+j] =  Re W
+    }
+    for (int idx = tid; idx < n * n; idx += 256) {
+        const int i = idx / n, j = idx % n;
+        a.V[2 * idx] = Vr[i][j];
+        a.V[2 * idx + 1] = Vi[i][j];
+    }
+}
+
+void launch_eig(const EigArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(pls_eig_kernel, dim3(1), dim3(256), 0, s, a);
+}
+
+}  // namespace pls

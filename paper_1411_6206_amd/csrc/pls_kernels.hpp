@@ -1,0 +1,127 @@
+// Kernel argument blocks and host-side launchers of the Priori L+S library.
+//
+// Internal layouts (device, owned by the handle):
+//   image state C, L, S      complex64 [nt][nx][nz][ny]   (each (t, x) plane contiguous)
+//   coil sensitivities       complex64 [nc][nx][nz][ny]
+//   prior weights            uint8     [nt][nx][nz][ny]   block-local (in-place) Haar order
+//   compact hybrid data dh   complex64, frame t at dh_off[t], index (x * nc + c) * ns[t] + s:
+//                            the unitary kx-IDFT of sample s of frame t, scaled by 1/sqrt(ny nz)
+//   sample map sidx          int16 [nt][nz][ny]: sample index of (kz, ky) or -1
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pls {
+
+struct DcArgs {
+    const float2* L;       // new iterate (Y = L + S); L NULL means Y = 0
+    const float2* S;       // NULL means S = 0
+    const float2* Lold;    // previous iterate, read only by the statistics variant
+    const float2* Sold;
+    float2* C;             // out: C = M - S = L - E^H(E Y - d)
+    const float2* sens;    // NULL: single unit coil
+    const float2* dh;
+    const int* dh_off;
+    const int* ns;
+    const int16_t* sidx;
+    const float2* twy;     // exp(-2 pi i m / ny)
+    const float2* twz;     // exp(-2 pi i m / nz)
+    double* part;          // per block: [0] sum |r|^2 (scaled), [1] sum |Y - Yold|^2, [2] sum |Yold|^2
+    int nx, nt, nc;
+    float inv_p;           // 1 / (ny nz)
+};
+
+struct XiArgs {
+    const float2* kspace;  // user layout [nc][nt][nz][ny][nx]
+    const int* plist;      // [nt][ny nz] sample positions z * ny + y in sample order
+    const int* line_off;   // [nt + 1] prefix of nc * ns
+    const int* ns;
+    const int* dh_off;
+    float2* dh;
+    const float2* twx;     // exp(-2 pi i m / nx)
+    int nx, nt, nc, P, total_lines;
+    float scale;           // 1 / sqrt(nx * ny * nz)
+};
+
+bool dc_supported(int ny, int nz);
+bool xifft_supported(int nx);
+// Launch the data-consistency pass over all (t, x) planes.  Returns the number of blocks
+// (rows of DcArgs::part written), 0 if the shape is unsupported.
+int launch_dc(int ny, int nz, bool stats, const DcArgs& a, hipStream_t s);
+int dc_blocks(int ny, int nz, int nx, int nt);
+bool launch_xifft(int nx, const XiArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- setup kernels
+void launch_mask_scan(const uint8_t* mask, int ny, int nz, int nt, int16_t* sidx, int* plist,
+                      int* ns, hipStream_t s);
+// user [F][nz][ny][nx] -> internal [F][nx][nz][ny]; in2 (optional) is added
+void launch_pack(const float2* in, const float2* in2, float2* out, int F, int nx, int ny,
+                 int nz, hipStream_t s);
+// internal [F][nx][nz][ny] -> user [F][nz][ny][nx]; out = a + b (b optional)
+void launch_unpack(const float2* a, const float2* b, float2* out, int F, int nx, int ny,
+                   int nz, hipStream_t s);
+// canonical Haar layout [nt][nz][ny][nx] -> internal block-local [nt][nx][nz][ny]
+void launch_pack_weights(const uint8_t* in, uint8_t* out, int nt, int nx, int ny, int nz,
+                         int levels, hipStream_t s);
+void launch_add(const float2* a, const float2* b, float2* out, size_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- Gram / eig / LS
+struct GramArgs {
+    const float2* C;       // [nt][N]
+    double* part;          // [blocks][NTILE * 256]
+    int N, nt, vox_per_block;
+};
+// returns number of blocks
+int launch_gram(int mode, const GramArgs& a, hipStream_t s);
+int gram_blocks(int N);
+int gram_tiles(int nt);
+void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s);
+
+struct EigArgs {
+    const double* gram;    // reduced tiles
+    double* V;             // [nt][nt] complex (re, im interleaved) eigenvectors, in/out (warm start)
+    int warm;              // use V as the starting basis
+    float* Wop;            // MFMA A-operand of the back-projection: [64][64] (or [32][32])
+    double* Wd;            // W = V diag(phi) V^H, complex [nt][nt] (FP64 copy)
+    const double* sigma_prev;  // [nt] descending, zero padded
+    double* stat;          // per-iteration record (see pls_stats layout in the runtime)
+    int nt;
+    double lambda_L, lambda_p;
+    int relative;
+};
+void launch_eig(const EigArgs& a, hipStream_t s);
+
+struct BpArgs {
+    const float2* C;
+    float2* L;
+    const float* Wop;
+    int N, nt;
+};
+void launch_bp(const BpArgs& a, hipStream_t s);
+
+struct SparseArgs {
+    const float2* C;       // M - S (so M - L_prev = C + S - L_prev)
+    const float2* S;       // previous S (may be NULL: zero)
+    const float2* Lp;      // previous L
+    const uint8_t* w;      // internal block-local weights or NULL
+    float2* Sout;
+    double* part;          // per block: weighted l1 of the shrunk coefficients
+    int nx, ny, nz, nt;
+    float lambda_S;
+};
+// returns number of blocks
+int launch_sparse(int levels, const SparseArgs& a, hipStream_t s);
+
+struct StatsArgs {
+    const double* dc_part;
+    int dc_blocks;
+    const double* sp_part;
+    int sp_blocks;
+    double* stat;          // per-iteration record
+    double p_scale;        // ny * nz (residual scaling)
+    double lambda_S;
+};
+void launch_stats(const StatsArgs& a, hipStream_t s);
+
+}  // namespace pls

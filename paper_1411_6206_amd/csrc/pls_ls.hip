@@ -1,0 +1,228 @@
+// Low-rank and sparse updates of Algorithm 1 and the per-iteration statistics.
+//
+//  * back-projection, steps (1)-(2): L = C W on FP32 MFMA (v_mfma_f32_16x16x4f32) with the
+//    frame-space operator W from the eigensolver, real-expanded: [Re L | Im L]^T =
+//    Wr^T [Re C | Im C]^T, 16 voxels per MFMA column block;
+//  * sparse update, step (3): S = T^{-1} soft(T(X - L_prev), lambda_S (1 - w)) with T the
+//    J-level orthonormal Haar (nonstandard pyramid) computed in place on (2^J)^3 blocks:
+//    x in registers, y and z across the lanes of a wave;
+//  * fixed-order FP64 reduction of the per-block partial sums into one record per iteration.
+#include "pls_common.hpp"
+#include "pls_kernels.hpp"
+
+namespace pls {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- back-projection
+template <int NB>
+__global__ void __launch_bounds__(256) pls_bp_kernel(BpArgs a) {
+    constexpr int NTP = 16 * NB, K2 = 2 * NTP, MB = K2 / 16, KS = K2 / 4, KH = NTP / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, g = lane >> 4;
+    float Areg[MB][KS];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) Areg[mb][ks] = a.Wop[(16 * mb + i16) * K2 + 4 * ks + g];
+    const size_t N = (size_t)a.N;
+    const size_t stride = (size_t)gridDim.x * 4 * 16;
+    for (size_t v0 = ((size_t)blockIdx.x * 4 + wave) * 16; v0 < N; v0 += stride) {
+        const size_t v = v0 + i16;
+        float2 cb[KH];
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) {
+            const int f = 4 * kk + g;
+            cb[kk] = (f < a.nt && v < N) ? a.C[(size_t)f * N + v] : make_float2(0.f, 0.f);
+        }
+        f4 acc[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const float b = ks < KH ? cb[ks].x : cb[ks - KH].y;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Areg[mb][ks], b, acc[mb], 0, 0, 0);
+        }
+        if (v < N) {
+#pragma unroll
+            for (int mb = 0; mb < MB / 2; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int f = 16 * mb + 4 * g + r;
+                    if (f < a.nt) a.L[(size_t)f * N + v] = make_float2(acc[mb][r], acc[mb + MB / 2][r]);
+                }
+        }
+    }
+}
+
+void launch_bp(const BpArgs& a, hipStream_t s) {
+    const int tiles = (a.N + 63) / 64;
+    const int grid = tiles < 2048 ? tiles : 2048;
+    if (a.nt <= 16)
+        hipLaunchKernelGGL(pls_bp_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(pls_bp_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------- sparse update
+__device__ __forceinline__ float2 shfl_xor2(float2 v, int m) {
+    return make_float2(__shfl_xor(v.x, m, kWave), __shfl_xor(v.y, m, kWave));
+}
+
+// (own, partner) -> a or d of the orthonormal 2-point Haar; self-inverse
+__device__ __forceinline__ float2 haar_pair(float2 u, float2 p, bool second) {
+    constexpr float s = 0.70710678118654752440f;
+    return second ? make_float2((p.x - u.x) * s, (p.y - u.y) * s)
+                  : make_float2((u.x + p.x) * s, (u.y + p.y) * s);
+}
+
+template <int J, bool ZA>
+__device__ __forceinline__ void haar_level(float2 (&v)[1 << J], int l, int yl, int zl, int lane) {
+    constexpr int B = 1 << J;
+    constexpr int ZW = ZA ? B : 1;
+    constexpr int YW = 64 / ZW;
+    const int st = 1 << l;
+    const bool lane_in = ((yl & (st - 1)) == 0) && ((zl & (st - 1)) == 0);
+    // x: registers k and k + st, k a multiple of 2 st
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        if ((k & (2 * st - 1)) == 0 && k + st < B && lane_in) {
+            const float2 u0 = v[k], u1 = v[k + st];
+            v[k] = haar_pair(u0, u1, false);
+            v[k + st] = haar_pair(u1, u0, true);
+        }
+    }
+    // y: lanes differing in bit l
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        if ((k & (st - 1)) == 0) {
+            const float2 p = shfl_xor2(v[k], st);
+            if (lane_in) v[k] = haar_pair(v[k], p, (yl >> l) & 1);
+        }
+    }
+    if constexpr (ZA) {
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if ((k & (st - 1)) == 0) {
+                const float2 p = shfl_xor2(v[k], st * YW);
+                if (lane_in) v[k] = haar_pair(v[k], p, (zl >> l) & 1);
+            }
+        }
+    }
+    (void)lane;
+}
+
+template <int J, bool ZA>
+__global__ void __launch_bounds__(256) pls_sparse_kernel(SparseArgs a) {
+    constexpr int B = 1 << J;
+    constexpr int ZW = ZA ? B : 1;
+    constexpr int YW = 64 / ZW;
+    constexpr int XW = B;
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int yl = lane % YW, zl = lane / YW;
+    const int nyt = (a.ny + 4 * YW - 1) / (4 * YW);
+    const int nzt = a.nz / ZW;
+    int tile = blockIdx.x;
+    const int yt = tile % nyt;
+    tile /= nyt;
+    const int zt = tile % nzt;
+    const int xt = tile / nzt;
+    const int t = blockIdx.y;
+    const int y = yt * 4 * YW + wave * YW + yl;
+    const int z = zt * ZW + zl;
+    const bool valid = y < a.ny;
+    float2 v[XW];
+    size_t gi[XW];
+#pragma unroll
+    for (int k = 0; k < XW; ++k) {
+        gi[k] = (((size_t)t * a.nx + xt * XW + k) * a.nz + z) * a.ny + y;
+        float2 u = make_float2(0.f, 0.f);
+        if (valid) {
+            u = a.C[gi[k]];
+            if (a.S) u = cadd(u, a.S[gi[k]]);
+            u = csub(u, a.Lp[gi[k]]);
+        }
+        v[k] = u;
+    }
+    for (int l = 0; l < J; ++l) haar_level<J, ZA>(v, l, yl, zl, lane);
+    double l1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < XW; ++k) {
+        const float w = (a.w && valid) ? (float)a.w[gi[k]] * (1.0f / 255.0f) : 0.0f;
+        const float tau = a.lambda_S * (1.0f - w);
+        const float2 u = v[k];
+        const float mag = sqrtf(fmaf(u.x, u.x, u.y * u.y));
+        float2 o = make_float2(0.f, 0.f);
+        if (mag > tau) {
+            const float sc = (mag - tau) / mag;
+            o = make_float2(u.x * sc, u.y * sc);
+        }
+        v[k] = o;
+        if (valid) l1 += (double)(1.0f - w) * (double)sqrtf(fmaf(o.x, o.x, o.y * o.y));
+    }
+    for (int l = J - 1; l >= 0; --l) haar_level<J, ZA>(v, l, yl, zl, lane);
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < XW; ++k) a.Sout[gi[k]] = v[k];
+    }
+    const double s = block_sum<256>(l1, red);
+    if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+template <int J, bool ZA>
+static int sparse_launch_t(const SparseArgs& a, hipStream_t s) {
+    constexpr int B = 1 << J;
+    constexpr int ZW = ZA ? B : 1;
+    constexpr int YW = 64 / ZW;
+    const int nyt = (a.ny + 4 * YW - 1) / (4 * YW);
+    const int tiles = nyt * (a.nz / ZW) * (a.nx / B);
+    hipLaunchKernelGGL((pls_sparse_kernel<J, ZA>), dim3(tiles, a.nt), dim3(256), 0, s, a);
+    return tiles * a.nt;
+}
+
+int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
+    const bool za = a.nz > 1;
+    switch (levels) {
+        case 0: return za ? sparse_launch_t<0, true>(a, s) : sparse_launch_t<0, false>(a, s);
+        case 1: return za ? sparse_launch_t<1, true>(a, s) : sparse_launch_t<1, false>(a, s);
+        case 2: return za ? sparse_launch_t<2, true>(a, s) : sparse_launch_t<2, false>(a, s);
+        case 3: return za ? sparse_launch_t<3, true>(a, s) : sparse_launch_t<3, false>(a, s);
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- statistics
+// stat record (doubles): [0] ||r||^2, [1] ||Y - Yold||^2, [2] ||Yold||^2, [3] weighted l1,
+// [4] nuclear norm, [5] tau_L, [6] Jacobi sweeps, [7] non-finite flag, [16..48) sigma
+__global__ void __launch_bounds__(256) pls_stats_kernel(StatsArgs a) {
+    __shared__ double red[4];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int b = threadIdx.x; b < a.dc_blocks; b += 256) {
+        s0 += a.dc_part[4 * b + 0];
+        s1 += a.dc_part[4 * b + 1];
+        s2 += a.dc_part[4 * b + 2];
+    }
+    for (int b = threadIdx.x; b < a.sp_blocks; b += 256) s3 += a.sp_part[b];
+    s0 = block_sum<256>(s0, red);
+    s1 = block_sum<256>(s1, red);
+    s2 = block_sum<256>(s2, red);
+    s3 = block_sum<256>(s3, red);
+    if (threadIdx.x == 0) {
+        a.stat[0] = s0 * a.p_scale;
+        a.stat[1] = s1;
+        a.stat[2] = s2;
+        a.stat[3] = s3;
+        const bool bad = !isfinite(s0) || !isfinite(s1) || !isfinite(s2) || !isfinite(s3) ||
+                         !isfinite(a.stat[4]);
+        a.stat[7] = bad ? 1.0 : 0.0;
+    }
+}
+
+void launch_stats(const StatsArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(pls_stats_kernel, dim3(1), dim3(256), 0, s, a);
+}
+
+}  // namespace pls

@@ -1,0 +1,814 @@
+// Host runtime and C ABI of the Priori L+S library: argument validation, device state,
+// set-up (sample lists, kx inverse DFT, layout permutations, step (0)), the iteration
+// schedule of Algorithm 1 (captured per chunk into a hipGraph and replayed), convergence
+// checks and output.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "prior_ls.h"
+#include "pls_kernels.hpp"
+
+using pls::DcArgs;
+
+namespace {
+
+constexpr int kStatRec = 64;          // doubles per iteration record
+constexpr int kMaxChunk = 1024;
+
+thread_local std::string g_create_error;
+
+struct HipError {
+    hipError_t e;
+    std::string where;
+};
+
+#define PLS_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) throw HipError{e_, #call};                     \
+    } while (0)
+
+bool is_pow2_div(int n, int J) { return n == 1 || (n % (1 << J)) == 0; }
+
+int check_dims(const prior_ls_dims* d, std::string& msg) {
+    if (!d) {
+        msg = "dims is NULL";
+        return PRIOR_LS_EINVAL;
+    }
+    if (d->struct_size != sizeof(prior_ls_dims)) {
+        msg = "dims.struct_size mismatch";
+        return PRIOR_LS_EINVAL;
+    }
+    if (d->reserved != 0) {
+        msg = "dims.reserved must be 0";
+        return PRIOR_LS_EINVAL;
+    }
+    if (d->gram_mode < PRIOR_LS_GRAM_FP64 || d->gram_mode > PRIOR_LS_GRAM_BF16X3) {
+        msg = "unknown gram_mode";
+        return PRIOR_LS_EINVAL;
+    }
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nt < 1 || d->nc < 1) {
+        msg = "dimensions must be >= 1";
+        return PRIOR_LS_ESHAPE;
+    }
+    if (d->nt > PRIOR_LS_MAX_NT) {
+        msg = "nt > 32 is not supported";
+        return PRIOR_LS_ESHAPE;
+    }
+    if (d->nc > 64) {
+        msg = "nc > 64 is not supported";
+        return PRIOR_LS_ESHAPE;
+    }
+    if (!pls::dc_supported(d->ny, d->nz)) {
+        msg = "unsupported (ny, nz) phase-encode plane";
+        return PRIOR_LS_ESHAPE;
+    }
+    if (!pls::xifft_supported(d->nx)) {
+        msg = "unsupported readout length nx";
+        return PRIOR_LS_ESHAPE;
+    }
+    const int J = d->wavelet_levels;
+    if (J < 0 || J > 3) {
+        msg = "wavelet_levels must be in [0, 3]";
+        return PRIOR_LS_ESHAPE;
+    }
+    if (!is_pow2_div(d->nx, J) || !is_pow2_div(d->ny, J) || !is_pow2_div(d->nz, J)) {
+        msg = "every spatial axis of size > 1 must be divisible by 2^wavelet_levels";
+        return PRIOR_LS_ESHAPE;
+    }
+    // the sparse kernel covers (2^J)^3 blocks with z across the lanes of one wave
+    if (d->nz > 1 && (d->nz % (1 << J)) != 0) {
+        msg = "nz must be divisible by 2^wavelet_levels";
+        return PRIOR_LS_ESHAPE;
+    }
+    return PRIOR_LS_OK;
+}
+
+struct Sizes {
+    size_t N, I, P;
+    uint64_t base_bytes;
+    int gblocks, gentries, dcb, spb;
+};
+
+int sparse_blocks(const prior_ls_dims& d) {
+    const int J = d.wavelet_levels;
+    const int B = 1 << J;
+    const int ZW = d.nz > 1 ? B : 1;
+    const int YW = 64 / ZW;
+    const int nyt = (d.ny + 4 * YW - 1) / (4 * YW);
+    return nyt * (d.nz / ZW) * (d.nx / B) * d.nt;
+}
+
+Sizes sizes_of(const prior_ls_dims& d) {
+    Sizes s;
+    s.P = (size_t)d.ny * d.nz;
+    s.N = s.P * d.nx;
+    s.I = s.N * d.nt;
+    s.gblocks = pls::gram_blocks((int)s.N);
+    s.gentries = pls::gram_tiles(d.nt) * 256;
+    s.dcb = pls::dc_blocks(d.ny, d.nz, d.nx, d.nt);
+    s.spb = sparse_blocks(d);
+    uint64_t b = 0;
+    b += 5 * s.I * 8;                                   // C, L[2], S[2]
+    if (d.nc > 1) b += (uint64_t)d.nc * s.N * 8;        // sensitivities
+    b += s.I;                                           // weights
+    b += (uint64_t)d.nt * s.P * (2 + 4) + 3 * (d.nt + 1) * 4;  // sidx, plist, ns, offsets
+    b += (uint64_t)(d.nx + d.ny + d.nz) * 8;            // twiddles
+    b += (uint64_t)s.gblocks * s.gentries * 8 + s.gentries * 8;
+    b += 64 * 64 * 4 + 2 * 32 * 32 * 16 + 64 * 8;
+    b += (uint64_t)s.dcb * 32 + (uint64_t)s.spb * 8 + (uint64_t)kMaxChunk * kStatRec * 8;
+    s.base_bytes = b;
+    return s;
+}
+
+}  // namespace
+
+struct prior_ls_handle {
+    prior_ls_dims d{};
+    hipStream_t ustream = nullptr;   // the caller's stream
+    hipStream_t stream = nullptr;    // the handle's own stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int device = 0;
+    Sizes sz{};
+    uint64_t owned = 0;
+    std::vector<void*> allocs;
+    // state
+    float2* C = nullptr;
+    float2* L[2] = {nullptr, nullptr};
+    float2* S[2] = {nullptr, nullptr};
+    float2* sens = nullptr;
+    uint8_t* w = nullptr;
+    bool has_w = false, has_sens = false;
+    float2* dh = nullptr;
+    size_t dh_cap = 0;
+    int *dh_off = nullptr, *ns = nullptr, *plist = nullptr, *line_off = nullptr;
+    int16_t* sidx = nullptr;
+    float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
+    double *gpart = nullptr, *gred = nullptr;
+    double *V = nullptr, *Wd = nullptr;
+    float* Wop = nullptr;
+    double* sigma_prev = nullptr;
+    double *dc_part = nullptr, *sp_part = nullptr;
+    double* stats_d = nullptr;
+    double* stats_h = nullptr;
+    // op scratch (lazy)
+    float2 *T1 = nullptr, *T2 = nullptr;
+    double *Vop = nullptr, *Wdop = nullptr;
+    float* Wopop = nullptr;
+    // iteration
+    int cur = 0;
+    int iters = 0;
+    bool loaded = false;
+    prior_ls_params params{};
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_objs;
+    std::string err;
+    double last[kStatRec] = {0};
+
+    template <class T>
+    T* alloc(size_t bytes) {
+        if (d.hbm_budget && owned + bytes > d.hbm_budget) throw std::bad_alloc();
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw std::bad_alloc();
+        }
+        allocs.push_back(p);
+        owned += bytes;
+        return static_cast<T*>(p);
+    }
+    void release(void* p, size_t bytes) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        (void)hipFree(p);
+        owned -= bytes;
+    }
+    void clear_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto g : graph_objs) (void)hipGraphDestroy(g);
+        graphs.clear();
+        graph_objs.clear();
+    }
+};
+
+namespace {
+
+int fail(prior_ls_handle* h, int code, const std::string& m) {
+    if (h) h->err = m;
+    return code;
+}
+
+void upload_twiddles(float2* dst, int n, hipStream_t s) {
+    std::vector<float2> tw(n);
+    for (int m = 0; m < n; ++m) {
+        const double ang = -2.0 * M_PI * (double)m / (double)n;
+        tw[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    PLS_HIP(hipMemcpyAsync(dst, tw.data(), n * sizeof(float2), hipMemcpyHostToDevice, s));
+    PLS_HIP(hipStreamSynchronize(s));
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+// one iteration of Algorithm 1 on the resident state (see the schedule in the header)
+void enqueue_iteration(prior_ls_handle* h, int slot, bool stats) {
+    const prior_ls_dims& d = h->d;
+    const Sizes& sz = h->sz;
+    hipStream_t s = h->stream;
+    const int p = h->cur, q = 1 - p;
+    double* rec = h->stats_d + (size_t)slot * kStatRec;
+    // steps (1)-(2): Gram, eigensolve, W
+    pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0};
+    const int gb = pls::launch_gram(d.gram_mode, ga, s);
+    pls::launch_gram_reduce(h->gpart, gb, sz.gentries, h->gred, s);
+    pls::EigArgs ea{};
+    ea.gram = h->gred;
+    ea.V = h->V;
+    ea.warm = 1;
+    ea.Wop = h->Wop;
+    ea.Wd = h->Wd;
+    ea.sigma_prev = h->sigma_prev;
+    ea.stat = rec;
+    ea.nt = d.nt;
+    ea.lambda_L = h->params.lambda_L;
+    ea.lambda_p = h->params.lambda_p;
+    ea.relative = h->params.lambda_L_relative;
+    pls::launch_eig(ea, s);
+    // step (3): S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)
+    pls::SparseArgs sa{};
+    sa.C = h->C;
+    sa.S = h->S[p];
+    sa.Lp = h->L[p];
+    sa.w = h->has_w ? h->w : nullptr;
+    sa.Sout = h->S[q];
+    sa.part = h->sp_part;
+    sa.nx = d.nx;
+    sa.ny = d.ny;
+    sa.nz = d.nz;
+    sa.nt = d.nt;
+    sa.lambda_S = (float)h->params.lambda_S;
+    const int spb = pls::launch_sparse(d.wavelet_levels, sa, s);
+    // steps (1)-(2): L_k = C W
+    pls::BpArgs ba{h->C, h->L[q], h->Wop, (int)sz.N, d.nt};
+    pls::launch_bp(ba, s);
+    // step (4): data consistency -> C = M_k - S_k
+    DcArgs da{};
+    da.L = h->L[q];
+    da.S = h->S[q];
+    da.Lold = h->L[p];
+    da.Sold = h->S[p];
+    da.C = h->C;
+    da.sens = h->has_sens ? h->sens : nullptr;
+    da.dh = h->dh;
+    da.dh_off = h->dh_off;
+    da.ns = h->ns;
+    da.sidx = h->sidx;
+    da.twy = h->twy;
+    da.twz = h->twz;
+    da.part = h->dc_part;
+    da.nx = d.nx;
+    da.nt = d.nt;
+    da.nc = d.nc;
+    da.inv_p = 1.0f / (float)sz.P;
+    const int dcb = pls::launch_dc(d.ny, d.nz, stats, da, s);
+    pls::StatsArgs st{h->dc_part, dcb, h->sp_part, spb, rec, (double)sz.P, h->params.lambda_S};
+    pls::launch_stats(st, s);
+    h->cur = q;
+}
+
+void run_chunk(prior_ls_handle* h, int n) {
+    const bool graph = h->params.use_graph != 0;
+    if (!graph) {
+        for (int j = 0; j < n; ++j) enqueue_iteration(h, j, j == n - 1);
+        PLS_HIP(hipGetLastError());
+        return;
+    }
+    const auto key = std::make_pair(n, h->cur);
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        const int cur0 = h->cur;
+        hipGraph_t g = nullptr;
+        PLS_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < n; ++j) enqueue_iteration(h, j, j == n - 1);
+        hipError_t le = hipGetLastError();
+        PLS_HIP(hipStreamEndCapture(h->stream, &g));
+        PLS_HIP(le);
+        hipGraphExec_t ex = nullptr;
+        PLS_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        h->graph_objs.push_back(g);
+        it = h->graphs.emplace(key, ex).first;
+        h->cur = cur0;
+    }
+    PLS_HIP(hipGraphLaunch(it->second, h->stream));
+    if (n % 2) h->cur = 1 - h->cur;
+}
+
+// Runs n iterations in chunks; returns status (ENONFINITE possible), fills h->last.
+int iterate(prior_ls_handle* h, int n, bool& converged) {
+    converged = false;
+    int done = 0;
+    const int ce = std::max(1, std::min(h->params.check_every, kMaxChunk));
+    while (done < n) {
+        const int m = std::min(ce, n - done);
+        run_chunk(h, m);
+        PLS_HIP(hipMemcpyAsync(h->stats_h, h->stats_d + (size_t)(m - 1) * kStatRec,
+                               kStatRec * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        PLS_HIP(hipStreamSynchronize(h->stream));
+        std::memcpy(h->last, h->stats_h, sizeof(h->last));
+        done += m;
+        h->iters += m;
+        if (h->last[7] != 0.0) return fail(h, PRIOR_LS_ENONFINITE, "non-finite value in the iterate");
+        const double rel = h->last[2] > 0 ? std::sqrt(h->last[1] / h->last[2]) : INFINITY;
+        if (h->params.tol > 0 && rel < h->params.tol) {
+            converged = true;
+            break;
+        }
+    }
+    return PRIOR_LS_OK;
+}
+
+void write_outputs(prior_ls_handle* h, const prior_ls_outputs* out) {
+    if (!out) return;
+    const prior_ls_dims& d = h->d;
+    const int p = h->cur;
+    hipStream_t s = h->stream;
+    if (out->L) pls::launch_unpack(h->L[p], nullptr, (float2*)out->L, d.nt, d.nx, d.ny, d.nz, s);
+    if (out->S) pls::launch_unpack(h->S[p], nullptr, (float2*)out->S, d.nt, d.nx, d.ny, d.nz, s);
+    if (out->X) pls::launch_unpack(h->L[p], h->S[p], (float2*)out->X, d.nt, d.nx, d.ny, d.nz, s);
+    if (out->M) pls::launch_unpack(h->C, h->S[p], (float2*)out->M, d.nt, d.nx, d.ny, d.nz, s);
+    PLS_HIP(hipGetLastError());
+}
+
+void fill_stats(prior_ls_handle* h, prior_ls_stats* st, bool converged, double ms) {
+    if (!st) return;
+    const double* r = h->last;
+    st->iters = h->iters;
+    st->converged = converged ? 1 : 0;
+    st->nonfinite = r[7] != 0.0;
+    st->sigma_count = h->d.nt;
+    st->rel_change = r[2] > 0 ? std::sqrt(r[1] / r[2]) : INFINITY;
+    st->resid_norm = std::sqrt(std::max(r[0], 0.0));
+    st->nuclear_norm = r[4];
+    st->l1_weighted = r[3];
+    st->tau_L = r[5];
+    st->objective = 0.5 * r[0] + r[5] * r[4] + h->params.lambda_S * r[3];
+    for (int i = 0; i < PRIOR_LS_MAX_NT; ++i) st->sigma[i] = i < h->d.nt ? r[16 + i] : 0.0;
+    st->ms = ms;
+}
+
+int check_params(prior_ls_handle* h, const prior_ls_params* p) {
+    if (!p) return fail(h, PRIOR_LS_EINVAL, "params is NULL");
+    if (p->struct_size != sizeof(prior_ls_params)) return fail(h, PRIOR_LS_EINVAL, "params.struct_size mismatch");
+    if (!(p->lambda_L >= 0) || !(p->lambda_S >= 0)) return fail(h, PRIOR_LS_EINVAL, "lambda_L and lambda_S must be >= 0");
+    if (!(p->lambda_p >= 0 && p->lambda_p <= 1)) return fail(h, PRIOR_LS_EINVAL, "lambda_p must be in [0, 1]");
+    if (!(p->tol >= 0)) return fail(h, PRIOR_LS_EINVAL, "tol must be >= 0");
+    if (p->max_iter < 0) return fail(h, PRIOR_LS_EINVAL, "max_iter must be >= 0");
+    if (p->check_every < 1) return fail(h, PRIOR_LS_EINVAL, "check_every must be >= 1");
+    return PRIOR_LS_OK;
+}
+
+void set_identity_V(prior_ls_handle* h, double* V) {
+    const int n = h->d.nt;
+    std::vector<double> I(2 * n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[2 * (i * n + i)] = 1.0;
+    PLS_HIP(hipMemcpyAsync(V, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    PLS_HIP(hipStreamSynchronize(h->stream));
+}
+
+DcArgs dc_args(prior_ls_handle* h, const float2* L, const float2* S, float2* C) {
+    DcArgs da{};
+    da.L = L;
+    da.S = S;
+    da.C = C;
+    da.sens = h->has_sens ? h->sens : nullptr;
+    da.dh = h->dh;
+    da.dh_off = h->dh_off;
+    da.ns = h->ns;
+    da.sidx = h->sidx;
+    da.twy = h->twy;
+    da.twz = h->twz;
+    da.part = h->dc_part;
+    da.nx = h->d.nx;
+    da.nt = h->d.nt;
+    da.nc = h->d.nc;
+    da.inv_p = 1.0f / (float)h->sz.P;
+    return da;
+}
+
+int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* p) {
+    const prior_ls_dims& d = h->d;
+    const Sizes& sz = h->sz;
+    hipStream_t s = h->stream;
+    h->clear_graphs();
+    h->params = *p;
+    h->loaded = false;
+    // sample lists
+    pls::launch_mask_scan(in->mask, d.ny, d.nz, d.nt, h->sidx, h->plist, h->ns, s);
+    PLS_HIP(hipGetLastError());
+    std::vector<int> ns(d.nt), off(d.nt), loff(d.nt + 1);
+    PLS_HIP(hipMemcpyAsync(ns.data(), h->ns, d.nt * sizeof(int), hipMemcpyDeviceToHost, s));
+    PLS_HIP(hipStreamSynchronize(s));
+    size_t total = 0;
+    int lines = 0;
+    for (int t = 0; t < d.nt; ++t) {
+        off[t] = (int)total;
+        loff[t] = lines;
+        total += (size_t)d.nx * d.nc * ns[t];
+        lines += d.nc * ns[t];
+    }
+    loff[d.nt] = lines;
+    if (total > (size_t)INT32_MAX) return fail(h, PRIOR_LS_ESHAPE, "sampled data exceed 2^31 entries");
+    if (total > h->dh_cap) {
+        h->release(h->dh, h->dh_cap * sizeof(float2));
+        h->dh = nullptr;
+        h->dh_cap = 0;
+        try {
+            h->dh = h->alloc<float2>(std::max<size_t>(total, 1) * sizeof(float2));
+        } catch (const std::bad_alloc&) {
+            return fail(h, PRIOR_LS_ENOMEM, "cannot allocate the compact k-space (hbm_budget or device memory)");
+        }
+        h->dh_cap = std::max<size_t>(total, 1);
+    }
+    PLS_HIP(hipMemcpyAsync(h->dh_off, off.data(), d.nt * sizeof(int), hipMemcpyHostToDevice, s));
+    PLS_HIP(hipMemcpyAsync(h->line_off, loff.data(), (d.nt + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    pls::XiArgs xa{};
+    xa.kspace = (const float2*)in->kspace;
+    xa.plist = h->plist;
+    xa.line_off = h->line_off;
+    xa.ns = h->ns;
+    xa.dh_off = h->dh_off;
+    xa.dh = h->dh;
+    xa.twx = h->twx;
+    xa.nx = d.nx;
+    xa.nt = d.nt;
+    xa.nc = d.nc;
+    xa.P = (int)sz.P;
+    xa.total_lines = lines;
+    xa.scale = (float)(1.0 / std::sqrt((double)d.nx * (double)sz.P));
+    pls::launch_xifft(d.nx, xa, s);
+    // coils, weights, sigma prior
+    h->has_sens = in->sens != nullptr;
+    if (h->has_sens) {
+        if (!h->sens) h->sens = h->alloc<float2>((size_t)d.nc * sz.N * sizeof(float2));
+        pls::launch_pack((const float2*)in->sens, nullptr, h->sens, d.nc, d.nx, d.ny, d.nz, s);
+    }
+    h->has_w = in->prior_w != nullptr;
+    if (h->has_w) pls::launch_pack_weights(in->prior_w, h->w, d.nt, d.nx, d.ny, d.nz, d.wavelet_levels, s);
+    std::vector<double> sp(d.nt, 0.0);
+    if (p->lambda_p > 0 && in->sigma_prev) {
+        for (int i = 0; i < d.nt; ++i) sp[i] = in->sigma_prev[i];
+        std::sort(sp.begin(), sp.end(), [](double a, double b) { return a > b; });
+    }
+    PLS_HIP(hipMemcpyAsync(h->sigma_prev, sp.data(), d.nt * sizeof(double), hipMemcpyHostToDevice, s));
+    set_identity_V(h, h->V);
+    // step (0)
+    h->cur = 0;
+    if (in->L0) {
+        pls::launch_pack((const float2*)in->L0, nullptr, h->L[0], d.nt, d.nx, d.ny, d.nz, s);
+        pls::launch_pack((const float2*)in->S0, nullptr, h->S[0], d.nt, d.nx, d.ny, d.nz, s);
+        DcArgs da = dc_args(h, h->L[0], h->S[0], h->C);
+        pls::launch_dc(d.ny, d.nz, false, da, s);
+    } else {
+        DcArgs da = dc_args(h, nullptr, nullptr, h->C);
+        pls::launch_dc(d.ny, d.nz, false, da, s);
+        PLS_HIP(hipMemsetAsync(h->S[0], 0, sz.I * sizeof(float2), s));
+        PLS_HIP(hipMemcpyAsync(h->L[0], h->C, sz.I * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    }
+    PLS_HIP(hipGetLastError());
+    PLS_HIP(hipStreamSynchronize(s));
+    h->iters = 0;
+    std::memset(h->last, 0, sizeof(h->last));
+    h->loaded = true;
+    return PRIOR_LS_OK;
+}
+
+void ensure_op_scratch(prior_ls_handle* h) {
+    const Sizes& sz = h->sz;
+    if (!h->T1) h->T1 = h->alloc<float2>(sz.I * sizeof(float2));
+    if (!h->T2) h->T2 = h->alloc<float2>(sz.I * sizeof(float2));
+    if (!h->Vop) h->Vop = h->alloc<double>(2 * 32 * 32 * sizeof(double));
+    if (!h->Wdop) h->Wdop = h->alloc<double>(2 * 32 * 32 * sizeof(double));
+    if (!h->Wopop) h->Wopop = h->alloc<float>(64 * 64 * sizeof(float));
+}
+
+// Work of a call runs on the handle's stream, after everything already queued on the
+// caller's stream; the caller's stream then waits for the handle's work.
+void enter(prior_ls_handle* h) {
+    PLS_HIP(hipEventRecord(h->ev_in, h->ustream));
+    PLS_HIP(hipStreamWaitEvent(h->stream, h->ev_in, 0));
+}
+void leave(prior_ls_handle* h) {
+    PLS_HIP(hipEventRecord(h->ev_out, h->stream));
+    PLS_HIP(hipStreamWaitEvent(h->ustream, h->ev_out, 0));
+}
+
+template <class F>
+int guarded(prior_ls_handle* h, F&& f) {
+    try {
+        return f();
+    } catch (const HipError& e) {
+        return fail(h, PRIOR_LS_EHIP, e.where + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return fail(h, PRIOR_LS_ENOMEM, "device allocation failed or hbm_budget exceeded");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* prior_ls_strerror(int status) {
+    switch (status) {
+        case PRIOR_LS_OK: return "success";
+        case PRIOR_LS_EINVAL: return "invalid argument";
+        case PRIOR_LS_ESHAPE: return "unsupported shape";
+        case PRIOR_LS_ENOMEM: return "out of device memory or over the HBM budget";
+        case PRIOR_LS_EHIP: return "HIP runtime error";
+        case PRIOR_LS_ENONFINITE: return "non-finite value in the iterate";
+    }
+    return "unknown status";
+}
+
+const char* prior_ls_last_error(const prior_ls_handle* h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+uint64_t prior_ls_plan_bytes(const prior_ls_dims* dims) {
+    std::string m;
+    if (check_dims(dims, m) != PRIOR_LS_OK) return 0;
+    return sizes_of(*dims).base_bytes;
+}
+
+int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** out) {
+    if (!out) {
+        g_create_error = "out is NULL";
+        return PRIOR_LS_EINVAL;
+    }
+    *out = nullptr;
+    std::string msg;
+    const int rc = check_dims(dims, msg);
+    if (rc != PRIOR_LS_OK) {
+        g_create_error = msg;
+        return rc;
+    }
+    const Sizes sz = sizes_of(*dims);
+    if (dims->hbm_budget && sz.base_bytes > dims->hbm_budget) {
+        g_create_error = "plan exceeds hbm_budget";
+        return PRIOR_LS_ENOMEM;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        g_create_error = "no HIP device";
+        return PRIOR_LS_EHIP;
+    }
+    auto* h = new prior_ls_handle();
+    h->d = *dims;
+    h->ustream = (hipStream_t)stream;
+    h->sz = sz;
+    const int r = guarded(h, [&]() -> int {
+        PLS_HIP(hipGetDevice(&h->device));
+        PLS_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        PLS_HIP(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+        const prior_ls_dims& d = h->d;
+        h->C = h->alloc<float2>(sz.I * sizeof(float2));
+        for (int k = 0; k < 2; ++k) {
+            h->L[k] = h->alloc<float2>(sz.I * sizeof(float2));
+            h->S[k] = h->alloc<float2>(sz.I * sizeof(float2));
+        }
+        if (d.nc > 1) h->sens = h->alloc<float2>((size_t)d.nc * sz.N * sizeof(float2));
+        h->w = h->alloc<uint8_t>(sz.I);
+        h->sidx = h->alloc<int16_t>((size_t)d.nt * sz.P * sizeof(int16_t));
+        h->plist = h->alloc<int>((size_t)d.nt * sz.P * sizeof(int));
+        h->ns = h->alloc<int>((d.nt + 1) * sizeof(int));
+        h->dh_off = h->alloc<int>((d.nt + 1) * sizeof(int));
+        h->line_off = h->alloc<int>((d.nt + 1) * sizeof(int));
+        h->twx = h->alloc<float2>(d.nx * sizeof(float2));
+        h->twy = h->alloc<float2>(d.ny * sizeof(float2));
+        h->twz = h->alloc<float2>(d.nz * sizeof(float2));
+        h->gpart = h->alloc<double>((size_t)sz.gblocks * sz.gentries * sizeof(double));
+        h->gred = h->alloc<double>(sz.gentries * sizeof(double));
+        h->V = h->alloc<double>(2 * 32 * 32 * sizeof(double));
+        h->Wd = h->alloc<double>(2 * 32 * 32 * sizeof(double));
+        h->Wop = h->alloc<float>(64 * 64 * sizeof(float));
+        h->sigma_prev = h->alloc<double>(64 * sizeof(double));
+        h->dc_part = h->alloc<double>((size_t)sz.dcb * 4 * sizeof(double));
+        h->sp_part = h->alloc<double>((size_t)std::max(sz.spb, 1) * sizeof(double));
+        h->stats_d = h->alloc<double>((size_t)kMaxChunk * kStatRec * sizeof(double));
+        PLS_HIP(hipHostMalloc((void**)&h->stats_h, kStatRec * sizeof(double), hipHostMallocDefault));
+        upload_twiddles(h->twx, d.nx, h->stream);
+        upload_twiddles(h->twy, d.ny, h->stream);
+        upload_twiddles(h->twz, d.nz, h->stream);
+        PLS_HIP(hipMemsetAsync(h->stats_d, 0, (size_t)kMaxChunk * kStatRec * sizeof(double), h->stream));
+        PLS_HIP(hipStreamSynchronize(h->stream));
+        return PRIOR_LS_OK;
+    });
+    if (r != PRIOR_LS_OK) {
+        g_create_error = h->err;
+        prior_ls_destroy(h);
+        return r;
+    }
+    *out = h;
+    return PRIOR_LS_OK;
+}
+
+void prior_ls_destroy(prior_ls_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    h->clear_graphs();
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->stats_h) (void)hipHostFree(h->stats_h);
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int prior_ls_solve(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* params,
+                   const prior_ls_outputs* out, prior_ls_stats* stats) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!in) return fail(h, PRIOR_LS_EINVAL, "inputs is NULL");
+    int rc = check_params(h, params);
+    if (rc) return rc;
+    if (stats && stats->struct_size != sizeof(prior_ls_stats))
+        return fail(h, PRIOR_LS_EINVAL, "stats.struct_size mismatch");
+    if (!in->kspace || !in->mask) return fail(h, PRIOR_LS_EINVAL, "kspace and mask are required");
+    if (h->d.nc > 1 && !in->sens) return fail(h, PRIOR_LS_EINVAL, "sens is required when nc > 1");
+    if ((in->L0 == nullptr) != (in->S0 == nullptr)) return fail(h, PRIOR_LS_EINVAL, "L0 and S0: both or neither");
+    if (params->lambda_p > 0 && !in->sigma_prev) return fail(h, PRIOR_LS_EINVAL, "sigma_prev is required when lambda_p > 0");
+    const void* dev[] = {in->kspace, in->mask, in->sens, in->prior_w, in->L0, in->S0};
+    for (const void* p : dev)
+        if (p && !is_device_ptr(p)) return fail(h, PRIOR_LS_EINVAL, "input array is not device memory");
+    if (out) {
+        const void* o[] = {out->L, out->S, out->X, out->M};
+        for (const void* p : o)
+            if (p && !is_device_ptr(p)) return fail(h, PRIOR_LS_EINVAL, "output array is not device memory");
+    }
+    return guarded(h, [&]() -> int {
+        enter(h);
+        int r = load_problem(h, in, params);
+        if (r) return r;
+        bool conv = false;
+        r = iterate(h, params->max_iter, conv);
+        write_outputs(h, out);
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(h->stream));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        fill_stats(h, stats, conv, ms);
+        return r;
+    });
+}
+
+int prior_ls_step(prior_ls_handle* h, int32_t n_iter, const prior_ls_outputs* out, prior_ls_stats* stats) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!h->loaded) return fail(h, PRIOR_LS_EINVAL, "step before solve");
+    if (n_iter < 0) return fail(h, PRIOR_LS_EINVAL, "n_iter must be >= 0");
+    if (stats && stats->struct_size != sizeof(prior_ls_stats))
+        return fail(h, PRIOR_LS_EINVAL, "stats.struct_size mismatch");
+    if (out) {
+        const void* o[] = {out->L, out->S, out->X, out->M};
+        for (const void* p : o)
+            if (p && !is_device_ptr(p)) return fail(h, PRIOR_LS_EINVAL, "output array is not device memory");
+    }
+    return guarded(h, [&]() -> int {
+        enter(h);
+        bool conv = false;
+        const int r = iterate(h, n_iter, conv);
+        write_outputs(h, out);
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(h->stream));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        fill_stats(h, stats, conv, ms);
+        return r;
+    });
+}
+
+int prior_ls_op_dc(prior_ls_handle* h, const void* Y, void* M, double* resid_norm) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    if (!h->loaded) return fail(h, PRIOR_LS_EINVAL, "no problem loaded (call solve first)");
+    if (!is_device_ptr(Y) || !is_device_ptr(M)) return fail(h, PRIOR_LS_EINVAL, "Y and M must be device memory");
+    return guarded(h, [&]() -> int {
+        const prior_ls_dims& d = h->d;
+        ensure_op_scratch(h);
+        enter(h);
+        hipStream_t s = h->stream;
+        pls::launch_pack((const float2*)Y, nullptr, h->T1, d.nt, d.nx, d.ny, d.nz, s);
+        DcArgs da = dc_args(h, h->T1, nullptr, h->T2);
+        const int dcb = pls::launch_dc(d.ny, d.nz, false, da, s);
+        double* rec = h->stats_d + (size_t)(kMaxChunk - 1) * kStatRec;
+        pls::StatsArgs st{h->dc_part, dcb, h->sp_part, 0, rec, (double)h->sz.P, 0.0};
+        pls::launch_stats(st, s);
+        pls::launch_unpack(h->T2, nullptr, (float2*)M, d.nt, d.nx, d.ny, d.nz, s);
+        PLS_HIP(hipGetLastError());
+        double r0 = 0;
+        PLS_HIP(hipMemcpyAsync(&r0, rec, sizeof(double), hipMemcpyDeviceToHost, s));
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(s));
+        if (resid_norm) *resid_norm = std::sqrt(std::max(r0, 0.0));
+        return PRIOR_LS_OK;
+    });
+}
+
+int prior_ls_op_svt(prior_ls_handle* h, const void* C, void* L, double* sigma) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    if (!h->loaded) return fail(h, PRIOR_LS_EINVAL, "no problem loaded (call solve first)");
+    if (!is_device_ptr(C) || !is_device_ptr(L)) return fail(h, PRIOR_LS_EINVAL, "C and L must be device memory");
+    return guarded(h, [&]() -> int {
+        const prior_ls_dims& d = h->d;
+        ensure_op_scratch(h);
+        enter(h);
+        hipStream_t s = h->stream;
+        pls::launch_pack((const float2*)C, nullptr, h->T1, d.nt, d.nx, d.ny, d.nz, s);
+        pls::GramArgs ga{h->T1, h->gpart, (int)h->sz.N, d.nt, 0};
+        const int gb = pls::launch_gram(d.gram_mode, ga, s);
+        pls::launch_gram_reduce(h->gpart, gb, h->sz.gentries, h->gred, s);
+        set_identity_V(h, h->Vop);
+        double* rec = h->stats_d + (size_t)(kMaxChunk - 1) * kStatRec;
+        pls::EigArgs ea{};
+        ea.gram = h->gred;
+        ea.V = h->Vop;
+        ea.warm = 1;
+        ea.Wop = h->Wopop;
+        ea.Wd = h->Wdop;
+        ea.sigma_prev = h->sigma_prev;
+        ea.stat = rec;
+        ea.nt = d.nt;
+        ea.lambda_L = h->params.lambda_L;
+        ea.lambda_p = h->params.lambda_p;
+        ea.relative = h->params.lambda_L_relative;
+        pls::launch_eig(ea, s);
+        pls::BpArgs ba{h->T1, h->T2, h->Wopop, (int)h->sz.N, d.nt};
+        pls::launch_bp(ba, s);
+        pls::launch_unpack(h->T2, nullptr, (float2*)L, d.nt, d.nx, d.ny, d.nz, s);
+        PLS_HIP(hipGetLastError());
+        double rr[kStatRec];
+        PLS_HIP(hipMemcpyAsync(rr, rec, sizeof(rr), hipMemcpyDeviceToHost, s));
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(s));
+        if (sigma)
+            for (int i = 0; i < d.nt; ++i) sigma[i] = rr[16 + i];
+        return PRIOR_LS_OK;
+    });
+}
+
+int prior_ls_op_sparse(prior_ls_handle* h, const void* Xm, const void* Lp, void* S) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    if (!h->loaded) return fail(h, PRIOR_LS_EINVAL, "no problem loaded (call solve first)");
+    if (!is_device_ptr(Xm) || !is_device_ptr(Lp) || !is_device_ptr(S))
+        return fail(h, PRIOR_LS_EINVAL, "Xm, Lp and S must be device memory");
+    return guarded(h, [&]() -> int {
+        const prior_ls_dims& d = h->d;
+        ensure_op_scratch(h);
+        enter(h);
+        hipStream_t s = h->stream;
+        pls::launch_pack((const float2*)Xm, nullptr, h->T1, d.nt, d.nx, d.ny, d.nz, s);
+        pls::launch_pack((const float2*)Lp, nullptr, h->T2, d.nt, d.nx, d.ny, d.nz, s);
+        pls::SparseArgs sa{};
+        sa.C = h->T1;
+        sa.S = nullptr;
+        sa.Lp = h->T2;
+        sa.w = h->has_w ? h->w : nullptr;
+        sa.Sout = h->T1;
+        sa.part = h->sp_part;
+        sa.nx = d.nx;
+        sa.ny = d.ny;
+        sa.nz = d.nz;
+        sa.nt = d.nt;
+        sa.lambda_S = (float)h->params.lambda_S;
+        pls::launch_sparse(d.wavelet_levels, sa, s);
+        pls::launch_unpack(h->T1, nullptr, (float2*)S, d.nt, d.nx, d.ny, d.nz, s);
+        PLS_HIP(hipGetLastError());
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(s));
+        return PRIOR_LS_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the header
+declares, and rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1411_6206_amd as pls
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prior_ls.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(pls.LIB_PATH),
+                                reason="libprior_ls.so not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(prior_ls_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(pls.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported():
+    L = C.CDLL(pls.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_struct_sizes_match_header():
+    # offsets and sizes the C compiler assigns (x86-64 SysV)
+    assert C.sizeof(pls.Dims) == 48
+    assert C.sizeof(pls.Params) == 56
+    assert C.sizeof(pls.Inputs) == 56
+    assert C.sizeof(pls.Outputs) == 32
+    assert C.sizeof(pls.Stats) == 8 + 16 + 6 * 8 + 32 * 8 + 8
+
+
+def _create(**kw):
+    base = dict(nx=64, ny=64, nz=1, nt=16, nc=1, wavelet_levels=2)
+    base.update(kw)
+    d = pls.make_dims(**base)
+    h = C.c_void_p()
+    rc = pls.lib().prior_ls_create(C.byref(d), None, C.byref(h))
+    return rc, h, pls.lib().prior_ls_last_error(None).decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nt=33), pls.ESHAPE),
+    (dict(nt=0), pls.ESHAPE),
+    (dict(ny=20), pls.ESHAPE),            # not in the FFT length set
+    (dict(ny=512), pls.ESHAPE),
+    (dict(nz=2), pls.ESHAPE),
+    (dict(nx=100), pls.ESHAPE),
+    (dict(wavelet_levels=4), pls.ESHAPE),
+    (dict(wavelet_levels=-1), pls.ESHAPE),
+    (dict(nz=4, wavelet_levels=3), pls.ESHAPE),   # 4 not divisible by 8
+    (dict(nc=65), pls.ESHAPE),
+    (dict(gram_mode=7), pls.EINVAL),
+])
+def test_create_rejects_bad_dims(kw, code):
+    rc, h, msg = _create(**kw)
+    assert rc == code, msg
+    assert h.value is None
+    assert msg
+
+
+def test_create_rejects_null_and_size_mismatch():
+    L = pls.lib()
+    h = C.c_void_p()
+    assert L.prior_ls_create(None, None, C.byref(h)) == pls.EINVAL
+    d = pls.make_dims(64, 64, 1, 16, 1)
+    d.struct_size = 12
+    assert L.prior_ls_create(C.byref(d), None, C.byref(h)) == pls.EINVAL
+    d = pls.make_dims(64, 64, 1, 16, 1)
+    d.reserved = 1
+    assert L.prior_ls_create(C.byref(d), None, C.byref(h)) == pls.EINVAL
+    assert L.prior_ls_create(C.byref(pls.make_dims(64, 64, 1, 16, 1)), None, None) == pls.EINVAL
+
+
+def test_budget_below_plan_is_enomem():
+    need = pls.plan_bytes(64, 64, 1, 16, 1)
+    assert need > 5 * 64 * 64 * 16 * 8
+    rc, h, msg = _create(hbm_budget=need // 2)
+    assert rc == pls.ENOMEM, msg
+
+
+def test_plan_bytes_zero_for_invalid():
+    assert pls.plan_bytes(64, 64, 1, 40, 1) == 0
+
+
+def test_null_handle_calls():
+    L = pls.lib()
+    L.prior_ls_destroy(None)
+    assert L.prior_ls_step(None, 1, None, None) == pls.EINVAL
+    assert L.prior_ls_solve(None, None, None, None, None) == pls.EINVAL
+    assert L.prior_ls_op_dc(None, None, None, None) == pls.EINVAL
+    for code in (0, -1, -2, -3, -4, -5):
+        assert pls.strerror(code)
+    assert pls.strerror(123) == "unknown status"
+
+
+def test_valid_dims_without_gpu_fail_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, h, msg = _create()
+    assert rc == pls.EHIP
+    assert h.value is None

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerance: relative L2 <= 1e-4 per result after K iterations (FP32 FFT / threshold
+path, FP64 Gram and eigensolve); the single-step operators are held to 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_1411_6206_amd as pls  # noqa: E402
+
+TOL = 1e-4
+TOL_OP = 1e-5
+
+# (name, problem kwargs, levels): several tiles, ragged plane batches, radix-3 lengths,
+# 2D and 3D, single and multi coil
+CASES = [
+    ("3d_16x16x4_nt6_nc2", dict(nx=16, ny=16, nz=4, nt=6, nc=2, accel=3, rank=2, nblobs=3, seed=11), 2),
+    ("3d_24x24x4_nt5_nc1", dict(nx=24, ny=24, nz=4, nt=5, nc=1, accel=2, rank=2, nblobs=2, seed=12), 1),
+    ("3d_32x48x8_nt12_nc3", dict(nx=32, ny=48, nz=8, nt=12, nc=3, accel=4, rank=3, nblobs=4, seed=13), 2),
+    ("2d_32x32_nt8_nc1", dict(nx=32, ny=32, nz=1, nt=8, nc=1, accel=3, rank=2, nblobs=3, seed=14), 2),
+    ("3d_48x96x16_nt17_nc2", dict(nx=48, ny=96, nz=16, nt=17, nc=2, accel=6, rank=3, nblobs=6, seed=15), 3),
+]
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.complex64)).cuda()
+
+
+def make(case):
+    name, kw, J = case
+    p = synth.small(**kw, levels=J)
+    return p, J
+
+
+def handle(p, J, **kw):
+    return pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J, **kw)
+
+
+def load(h, p, **kw):
+    t = pls.to_device(p)
+    args = dict(lambda_L=p.lambda_L, lambda_S=p.lambda_S, max_iter=0)
+    args.update(kw)
+    return h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], **args)
+
+
+@pytest.fixture(params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    return make(request.param)
+
+
+def test_step0_adjoint_of_data(case):
+    p, J = case
+    with handle(p, J) as h:
+        out, st = load(h, p)
+        want = oracle.EH(p.kspace, p.mask, p.sens)
+        assert rel(host(out["M"]), want) < TOL_OP
+        assert rel(host(out["L"]), want) < TOL_OP
+        assert np.abs(host(out["S"])).max() == 0
+
+
+def test_op_dc_matches_oracle(case):
+    p, J = case
+    rng = np.random.default_rng(3)
+    Y = p.X_true + 0.1 * (rng.standard_normal(p.X_true.shape) + 1j * rng.standard_normal(p.X_true.shape))
+    Y = Y.astype(np.complex64).astype(np.complex128)
+    with handle(p, J) as h:
+        load(h, p)
+        M, r = h.op_dc(dev(Y))
+    want, R = oracle.dc_step(Y, p.kspace, p.mask, p.sens)
+    assert rel(host(M), want) < TOL_OP
+    assert r == pytest.approx(np.linalg.norm(R), rel=1e-5)
+
+
+def test_normal_operator_is_hermitian(case):
+    """<N x, y> = <x, N y> for N = E^H E = op_dc(0) - op_dc(Y) + Y (adjoint identity)."""
+    p, J = case
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(p.shape) + 1j * rng.standard_normal(p.shape)).astype(np.complex64)
+    y = (rng.standard_normal(p.shape) + 1j * rng.standard_normal(p.shape)).astype(np.complex64)
+    with handle(p, J) as h:
+        load(h, p)
+        m0, _ = h.op_dc(torch.zeros(p.shape, dtype=torch.complex64, device="cuda"))
+        mx, _ = h.op_dc(dev(x))
+        my, _ = h.op_dc(dev(y))
+    Nx = host(m0) - host(mx) + x
+    Ny = host(m0) - host(my) + y
+    lhs = np.vdot(y, Nx)
+    rhs = np.vdot(Ny, x)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    assert rel(Nx, oracle.EH(oracle.E(x, p.mask, p.sens), p.mask, p.sens)) < TOL_OP
+
+
+def test_op_svt_matches_oracle(case):
+    p, J = case
+    with handle(p, J) as h:
+        load(h, p)
+        Cm = oracle.EH(p.kspace, p.mask, p.sens).astype(np.complex64).astype(np.complex128)
+        Lg, sig = h.op_svt(dev(Cm))
+    Lw, sw, _, _ = oracle.svt(oracle.cas(Cm), p.lambda_L)
+    assert rel(host(Lg), oracle.uncas(Lw, p.shape)) < TOL_OP
+    np.testing.assert_allclose(sig, sw, rtol=1e-5, atol=1e-6 * sw[0])
+
+
+def test_op_svt_sigma_prior(case):
+    p, J = case
+    rng = np.random.default_rng(8)
+    prev = np.sort(rng.uniform(0, 2, p.nt))[::-1]
+    with handle(p, J) as h:
+        load(h, p, lambda_p=0.5, sigma_prev=prev)
+        Cm = oracle.EH(p.kspace, p.mask, p.sens).astype(np.complex64).astype(np.complex128)
+        Lg, _ = h.op_svt(dev(Cm))
+    Lw, _, _, _ = oracle.svt(oracle.cas(Cm), p.lambda_L, True, 0.5, prev)
+    assert rel(host(Lg), oracle.uncas(Lw, p.shape)) < TOL_OP
+
+
+def test_op_sparse_matches_oracle(case):
+    p, J = case
+    M0 = oracle.EH(p.kspace, p.mask, p.sens)
+    Lp = (0.5 * M0).astype(np.complex64).astype(np.complex128)
+    M0 = M0.astype(np.complex64).astype(np.complex128)
+    with handle(p, J) as h:
+        load(h, p, lambda_S=0.02)
+        Sg = h.op_sparse(dev(M0), dev(Lp))
+    Sw, _ = oracle.sparse_step(M0, Lp, p.prior_w, 0.02, J)
+    assert rel(host(Sg), Sw) < TOL_OP
+
+
+@pytest.mark.parametrize("iters", [1, 7])
+def test_solve_matches_oracle(case, iters):
+    p, J = case
+    with handle(p, J) as h:
+        out, st = load(h, p, max_iter=iters, check_every=3)
+    r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=J,
+                     iters=iters)
+    for k in ("L", "S", "X", "M"):
+        assert rel(host(out[k]), r[k]) < TOL, k
+    assert st["iters"] == iters
+    assert st["resid_norm"] == pytest.approx(r["resid"][-1], rel=1e-4)
+    assert st["nuclear_norm"] == pytest.approx(r["nuclear"][-1], rel=1e-4)
+    assert st["rel_change"] == pytest.approx(r["rel_change"][-1], rel=1e-3)
+    np.testing.assert_allclose(st["sigma"], r["sigma"][-1], rtol=1e-4, atol=1e-5 * r["sigma"][-1][0])
+
+
+def test_solve_with_sigma_prior_and_warm_start(case):
+    p, J = case
+    rng = np.random.default_rng(9)
+    prev = np.sort(rng.uniform(0, 3, p.nt))[::-1]
+    L0 = (0.9 * p.L_true).astype(np.complex64).astype(np.complex128)
+    S0 = (0.8 * p.S_true).astype(np.complex64).astype(np.complex128)
+    with handle(p, J) as h:
+        out, st = load(h, p, max_iter=5, lambda_p=0.5, sigma_prev=prev, L0=dev(L0), S0=dev(S0))
+    r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, lambda_p=0.5,
+                     sigma_prev=prev, levels=J, iters=5, L0=L0, S0=S0)
+    for k in ("L", "S", "X", "M"):
+        assert rel(host(out[k]), r[k]) < TOL, k
+
+
+def test_determinism_resume_and_graphs(case):
+    p, J = case
+    with handle(p, J) as h:
+        a, _ = load(h, p, max_iter=6, check_every=4)
+        b, _ = load(h, p, max_iter=6, check_every=2, use_graph=False)
+        c0, _ = load(h, p, max_iter=4, check_every=4)
+        c, _ = h.step(2)
+    for k in ("L", "S", "M"):
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(a[k], c[k]), k
+
+
+def test_config1_full(request):
+    p = synth.config(1)
+    with handle(p, 2) as h:
+        out, st = load(h, p, max_iter=p.iters, check_every=10)
+    r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=2,
+                     iters=p.iters)
+    for k in ("L", "S", "X", "M"):
+        assert rel(host(out[k]), r[k]) < TOL, k
