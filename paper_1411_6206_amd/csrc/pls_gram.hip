@@ -108,8 +108,9 @@ __global__ void __launch_bounds__(256) pls_gram_f64_kernel(GramArgs a) {
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                // MFMA 16x16 output: lane holds row 4 * (lane / 16) + r, column lane % 16
-                const int row = 4 * g + r, col = i16;
+                // v_mfma_f64_16x16x4 output: register r of a lane holds row lane/16 + 4 r,
+                // column lane % 16 (the f32 variant uses row 4 (lane/16) + r instead)
+                const int row = g + 4 * r, col = i16;
                 out[p * 256 + row * 16 + col] = acc[p][r] + red[0][p * 256 + r * 64 + slot];
             }
     }

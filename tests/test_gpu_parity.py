@@ -70,8 +70,8 @@ def test_step0_adjoint_of_data(case):
     with handle(p, J) as h:
         out, st = load(h, p)
         want = oracle.EH(p.kspace, p.mask, p.sens)
-        assert rel(host(out["M"]), want) < TOL_OP
-        assert rel(host(out["L"]), want) < TOL_OP
+        e1, e2 = rel(host(out["M"]), want), rel(host(out["L"]), want)
+        assert e1 < TOL_OP and e2 < TOL_OP, (e1, e2)
         assert np.abs(host(out["S"])).max() == 0
 
 
@@ -84,7 +84,8 @@ def test_op_dc_matches_oracle(case):
         load(h, p)
         M, r = h.op_dc(dev(Y))
     want, R = oracle.dc_step(Y, p.kspace, p.mask, p.sens)
-    assert rel(host(M), want) < TOL_OP
+    e = rel(host(M), want)
+    assert e < TOL_OP, e
     assert r == pytest.approx(np.linalg.norm(R), rel=1e-5)
 
 
@@ -104,7 +105,8 @@ def test_normal_operator_is_hermitian(case):
     lhs = np.vdot(y, Nx)
     rhs = np.vdot(Ny, x)
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
-    assert rel(Nx, oracle.EH(oracle.E(x, p.mask, p.sens), p.mask, p.sens)) < TOL_OP
+    e = rel(Nx, oracle.EH(oracle.E(x, p.mask, p.sens), p.mask, p.sens))
+    assert e < TOL_OP, e
 
 
 def test_op_svt_matches_oracle(case):
@@ -114,7 +116,8 @@ def test_op_svt_matches_oracle(case):
         Cm = oracle.EH(p.kspace, p.mask, p.sens).astype(np.complex64).astype(np.complex128)
         Lg, sig = h.op_svt(dev(Cm))
     Lw, sw, _, _ = oracle.svt(oracle.cas(Cm), p.lambda_L)
-    assert rel(host(Lg), oracle.uncas(Lw, p.shape)) < TOL_OP
+    e = rel(host(Lg), oracle.uncas(Lw, p.shape))
+    assert e < TOL_OP, e
     np.testing.assert_allclose(sig, sw, rtol=1e-5, atol=1e-6 * sw[0])
 
 
@@ -127,7 +130,8 @@ def test_op_svt_sigma_prior(case):
         Cm = oracle.EH(p.kspace, p.mask, p.sens).astype(np.complex64).astype(np.complex128)
         Lg, _ = h.op_svt(dev(Cm))
     Lw, _, _, _ = oracle.svt(oracle.cas(Cm), p.lambda_L, True, 0.5, prev)
-    assert rel(host(Lg), oracle.uncas(Lw, p.shape)) < TOL_OP
+    e = rel(host(Lg), oracle.uncas(Lw, p.shape))
+    assert e < TOL_OP, e
 
 
 def test_op_sparse_matches_oracle(case):
@@ -139,7 +143,8 @@ def test_op_sparse_matches_oracle(case):
         load(h, p, lambda_S=0.02)
         Sg = h.op_sparse(dev(M0), dev(Lp))
     Sw, _ = oracle.sparse_step(M0, Lp, p.prior_w, 0.02, J)
-    assert rel(host(Sg), Sw) < TOL_OP
+    e = rel(host(Sg), Sw)
+    assert e < TOL_OP, e
 
 
 @pytest.mark.parametrize("iters", [1, 7])
@@ -150,7 +155,8 @@ def test_solve_matches_oracle(case, iters):
     r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=J,
                      iters=iters)
     for k in ("L", "S", "X", "M"):
-        assert rel(host(out[k]), r[k]) < TOL, k
+        e = rel(host(out[k]), r[k])
+        assert e < TOL, (k, e)
     assert st["iters"] == iters
     assert st["resid_norm"] == pytest.approx(r["resid"][-1], rel=1e-4)
     assert st["nuclear_norm"] == pytest.approx(r["nuclear"][-1], rel=1e-4)
@@ -169,7 +175,8 @@ def test_solve_with_sigma_prior_and_warm_start(case):
     r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, lambda_p=0.5,
                      sigma_prev=prev, levels=J, iters=5, L0=L0, S0=S0)
     for k in ("L", "S", "X", "M"):
-        assert rel(host(out[k]), r[k]) < TOL, k
+        e = rel(host(out[k]), r[k])
+        assert e < TOL, (k, e)
 
 
 def test_determinism_resume_and_graphs(case):
@@ -191,4 +198,5 @@ def test_config1_full(request):
     r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=2,
                      iters=p.iters)
     for k in ("L", "S", "X", "M"):
-        assert rel(host(out[k]), r[k]) < TOL, k
+        e = rel(host(out[k]), r[k])
+        assert e < TOL, (k, e)
