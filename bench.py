@@ -1,0 +1,230 @@
+"""Benchmark: Priori L+S iterations/s at 192^2 x 32 x 30 frames x 8 coils on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one iteration of Algorithm 1 over the whole volume (Gram, eigensolve,
+sparse update, back-projection, data consistency, statistics).  Inputs are the seeded
+synthetic phantom of the 192x192x32x30x8 workload, resident in HBM before timing.
+The timed region runs K iterations through prior_ls_step_timed, which records a
+hipEvent around every kernel on the library's stream; the dominant kernel's average
+launch duration comes from those events.  Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Priori L+S iterations/s at 192²×32×30×8coil; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_VALU_TFLOPS = 157.3     # MI355X FP32 vector peak
+FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+FP64_MFMA_TFLOPS = 78.6      # MI355X dense FP64 matrix peak
+KERNEL_SOURCES = {
+    "data_consistency": ["pls_dc_impl.hpp", "pls_fft.hpp", "pls_common.hpp"],
+    "gram": ["pls_gram.hip", "pls_common.hpp"],
+    "backproject": ["pls_ls.hip"],
+    "sparse": ["pls_ls.hip"],
+}
+
+
+def algorithmic(name, p, nsamp):
+    """(bytes, flops, bound-unit peak) per launch of a kernel, from the problem size alone.
+    bytes: each array the kernel must read or write once; flops: the operation's count."""
+    N = p.nx * p.ny * p.nz
+    I = N * p.nt * 8                      # one complex64 image array
+    P = p.ny * p.nz
+    if name == "data_consistency":
+        dh = p.nx * p.nc * nsamp * 8      # compact hybrid k-space, sampled entries only
+        sens = p.nc * N * 8 if p.nc > 1 else 0
+        b = 3 * I + dh + sens + p.nt * P * 2
+        f = p.nc * p.nt * p.nx * 2 * 5 * P * math.log2(P) + p.nc * p.nt * N * 14
+        return b, f
+    if name == "gram":
+        return I, 8 * N * p.nt ** 2
+    if name == "backproject":
+        return 2 * I, 8 * N * p.nt ** 2
+    if name == "sparse":
+        return 4 * I + N * p.nt, 0
+    return 0, 0
+
+
+def source_hash(name):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(name, []):
+        with open(os.path.join(ROOT, "paper_1411_6206_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(name, workload):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (committed under
+    profiles/), or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(f"{workload}:{name}")
+    if not rec or rec.get("source_hash") != source_hash(name):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(p, frames):
+    """The FP64 oracle, untuned, on a bounded sample: one iteration of Algorithm 1 on the
+    first `frames` frames of the same volume and coils; seconds scaled by nt / frames."""
+    import numpy as np
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    d = np.ascontiguousarray(p.kspace[:, :frames])
+    m = np.ascontiguousarray(p.mask[:frames])
+    w = None if p.prior_w is None else np.ascontiguousarray(p.prior_w[:frames])
+    t0 = time.perf_counter()
+    oracle.solve(d, m, p.sens, w, p.lambda_L, p.lambda_S, levels=2, iters=0)
+    t1 = time.perf_counter()
+    oracle.solve(d, m, p.sens, w, p.lambda_L, p.lambda_S, levels=2, iters=1)
+    t2 = time.perf_counter()
+    it_s = max((t2 - t1) - (t1 - t0), 1e-9)        # one iteration, initialisation removed
+    full = it_s * p.nt / frames
+    return {"value": 1.0 / full, "unit": "iterations/s", "cores": cores, "kind": "oracle",
+            "sample": f"one FP64 oracle iteration on {frames} of {p.nt} frames of the same "
+                      f"{p.nx}x{p.ny}x{p.nz} x {p.nc}-coil problem ({it_s:.1f} s), scaled by "
+                      f"{p.nt}/{frames}; numpy FFT single-threaded, LAPACK SVD threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--latency-iters", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=8)
+    ap.add_argument("--gram-mode", default="fp64")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the iteration shards by x-plane with one Gram all-reduce per iteration; not built)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1411_6206_amd as pls
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    pls.lib()                                   # fails loudly when the library is missing
+    t0 = time.perf_counter()
+    p = synth.config(args.config)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] inputs generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    nsamp = int(p.mask.sum())
+    t = pls.to_device(p)
+    h = pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=2, gram_mode=args.gram_mode)
+    solve_kw = dict(lambda_L=p.lambda_L, lambda_S=p.lambda_S)
+
+    def solve(n, **kw):
+        return h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], max_iter=n,
+                       outputs=(), **solve_kw, **kw)
+
+    solve(0)                                    # load: compact k-space, coils, weights, X_0
+    h.step(args.warmup) if args.warmup > 0 else None
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    kms, st = h.step_timed(args.steps)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    ms_per_step = (te - ts) * 1e3 / args.steps
+    value = args.steps / (te - ts)
+
+    # the same iterations replayed as hipGraph chunks (production path)
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    h.step(args.steps)
+    torch.cuda.synchronize()
+    graph_its = args.steps / (time.perf_counter() - tg)
+
+    # solve latency (load + step (0) + latency_iters iterations + outputs)
+    lat = []
+    for _ in range(args.latency_reps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        solve(args.latency_iters, check_every=args.latency_iters)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    lat = np.array(lat)
+    print(f"[bench] timed {args.steps} iterations: {value:.1f} it/s; solve latency done",
+          file=sys.stderr, flush=True)
+
+    workload = f"c{args.config}"
+    kernels = {}
+    for name, tot in kms.items():
+        per = tot / args.steps
+        b, f = algorithmic(name, p, nsamp)
+        kernels[name] = {"ms_per_launch": per,
+                         "GB_s": (b / (per * 1e-3) / 1e9) if b and per > 0 else None,
+                         "TFLOP_s": (f / (per * 1e-3) / 1e12) if f and per > 0 else None}
+    dom = max(kms, key=kms.get)
+    per = kms[dom] / args.steps
+    b, f = algorithmic(dom, p, nsamp)
+    gbs = b / (per * 1e-3) / 1e9 if b else 0.0
+    if dom == "data_consistency":
+        tfl = f / (per * 1e-3) / 1e12
+        if tfl / FP32_VALU_TFLOPS >= gbs / HBM_PEAK_GBS:
+            roof = {"bound": "alu", "achieved": tfl, "peak": FP32_VALU_TFLOPS, "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif dom == "gram" and args.gram_mode == "fp64":
+        tfl = f / (per * 1e-3) / 1e12
+        if tfl / FP64_MFMA_TFLOPS >= gbs / HBM_PEAK_GBS:
+            roof = {"bound": "mfma", "achieved": tfl, "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+    roof["traffic"] = traffic_for(dom, workload)
+    roof["algorithmic_bytes_per_launch"] = b
+    roof["algorithmic_flops_per_launch"] = f
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{p.nx}x{p.ny}x{p.nz} voxels x {p.nt} frames x {p.nc} coils, "
+                               f"{nsamp} of {p.nt * p.ny * p.nz} phase-encode lines (10x), "
+                               f"rank-6 + 60 blobs seeded phantom, J=2 Haar, FP64 Gram",
+                   "nx": p.nx, "ny": p.ny, "nz": p.nz, "nt": p.nt, "nc": p.nc,
+                   "gram_mode": args.gram_mode},
+        "roofline": roof,
+        "p50_solve_ms": float(np.percentile(lat, 50)),
+        "p99_solve_ms": float(np.percentile(lat, 99)),
+        "solve_iters": args.latency_iters,
+        "graph_iterations_per_s": graph_its,
+        "kernels": kernels,
+        "resid_norm": st["resid_norm"],
+        "input_gen_s": gen_s,
+    }
+    h.close()
+    del t
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, min(args.cpu_frames, p.nt))
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

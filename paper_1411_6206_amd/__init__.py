@@ -28,7 +28,9 @@ MAX_NT = 32
 # every symbol include/prior_ls.h declares
 EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destroy",
            "prior_ls_strerror", "prior_ls_last_error", "prior_ls_plan_bytes",
-           "prior_ls_op_dc", "prior_ls_op_svt", "prior_ls_op_sparse")
+           "prior_ls_op_dc", "prior_ls_op_svt", "prior_ls_op_sparse", "prior_ls_step_timed")
+NKERNELS = 7
+KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats")
 
 
 class LibraryMissing(RuntimeError):
@@ -111,6 +113,9 @@ def lib():
     L.prior_ls_op_svt.restype = C.c_int
     L.prior_ls_op_sparse.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p]
     L.prior_ls_op_sparse.restype = C.c_int
+    L.prior_ls_step_timed.argtypes = [H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                      C.POINTER(Stats)]
+    L.prior_ls_step_timed.restype = C.c_int
     _lib = L
     return L
 
@@ -197,6 +202,17 @@ class PriorLS:
         rc = lib().prior_ls_step(self._h, int(n_iter), C.byref(o), C.byref(st))
         self._check(rc, "prior_ls_step")
         return outs, st.as_dict()
+
+    def step_timed(self, n_iter):
+        """prior_ls_step_timed: n_iter iterations with per-kernel hipEvent timing.
+        Returns ({kernel name: summed ms}, stats)."""
+        ms = (C.c_double * NKERNELS)()
+        cnt = (C.c_int32 * NKERNELS)()
+        st = Stats()
+        st.struct_size = C.sizeof(Stats)
+        rc = lib().prior_ls_step_timed(self._h, int(n_iter), ms, cnt, C.byref(st))
+        self._check(rc, "prior_ls_step_timed")
+        return {k: ms[i] for i, k in enumerate(KERNEL_NAMES)}, st.as_dict()
 
     def op_dc(self, Y):
         """prior_ls_op_dc: M = Y - A^H(A(Y) - d), step (4)."""

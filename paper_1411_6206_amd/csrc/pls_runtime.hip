@@ -230,16 +230,23 @@ bool is_device_ptr(const void* p) {
 }
 
 // one iteration of Algorithm 1 on the resident state (see the schedule in the header)
-void enqueue_iteration(prior_ls_handle* h, int slot, bool stats) {
+// ev (optional): 8 timing events recorded around the 7 launches of the iteration
+void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev = nullptr) {
     const prior_ls_dims& d = h->d;
     const Sizes& sz = h->sz;
     hipStream_t s = h->stream;
     const int p = h->cur, q = 1 - p;
     double* rec = h->stats_d + (size_t)slot * kStatRec;
+    auto mark = [&](int k) {
+        if (ev) PLS_HIP(hipEventRecord(ev[k], s));
+    };
     // steps (1)-(2): Gram, eigensolve, W
+    mark(0);
     pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0};
     const int gb = pls::launch_gram(d.gram_mode, ga, s);
+    mark(1);
     pls::launch_gram_reduce(h->gpart, gb, sz.gentries, h->gred, s);
+    mark(2);
     pls::EigArgs ea{};
     ea.gram = h->gred;
     ea.V = h->V;
@@ -253,6 +260,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats) {
     ea.lambda_p = h->params.lambda_p;
     ea.relative = h->params.lambda_L_relative;
     pls::launch_eig(ea, s);
+    mark(3);
     // step (3): S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)
     pls::SparseArgs sa{};
     sa.C = h->C;
@@ -267,9 +275,11 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats) {
     sa.nt = d.nt;
     sa.lambda_S = (float)h->params.lambda_S;
     const int spb = pls::launch_sparse(d.wavelet_levels, sa, s);
+    mark(4);
     // steps (1)-(2): L_k = C W
     pls::BpArgs ba{h->C, h->L[q], h->Wop, (int)sz.N, d.nt};
     pls::launch_bp(ba, s);
+    mark(5);
     // step (4): data consistency -> C = M_k - S_k
     DcArgs da{};
     da.L = h->L[q];
@@ -290,8 +300,10 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats) {
     da.nc = d.nc;
     da.inv_p = 1.0f / (float)sz.P;
     const int dcb = pls::launch_dc(d.ny, d.nz, stats, da, s);
+    mark(6);
     pls::StatsArgs st{h->dc_part, dcb, h->sp_part, spb, rec, (double)sz.P, h->params.lambda_S};
     pls::launch_stats(st, s);
+    mark(7);
     h->cur = q;
 }
 
@@ -705,6 +717,47 @@ int prior_ls_step(prior_ls_handle* h, int32_t n_iter, const prior_ls_outputs* ou
         fill_stats(h, stats, conv, ms);
         return r;
     });
+}
+
+int prior_ls_step_timed(prior_ls_handle* h, int32_t n_iter, double* kernel_ms,
+                        int32_t* kernel_launches, prior_ls_stats* stats) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!h->loaded) return fail(h, PRIOR_LS_EINVAL, "step before solve");
+    if (n_iter < 1 || n_iter > kMaxChunk) return fail(h, PRIOR_LS_EINVAL, "n_iter must be in [1, 1024]");
+    if (!kernel_ms) return fail(h, PRIOR_LS_EINVAL, "kernel_ms is NULL");
+    if (stats && stats->struct_size != sizeof(prior_ls_stats))
+        return fail(h, PRIOR_LS_EINVAL, "stats.struct_size mismatch");
+    std::vector<hipEvent_t> ev((size_t)n_iter * 8, nullptr);
+    const int r = guarded(h, [&]() -> int {
+        for (auto& e : ev) PLS_HIP(hipEventCreate(&e));
+        enter(h);
+        for (int j = 0; j < n_iter; ++j) enqueue_iteration(h, j, j == n_iter - 1, &ev[(size_t)j * 8]);
+        PLS_HIP(hipGetLastError());
+        PLS_HIP(hipMemcpyAsync(h->stats_h, h->stats_d + (size_t)(n_iter - 1) * kStatRec,
+                               kStatRec * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(h->stream));
+        std::memcpy(h->last, h->stats_h, sizeof(h->last));
+        h->iters += n_iter;
+        for (int k = 0; k < PRIOR_LS_NKERNELS; ++k) {
+            double tot = 0.0;
+            for (int j = 0; j < n_iter; ++j) {
+                float ms = 0.f;
+                PLS_HIP(hipEventElapsedTime(&ms, ev[(size_t)j * 8 + k], ev[(size_t)j * 8 + k + 1]));
+                tot += ms;
+            }
+            kernel_ms[k] = tot;
+            if (kernel_launches) kernel_launches[k] = n_iter;
+        }
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        fill_stats(h, stats, false, ms);
+        return h->last[7] != 0.0 ? fail(h, PRIOR_LS_ENONFINITE, "non-finite value in the iterate") : PRIOR_LS_OK;
+    });
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return r;
 }
 
 int prior_ls_op_dc(prior_ls_handle* h, const void* Y, void* M, double* resid_norm) {
