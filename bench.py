@@ -215,6 +215,7 @@ def main():
         "graph_iterations_per_s": graph_its,
         "kernels": kernels,
         "resid_norm": st["resid_norm"],
+        "eig_sweeps_last": st["eig_sweeps"],
         "input_gen_s": gen_s,
     }
     h.close()

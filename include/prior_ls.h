@@ -125,6 +125,8 @@ typedef struct {
     int32_t converged;          /* rel_change < tol at the last check */
     int32_t nonfinite;
     int32_t sigma_count;        /* = nt */
+    int32_t eig_sweeps;         /* Jacobi sweeps of the last eigensolve (warm-started) */
+    int32_t reserved;
     double  rel_change;         /* ||Y_k - Y_{k-1}|| / ||Y_{k-1}|| at the last iteration */
     double  resid_norm;         /* ||A(L_k + S_k) - d|| over the sampled entries (FP64) */
     double  nuclear_norm;       /* sum of the singular values of L_k */

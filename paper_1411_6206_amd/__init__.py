@@ -69,13 +69,15 @@ class Outputs(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("iters", C.c_int32), ("converged", C.c_int32),
                 ("nonfinite", C.c_int32), ("sigma_count", C.c_int32),
+                ("eig_sweeps", C.c_int32), ("reserved", C.c_int32),
                 ("rel_change", C.c_double), ("resid_norm", C.c_double),
                 ("nuclear_norm", C.c_double), ("l1_weighted", C.c_double),
                 ("objective", C.c_double), ("tau_L", C.c_double),
                 ("sigma", C.c_double * MAX_NT), ("ms", C.c_double)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("sigma", "struct_size")}
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("sigma", "struct_size", "reserved")}
         d["sigma"] = list(self.sigma)[: self.sigma_count]
         return d
 

@@ -17,17 +17,49 @@ template <int NY, int NZ>
 struct DcCfg {
     static constexpr int P = NY * NZ;
     static constexpr bool kHas3 = (NY % 3 == 0);
-    static constexpr int Q0 = kHas3 ? 24 : 16;
-    static constexpr int Q = (P / Q0 > 256) ? P / 256 : Q0;
+    static constexpr int Q0 = kHas3 ? 12 : 16;
+    static constexpr int Q = (P / Q0 > 512) ? P / 512 : Q0;
     static constexpr int PB = (P / Q >= 64) ? 1 : (64 * Q) / P;
-    using G = Geom<NY, NZ, PB, Q, 5>;
+    static constexpr int T = PB * P / Q;
+    // large blocks reload Y = L + S per coil (L2 hits) and cap registers at 128 so two
+    // blocks share a CU; small blocks keep Y in registers
+    using G = Geom<NY, NZ, PB, Q, 0, 32, (T >= 256 ? 4 : 2), (T < 256)>;
+};
+
+// Register distribution of a first pass of radix R along axis AX: element (i, r) of a
+// thread sits at plane-batch offset rel + r * STEP of plane pb (unpadded global layout).
+template <class G, int AX, int R>
+struct Dist {
+    using M = PassMap<G, AX, R>;
+    static constexpr int NB = M::NB;
+    static constexpr int JN = M::JN;
+    static constexpr int STEP = (AX == 0) ? JN : JN * G::NY;
+    int pb[NB];     // plane of the batch
+    int rel[NB];    // offset inside the plane of element (i, 0)
+    __device__ __forceinline__ Dist(int tid) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            int line, j;
+            M::map(tid, i, line, j);
+            if constexpr (AX == 0) {
+                pb[i] = line / G::NZ;
+                rel[i] = (line % G::NZ) * G::NY + j;
+            } else {
+                pb[i] = line / G::NY;
+                rel[i] = j * G::NY + (line % G::NY);
+            }
+        }
+    }
 };
 
 template <class G, bool STATS>
-__global__ void __launch_bounds__(G::T) pls_dc_kernel(DcArgs a) {
+__global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
     constexpr int Q = G::Q, P = G::P, NY = G::NY, NZ = G::NZ, PB = G::PB;
     constexpr int R0 = radix_in<G>();
     constexpr int RL = radix_out<G>();
+    constexpr int AXL = G::NPZ > 0 ? 1 : 0;
+    using D0 = Dist<G, 0, R0>;
+    using DL = Dist<G, AXL, RL>;
     __shared__ float2 lds[G::LDS_ELEMS];
     __shared__ float2 twy[NY];
     __shared__ float2 twz[NZ];
@@ -38,93 +70,126 @@ __global__ void __launch_bounds__(G::T) pls_dc_kernel(DcArgs a) {
 
     const int t = blockIdx.x % a.nt;
     const int x0 = (blockIdx.x / a.nt) * PB;
-    const size_t frame = (size_t)t * a.nx * P;
+    const int nvalid = a.nx - x0;              // planes of this batch that exist
+    const int plane0 = (t * a.nx + x0) * P;    // element offset of plane (t, x0)
     const bool has_y = (a.L != nullptr);
+    const D0 d0(tid);
+    const DL dl(tid);
 
-    float2 Y[Q], acc[Q], v[Q];
+    float2 Y[G::KEEPY ? Q : 1], acc[Q], v[Q];
     double dy2 = 0.0, y2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q / R0; ++i)
+    for (int i = 0; i < D0::NB; ++i) {
+        const bool ok = has_y && d0.pb[i] < nvalid;
+        const int o = plane0 + d0.pb[i] * P + d0.rel[i];
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            int pb, z, y;
-            pos_in<G>(tid, i, r, pb, z, y);
             const int q = i * R0 + r;
-            float2 yv = make_float2(0.f, 0.f);
-            if (has_y && x0 + pb < a.nx) {
-                const size_t gi = frame + (size_t)(x0 + pb) * P + z * NY + y;
-                yv = a.S ? cadd(a.L[gi], a.S[gi]) : a.L[gi];
-                if constexpr (STATS) {
-                    const float2 yo = cadd(a.Lold[gi], a.Sold[gi]);
-                    const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
-                    dy2 += dx * dx + dyy * dyy;
-                    y2 += (double)yo.x * yo.x + (double)yo.y * yo.y;
+            if constexpr (G::KEEPY || STATS) {
+                float2 yv = make_float2(0.f, 0.f);
+                if (ok) {
+                    const int gi = o + r * D0::STEP;
+                    yv = a.S ? cadd(a.L[gi], a.S[gi]) : a.L[gi];
+                    if constexpr (STATS) {
+                        const float2 yo = cadd(a.Lold[gi], a.Sold[gi]);
+                        const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
+                        dy2 += dx * dx + dyy * dyy;
+                        y2 += (double)yo.x * yo.x + (double)yo.y * yo.y;
+                    }
                 }
+                if constexpr (G::KEEPY) Y[q] = yv;
             }
-            Y[q] = yv;
             acc[q] = make_float2(0.f, 0.f);
         }
+    }
+    // sample index of every element of the post-transform distribution (same for all coils)
+    int16_t sid[G::KEEPY ? Q : 1];
+    if constexpr (G::KEEPY) {
+#pragma unroll
+        for (int i = 0; i < DL::NB; ++i)
+#pragma unroll
+            for (int r = 0; r < RL; ++r)
+                sid[i * RL + r] = (dl.pb[i] < nvalid) ? a.sidx[t * P + dl.rel[i] + r * DL::STEP]
+                                                      : (int16_t)-1;
+    }
 
     const int nst = a.ns[t];
-    const int off = a.dh_off[t];
+    const float2* dh_t = a.dh + a.dh_off[t];
     double res2 = 0.0;
+    __syncthreads();  // twiddle tables visible
     for (int c = 0; c < a.nc; ++c) {
-        const float2* sc = a.sens ? a.sens + (size_t)c * a.nx * P : nullptr;
+        const int tidc = opaque(tid);
+        const D0 e0(tidc);
+        const DL el(tidc);
+        const float2* sc = a.sens ? a.sens + (c * a.nx + x0) * P : nullptr;
 #pragma unroll
-        for (int i = 0; i < Q / R0; ++i)
+        for (int i = 0; i < D0::NB; ++i) {
+            const bool ok = e0.pb[i] < nvalid;
+            const int o = e0.pb[i] * P + e0.rel[i];
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-                int pb, z, y;
-                pos_in<G>(tid, i, r, pb, z, y);
                 const int q = i * R0 + r;
-                float2 sv = make_float2(1.f, 0.f);
-                if (sc && x0 + pb < a.nx) sv = sc[(size_t)(x0 + pb) * P + z * NY + y];
-                v[q] = cmul(sv, Y[q]);
+                float2 yv;
+                if constexpr (G::KEEPY) {
+                    yv = Y[q];
+                } else {
+                    yv = make_float2(0.f, 0.f);
+                    if (ok && has_y) {
+                        const int gi = plane0 + o + r * D0::STEP;
+                        yv = a.S ? cadd(a.L[gi], a.S[gi]) : a.L[gi];
+                    }
+                }
+                const float2 sv = (sc && ok) ? sc[o + r * D0::STEP] : make_float2(1.f, 0.f);
+                v[q] = cmul(sv, yv);
             }
-        __syncthreads();  // twiddle tables visible; previous LDS reads finished
-        fft2_fwd<G>(v, lds, twy, twz);
+        }
+        // rows of this wave were last read by this wave (previous inverse); the column
+        // phases of the previous coil ended at the barrier inside fft2_inv
+        fft2_fwd<G>(v, lds, twy, twz, tidc);
 #pragma unroll
-        for (int i = 0; i < Q / RL; ++i)
+        for (int i = 0; i < DL::NB; ++i) {
+            const float2* dh_p = dh_t + ((x0 + el.pb[i]) * a.nc + c) * nst;
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
-                int pb, z, y;
-                pos_out<G>(tid, i, r, pb, z, y);
                 const int q = i * RL + r;
-                const int s = a.sidx[(size_t)t * P + z * NY + y];
+                int s;
+                if constexpr (G::KEEPY) s = sid[q];
+                else s = (el.pb[i] < nvalid) ? a.sidx[t * P + el.rel[i] + r * DL::STEP] : -1;
                 float2 rv = make_float2(0.f, 0.f);
-                if (s >= 0 && x0 + pb < a.nx) {
-                    const float2 d = a.dh[off + ((size_t)(x0 + pb) * a.nc + c) * nst + s];
+                if (s >= 0) {
+                    const float2 d = dh_p[s];
                     rv = make_float2(fmaf(v[q].x, a.inv_p, -d.x), fmaf(v[q].y, a.inv_p, -d.y));
                     res2 += (double)rv.x * rv.x + (double)rv.y * rv.y;
                 }
                 v[q] = rv;
             }
-        fft2_inv<G>(v, lds, twy, twz);
+        }
+        fft2_inv<G>(v, lds, twy, twz, tidc);
 #pragma unroll
-        for (int i = 0; i < Q / R0; ++i)
+        for (int i = 0; i < D0::NB; ++i) {
+            const bool ok = sc && e0.pb[i] < nvalid;
+            const int o = e0.pb[i] * P + e0.rel[i];
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
-                int pb, z, y;
-                pos_in<G>(tid, i, r, pb, z, y);
                 const int q = i * R0 + r;
-                float2 sv = make_float2(1.f, 0.f);
-                if (sc && x0 + pb < a.nx) sv = sc[(size_t)(x0 + pb) * P + z * NY + y];
+                const float2 sv = ok ? sc[o + r * D0::STEP] : make_float2(1.f, 0.f);
                 acc[q] = cadd(acc[q], cmulc(v[q], sv));
             }
+        }
     }
 #pragma unroll
-    for (int i = 0; i < Q / R0; ++i)
+    for (int i = 0; i < D0::NB; ++i) {
+        if (d0.pb[i] < nvalid) {
+            const int o = plane0 + d0.pb[i] * P + d0.rel[i];
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            int pb, z, y;
-            pos_in<G>(tid, i, r, pb, z, y);
-            const int q = i * R0 + r;
-            if (x0 + pb < a.nx) {
-                const size_t gi = frame + (size_t)(x0 + pb) * P + z * NY + y;
+            for (int r = 0; r < R0; ++r) {
+                const int q = i * R0 + r;
+                const int gi = o + r * D0::STEP;
                 const float2 l = has_y ? a.L[gi] : make_float2(0.f, 0.f);
                 a.C[gi] = csub(l, acc[q]);
             }
         }
+    }
     const double s0 = block_sum<G::T>(res2, red);
     double s1 = 0.0, s2 = 0.0;
     if constexpr (STATS) {
@@ -174,11 +239,11 @@ __global__ void __launch_bounds__(G::T) pls_xifft_kernel(XiArgs a) {
     // inverse transform; the plane machinery with NZ = 1 runs only y (= x here) passes
     {
         constexpr int NP = G::NPY;
-        sfor<NP>([&](auto pI) {
+        sfor<NP>([&](auto pI) __attribute__((always_inline)) {
             constexpr int p = decltype(pI)::value;
             constexpr int R = G::PY.r[p];
             constexpr int LS = plan_prod(G::PY, p);
-            fft_pass<G, 0, R, LS, true, p == 0, p == NP - 1>(v, lds, twx);
+            fft_pass<G, 0, R, LS, true, p == 0, p == NP - 1>(v, lds, twx, tid);
         });
     }
 #pragma unroll

@@ -50,22 +50,22 @@ __device__ __forceinline__ void dft(float2* x) {
         constexpr int A = (R % 4 == 0) ? 4 : ((R % 2 == 0) ? 2 : 3);
         constexpr int B = R / A;
         float2 t[R];
-        sfor<B>([&](auto bI) {
+        sfor<B>([&](auto bI) __attribute__((always_inline)) {
             constexpr int b = decltype(bI)::value;
             float2 y[A];
-            sfor<A>([&](auto aI) { y[decltype(aI)::value] = x[B * decltype(aI)::value + b]; });
+            sfor<A>([&](auto aI) __attribute__((always_inline)) { y[decltype(aI)::value] = x[B * decltype(aI)::value + b]; });
             dft<A, INV>(y);
-            sfor<A>([&](auto cI) {
+            sfor<A>([&](auto cI) __attribute__((always_inline)) {
                 constexpr int c = decltype(cI)::value;
                 t[c * B + b] = ctw<b * c, R, INV>(y[c]);
             });
         });
-        sfor<A>([&](auto cI) {
+        sfor<A>([&](auto cI) __attribute__((always_inline)) {
             constexpr int c = decltype(cI)::value;
             float2 z[B];
-            sfor<B>([&](auto bI) { z[decltype(bI)::value] = t[c * B + decltype(bI)::value]; });
+            sfor<B>([&](auto bI) __attribute__((always_inline)) { z[decltype(bI)::value] = t[c * B + decltype(bI)::value]; });
             dft<B, INV>(z);
-            sfor<B>([&](auto dI) { x[c + A * decltype(dI)::value] = z[decltype(dI)::value]; });
+            sfor<B>([&](auto dI) __attribute__((always_inline)) { x[c + A * decltype(dI)::value] = z[decltype(dI)::value]; });
         });
     }
 }
@@ -79,14 +79,14 @@ struct RadixPlan {
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 
 // Factor N into radices that each divide Q (so every thread holds whole butterflies),
-// each <= 32, sorted ascending.  n = -1 when impossible.
-constexpr RadixPlan plan_axis(int N, int Q) {
+// each <= RMAX, sorted ascending.  n = -1 when impossible.
+constexpr RadixPlan plan_axis(int N, int Q, int RMAX = 32) {
     RadixPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
     int rem = N;
     while (rem > 1) {
         int g = cgcd(rem, Q);
-        while (g > 32) {
-            int d = 32;
+        if (g > RMAX) {
+            int d = RMAX;
             while (d > 1 && g % d != 0) --d;
             g = d;
         }
@@ -114,79 +114,120 @@ constexpr int plan_prod(const RadixPlan& p, int upto) {
 }
 
 // ---------------------------------------------------------------- plane geometry
-template <int NY_, int NZ_, int PB_, int Q_, int PADSH_>
+template <int NY_, int NZ_, int PB_, int Q_, int PADY_, int RMAX_ = 32, int MINW_ = 1,
+          bool KEEPY_ = true>
 struct Geom {
     static constexpr int NY = NY_, NZ = NZ_, PB = PB_, Q = Q_;
+    static constexpr int MINW = MINW_;   // launch bound: minimum waves per SIMD
+    static constexpr bool KEEPY = KEEPY_; // data-consistency: keep Y in registers across coils
     static constexpr int P = NY * NZ;
     static constexpr int T = PB * P / Q;
-    // LDS address of linear plane index e = (pb * NZ + z) * NY + y: one pad element
-    // every 2^PADSH elements spreads strided Stockham accesses over the LDS banks.
-    static constexpr int PADSH = PADSH_;
-    static constexpr int LDS_ELEMS = PB * P + (PADSH > 0 ? ((PB * P) >> PADSH) : 0) + 1;
-    static constexpr RadixPlan PY = plan_axis(NY, Q);
-    static constexpr RadixPlan PZ = plan_axis(NZ, Q);
+    // LDS layout: plane pb, row z, column y at pb * PS + z * LDY + y.  Every access of a
+    // pass is a per-butterfly base plus a compile-time offset (ds_read/ds_write immediate).
+    static constexpr int LDY = NY + PADY_;
+    static constexpr int PS = LDY * NZ;
+    static constexpr int LDS_ELEMS = PS * PB;
+    static constexpr RadixPlan PY = plan_axis(NY, Q, RMAX_);
+    static constexpr RadixPlan PZ = plan_axis(NZ, Q, RMAX_);
     static constexpr int NPY = PY.n;
     static constexpr int NPZ = PZ.n;
     static_assert(PB * P % Q == 0, "Q must divide the block's points");
     static_assert(T % 64 == 0 && T <= 1024, "threads must be whole waves");
     static_assert(NPY >= 1 && NPZ >= 0, "axis not factorable with this Q");
-    __device__ static __forceinline__ int lds_addr(int e) {
-        if constexpr (PADSH > 0) return e + (e >> PADSH);
-        else return e;
+};
+
+// Wave-local LDS ordering.  The LDS executes the instructions of one wave in issue order,
+// so a read issued after a write of the same wave sees it, and a write issued after a read
+// cannot overtake it; only the compiler must be kept from moving LDS accesses across.
+#define PLS_WAVE_SYNC() asm volatile("" ::: "memory")
+
+// A copy of x the compiler cannot see through: address arithmetic derived from it is
+// recomputed where it is used instead of being hoisted out of a loop (and pinning
+// registers for its whole duration).
+__device__ __forceinline__ int opaque(int x) {
+    int y;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+
+// Line ownership of a pass of radix R along axis AX (0 = y, 1 = z).  The lines of the axis
+// (PB * NZ rows for y, PB * NY columns for z) are split evenly over the waves of the
+// block, so every exchange between two passes of the same axis stays inside one wave;
+// only the change of axis needs a block barrier.  Butterfly i of a thread is butterfly
+// k = lane + 64 i of its wave: along y consecutive lanes take consecutive butterflies of
+// a row, along z consecutive lanes take consecutive columns.
+template <class G, int AX, int R>
+struct PassMap {
+    static constexpr int N = (AX == 0) ? G::NY : G::NZ;
+    static constexpr int JN = N / R;
+    static constexpr int NB = G::Q / R;
+    static constexpr int LINES = (AX == 0) ? G::PB * G::NZ : G::PB * G::NY;
+    static constexpr int W = G::T / 64;
+    static constexpr int LPW = LINES / W;
+    static constexpr int STRIDE = (AX == 0) ? 1 : G::LDY;
+    static_assert(LINES % W == 0 && LPW * JN == 64 * NB, "lines do not split over waves");
+    __device__ static __forceinline__ void map(int tid, int i, int& line, int& j) {
+        const int k = (tid & 63) + 64 * i;
+        const int w = tid >> 6;
+        if constexpr (AX == 0) {
+            line = w * LPW + k / JN;
+            j = k % JN;
+        } else {
+            line = w * LPW + k % LPW;
+            j = k / LPW;
+        }
+    }
+    // LDS offset of point 0 of a line
+    __device__ static __forceinline__ int lbase(int line) {
+        if constexpr (AX == 0) return (line / G::NZ) * G::PS + (line % G::NZ) * G::LDY;
+        else return (line / G::NY) * G::PS + (line % G::NY);
+    }
+    // (plane, z, y) of element (i, r) in the distribution a first pass of this radix reads
+    __device__ static __forceinline__ void pos(int tid, int i, int r, int& pb, int& z, int& y) {
+        int line, j;
+        map(tid, i, line, j);
+        if constexpr (AX == 0) {
+            pb = line / G::NZ;
+            z = line % G::NZ;
+            y = j + r * JN;
+        } else {
+            pb = line / G::NY;
+            y = line % G::NY;
+            z = j + r * JN;
+        }
     }
 };
 
 // Position (plane, z, y) of element (i, r) of a thread's registers in the distribution
-// that a first pass of radix R along axis AX (0 = y, 1 = z) reads.
+// that a first pass of radix R along axis AX reads.
 template <class G, int AX, int R>
 __device__ __forceinline__ void pass_pos(int tid, int i, int r, int& pb, int& z, int& y) {
-    const int b = tid + i * G::T;
-    if constexpr (AX == 0) {
-        constexpr int JN = G::NY / R;
-        const int j = b % JN;
-        const int line = b / JN;
-        z = line % G::NZ;
-        pb = line / G::NZ;
-        y = j + r * JN;
-    } else {
-        constexpr int JN = G::NZ / R;
-        y = b % G::NY;
-        const int rest = b / G::NY;
-        const int j = rest % JN;
-        pb = rest / JN;
-        z = j + r * JN;
-    }
+    PassMap<G, AX, R>::pos(tid, i, r, pb, z, y);
 }
 
 // One Stockham pass.  tw = exp(-2 pi i m / N), m in [0, N), for this axis' length N.
+// Reads follow a block barrier or a wave-local sync of the previous pass; writes are
+// followed by a wave-local sync (callers add the block barrier at a change of axis).
 template <class G, int AX, int R, int LS, bool INV, bool IN_REG, bool OUT_REG>
-__device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const float2* tw) {
-    constexpr int N = (AX == 0) ? G::NY : G::NZ;
-    constexpr int JN = N / R;
-    constexpr int NB = G::Q / R;
-    constexpr int STRIDE = (AX == 0) ? 1 : G::NY;
+__device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const float2* tw,
+                                         int tid) {
+    using M = PassMap<G, AX, R>;
+    constexpr int N = M::N, JN = M::JN, NB = M::NB, STRIDE = M::STRIDE;
     static_assert(G::Q % R == 0 && N % (R * LS) == 0, "bad pass");
-    const int tid = threadIdx.x;
     int base[NB], jj[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const int b = tid + i * G::T;
-        if constexpr (AX == 0) {
-            jj[i] = b % JN;
-            base[i] = (b / JN) * G::NY;           // line = pb * NZ + z
-        } else {
-            const int y = b % G::NY;
-            const int rest = b / G::NY;
-            jj[i] = rest % JN;
-            base[i] = (rest / JN) * G::P + y;
-        }
+        int line;
+        M::map(tid, i, line, jj[i]);
+        base[i] = M::lbase(line);
     }
     if constexpr (!IN_REG) {
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
+        for (int i = 0; i < NB; ++i) {
+            const float2* src = lds + base[i] + jj[i] * STRIDE;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                v[i * R + r] = lds[G::lds_addr(base[i] + (jj[i] + r * JN) * STRIDE)];
+            for (int r = 0; r < R; ++r) v[i * R + r] = src[r * JN * STRIDE];
+        }
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -203,38 +244,40 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const f
         dft<R, INV>(&v[i * R]);
     }
     if constexpr (!OUT_REG) {
-        __syncthreads();
+        PLS_WAVE_SYNC();   // this wave's reads of the lines it is about to overwrite are done
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int j = jj[i];
-            const int o = (j / LS) * LS * R + (j % LS);
+            float2* dst = lds + base[i] + ((j / LS) * LS * R + (j % LS)) * STRIDE;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[G::lds_addr(base[i] + (o + r * LS) * STRIDE)] = v[i * R + r];
+            for (int r = 0; r < R; ++r) dst[r * LS * STRIDE] = v[i * R + r];
         }
-        __syncthreads();
+        PLS_WAVE_SYNC();
     }
 }
 
 // Forward 2D transform: y passes (ascending radices) then z passes (ascending).
 // Input: registers in the distribution of the first y pass; output: registers in the
 // distribution of a first pass of radix (last z radix) along z (or y when NZ == 1).
+// The caller guarantees that no other wave still reads this block's rows (LDS).
 template <class G>
 __device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const float2* twy,
-                                         const float2* twz) {
+                                         const float2* twz, int tid) {
     constexpr int NPY = G::NPY, NPZ = G::NPZ, NP = NPY + NPZ;
-    sfor<NP>([&](auto pI) {
+    sfor<NP>([&](auto pI) __attribute__((always_inline)) {
         constexpr int p = decltype(pI)::value;
         constexpr bool IN_REG = (p == 0);
         constexpr bool OUT_REG = (p == NP - 1);
         if constexpr (p < NPY) {
             constexpr int R = G::PY.r[p];
             constexpr int LS = plan_prod(G::PY, p);
-            fft_pass<G, 0, R, LS, false, IN_REG, OUT_REG>(v, lds, twy);
+            fft_pass<G, 0, R, LS, false, IN_REG, OUT_REG>(v, lds, twy, tid);
         } else {
             constexpr int q = p - NPY;
             constexpr int R = G::PZ.r[q];
             constexpr int LS = plan_prod(G::PZ, q);
-            fft_pass<G, 1, R, LS, false, IN_REG, OUT_REG>(v, lds, twz);
+            if constexpr (q == 0) __syncthreads();   // rows -> columns
+            fft_pass<G, 1, R, LS, false, IN_REG, OUT_REG>(v, lds, twz, tid);
         }
     });
 }
@@ -244,9 +287,9 @@ __device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const f
 // distribution fft2_fwd read.
 template <class G>
 __device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const float2* twy,
-                                         const float2* twz) {
+                                         const float2* twz, int tid) {
     constexpr int NPY = G::NPY, NPZ = G::NPZ, NP = NPY + NPZ;
-    sfor<NP>([&](auto pI) {
+    sfor<NP>([&](auto pI) __attribute__((always_inline)) {
         constexpr int p = decltype(pI)::value;
         constexpr bool IN_REG = (p == 0);
         constexpr bool OUT_REG = (p == NP - 1);
@@ -258,7 +301,7 @@ __device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const f
                 for (int u = NPZ - 1; u > idx; --u) s *= G::PZ.r[u];
                 return s;
             }();
-            fft_pass<G, 1, R, LS, true, IN_REG, OUT_REG>(v, lds, twz);
+            fft_pass<G, 1, R, LS, true, IN_REG, OUT_REG>(v, lds, twz, tid);
         } else {
             constexpr int q = p - NPZ;
             constexpr int idx = NPY - 1 - q;
@@ -268,7 +311,8 @@ __device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const f
                 for (int u = NPY - 1; u > idx; --u) s *= G::PY.r[u];
                 return s;
             }();
-            fft_pass<G, 0, R, LS, true, IN_REG, OUT_REG>(v, lds, twy);
+            if constexpr (q == 0 && NPZ > 0) __syncthreads();   // columns -> rows
+            fft_pass<G, 0, R, LS, true, IN_REG, OUT_REG>(v, lds, twy, tid);
         }
     });
 }

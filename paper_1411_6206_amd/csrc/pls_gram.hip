@@ -130,18 +130,35 @@ int launch_gram(int mode, const GramArgs& a0, hipStream_t s) {
     return grid;
 }
 
-// out[e] = sum_b part[b * entries + e], b ascending
+// out[e] = sum over the per-block partials, in a fixed order: each of 8 row groups of a
+// block sums the partials b = g, g + 8, g + 16, ... of 32 entries, then the 8 group sums
+// are added in group order.
 __global__ void __launch_bounds__(256) pls_gram_reduce_kernel(const double* part, int blocks,
                                                               int entries, double* out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= entries) return;
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += part[(size_t)b * entries + e];
-    out[e] = s;
+    __shared__ double red[8][32];
+    const int le = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + le;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < entries) {
+        int b = g;
+        for (; b + 8 < blocks; b += 16) {
+            s0 += part[(size_t)b * entries + e];
+            s1 += part[(size_t)(b + 8) * entries + e];
+        }
+        if (b < blocks) s0 += part[(size_t)b * entries + e];
+    }
+    red[g][le] = s0 + s1;
+    __syncthreads();
+    if (g == 0 && e < entries) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += red[k][le];
+        out[e] = t;
+    }
 }
 
 void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(pls_gram_reduce_kernel, dim3((entries + 255) / 256), dim3(256), 0, s, part,
+    hipLaunchKernelGGL(pls_gram_reduce_kernel, dim3((entries + 31) / 32), dim3(256), 0, s, part,
                        blocks, entries, out);
 }
 
@@ -252,7 +269,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
         }
         off = block_sum<256>(off, red);
         dg = block_sum<256>(dg, red);
-        if (!(off > 1e-28 * dg)) break;   // also stops on NaN
+        if (!(off > 1e-26 * dg)) break;   // off-diagonal below 1e-13 of the diagonal; NaN stops
         for (int r = 0; r < ne - 1; ++r) {
             if (tid < half) {
                 int p, q;

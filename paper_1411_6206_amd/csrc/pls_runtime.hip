@@ -301,8 +301,11 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     da.inv_p = 1.0f / (float)sz.P;
     const int dcb = pls::launch_dc(d.ny, d.nz, stats, da, s);
     mark(6);
-    pls::StatsArgs st{h->dc_part, dcb, h->sp_part, spb, rec, (double)sz.P, h->params.lambda_S};
-    pls::launch_stats(st, s);
+    // statistics are reduced only where they are read: the last iteration of a chunk
+    if (stats) {
+        pls::StatsArgs st{h->dc_part, dcb, h->sp_part, spb, rec, (double)sz.P, h->params.lambda_S};
+        pls::launch_stats(st, s);
+    }
     mark(7);
     h->cur = q;
 }
@@ -377,6 +380,8 @@ void fill_stats(prior_ls_handle* h, prior_ls_stats* st, bool converged, double m
     st->converged = converged ? 1 : 0;
     st->nonfinite = r[7] != 0.0;
     st->sigma_count = h->d.nt;
+    st->eig_sweeps = (int32_t)r[6];
+    st->reserved = 0;
     st->rel_change = r[2] > 0 ? std::sqrt(r[1] / r[2]) : INFINITY;
     st->resid_norm = std::sqrt(std::max(r[0], 0.0));
     st->nuclear_norm = r[4];

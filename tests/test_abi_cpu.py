@@ -37,7 +37,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(pls.Params) == 56
     assert C.sizeof(pls.Inputs) == 56
     assert C.sizeof(pls.Outputs) == 32
-    assert C.sizeof(pls.Stats) == 8 + 16 + 6 * 8 + 32 * 8 + 8
+    assert C.sizeof(pls.Stats) == 8 + 24 + 6 * 8 + 32 * 8 + 8
 
 
 def _create(**kw):
