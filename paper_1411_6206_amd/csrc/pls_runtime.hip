@@ -136,7 +136,9 @@ struct prior_ls_handle {
     prior_ls_dims d{};
     hipStream_t ustream = nullptr;   // the caller's stream
     hipStream_t stream = nullptr;    // the handle's own stream (capturable)
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t side = nullptr;      // second stream: the sparse update runs beside the
+                                     // Gram / eigensolve / back-projection chain
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     Sizes sz{};
     uint64_t owned = 0;
@@ -230,38 +232,23 @@ bool is_device_ptr(const void* p) {
 }
 
 // one iteration of Algorithm 1 on the resident state (see the schedule in the header)
-// ev (optional): 8 timing events recorded around the 7 launches of the iteration
+// One iteration of Algorithm 1 on the resident state.  Steps (1)-(2) (Gram, eigensolve,
+// back-projection) run on the main stream while step (3) (sparse update) runs on the side
+// stream; both only read C = M - S, S and L of the previous iterate, and step (4) (data
+// consistency) joins them.  ev (optional): 2 timing events around each of the 7 kernels,
+// recorded on the stream the kernel runs on.
 void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev = nullptr) {
     const prior_ls_dims& d = h->d;
     const Sizes& sz = h->sz;
-    hipStream_t s = h->stream;
+    hipStream_t s = h->stream, s2 = h->side;
     const int p = h->cur, q = 1 - p;
     double* rec = h->stats_d + (size_t)slot * kStatRec;
-    auto mark = [&](int k) {
-        if (ev) PLS_HIP(hipEventRecord(ev[k], s));
+    auto mark = [&](int k, hipStream_t st) {
+        if (ev) PLS_HIP(hipEventRecord(ev[k], st));
     };
-    // steps (1)-(2): Gram, eigensolve, W
-    mark(0);
-    pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0};
-    const int gb = pls::launch_gram(d.gram_mode, ga, s);
-    mark(1);
-    pls::launch_gram_reduce(h->gpart, gb, sz.gentries, h->gred, s);
-    mark(2);
-    pls::EigArgs ea{};
-    ea.gram = h->gred;
-    ea.V = h->V;
-    ea.warm = 1;
-    ea.Wop = h->Wop;
-    ea.Wd = h->Wd;
-    ea.sigma_prev = h->sigma_prev;
-    ea.stat = rec;
-    ea.nt = d.nt;
-    ea.lambda_L = h->params.lambda_L;
-    ea.lambda_p = h->params.lambda_p;
-    ea.relative = h->params.lambda_L_relative;
-    pls::launch_eig(ea, s);
-    mark(3);
-    // step (3): S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)
+    PLS_HIP(hipEventRecord(h->ev_fork, s));
+    PLS_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
+    // step (3): S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)   [side stream]
     pls::SparseArgs sa{};
     sa.C = h->C;
     sa.S = h->S[p];
@@ -274,13 +261,39 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     sa.nz = d.nz;
     sa.nt = d.nt;
     sa.lambda_S = (float)h->params.lambda_S;
-    const int spb = pls::launch_sparse(d.wavelet_levels, sa, s);
-    mark(4);
-    // steps (1)-(2): L_k = C W
+    mark(6, s2);
+    const int spb = pls::launch_sparse(d.wavelet_levels, sa, s2);
+    mark(7, s2);
+    PLS_HIP(hipEventRecord(h->ev_join, s2));
+    // steps (1)-(2): Gram, eigensolve, W, L_k = C W   [main stream]
+    mark(0, s);
+    pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0};
+    const int gb = pls::launch_gram(d.gram_mode, ga, s);
+    mark(1, s);
+    mark(2, s);
+    pls::launch_gram_reduce(h->gpart, gb, sz.gentries, h->gred, s);
+    mark(3, s);
+    pls::EigArgs ea{};
+    ea.gram = h->gred;
+    ea.V = h->V;
+    ea.warm = 1;
+    ea.Wop = h->Wop;
+    ea.Wd = h->Wd;
+    ea.sigma_prev = h->sigma_prev;
+    ea.stat = rec;
+    ea.nt = d.nt;
+    ea.lambda_L = h->params.lambda_L;
+    ea.lambda_p = h->params.lambda_p;
+    ea.relative = h->params.lambda_L_relative;
+    mark(4, s);
+    pls::launch_eig(ea, s);
+    mark(5, s);
     pls::BpArgs ba{h->C, h->L[q], h->Wop, (int)sz.N, d.nt};
+    mark(8, s);
     pls::launch_bp(ba, s);
-    mark(5);
-    // step (4): data consistency -> C = M_k - S_k
+    mark(9, s);
+    // step (4): data consistency -> C = M_k - S_k   (joins the sparse update)
+    PLS_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
     DcArgs da{};
     da.L = h->L[q];
     da.S = h->S[q];
@@ -299,14 +312,16 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     da.nt = d.nt;
     da.nc = d.nc;
     da.inv_p = 1.0f / (float)sz.P;
+    mark(10, s);
     const int dcb = pls::launch_dc(d.ny, d.nz, stats, da, s);
-    mark(6);
+    mark(11, s);
     // statistics are reduced only where they are read: the last iteration of a chunk
+    mark(12, s);
     if (stats) {
         pls::StatsArgs st{h->dc_part, dcb, h->sp_part, spb, rec, (double)sz.P, h->params.lambda_S};
         pls::launch_stats(st, s);
     }
-    mark(7);
+    mark(13, s);
     h->cur = q;
 }
 
@@ -605,8 +620,11 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
     const int r = guarded(h, [&]() -> int {
         PLS_HIP(hipGetDevice(&h->device));
         PLS_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        PLS_HIP(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
         PLS_HIP(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         const prior_ls_dims& d = h->d;
         h->C = h->alloc<float2>(sz.I * sizeof(float2));
         for (int k = 0; k < 2; ++k) {
@@ -655,8 +673,12 @@ void prior_ls_destroy(prior_ls_handle* h) {
     h->clear_graphs();
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->stats_h) (void)hipHostFree(h->stats_h);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
@@ -734,11 +756,12 @@ int prior_ls_step_timed(prior_ls_handle* h, int32_t n_iter, double* kernel_ms,
     if (!kernel_ms) return fail(h, PRIOR_LS_EINVAL, "kernel_ms is NULL");
     if (stats && stats->struct_size != sizeof(prior_ls_stats))
         return fail(h, PRIOR_LS_EINVAL, "stats.struct_size mismatch");
-    std::vector<hipEvent_t> ev((size_t)n_iter * 8, nullptr);
+    constexpr int kEv = 14;
+    std::vector<hipEvent_t> ev((size_t)n_iter * kEv, nullptr);
     const int r = guarded(h, [&]() -> int {
         for (auto& e : ev) PLS_HIP(hipEventCreate(&e));
         enter(h);
-        for (int j = 0; j < n_iter; ++j) enqueue_iteration(h, j, j == n_iter - 1, &ev[(size_t)j * 8]);
+        for (int j = 0; j < n_iter; ++j) enqueue_iteration(h, j, j == n_iter - 1, &ev[(size_t)j * kEv]);
         PLS_HIP(hipGetLastError());
         PLS_HIP(hipMemcpyAsync(h->stats_h, h->stats_d + (size_t)(n_iter - 1) * kStatRec,
                                kStatRec * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -746,11 +769,14 @@ int prior_ls_step_timed(prior_ls_handle* h, int32_t n_iter, double* kernel_ms,
         PLS_HIP(hipStreamSynchronize(h->stream));
         std::memcpy(h->last, h->stats_h, sizeof(h->last));
         h->iters += n_iter;
+        // event pair of each kernel in the ABI order gram, reduce, eig, sparse, bp, dc, stats
+        const int pair[PRIOR_LS_NKERNELS] = {0, 2, 4, 6, 8, 10, 12};
         for (int k = 0; k < PRIOR_LS_NKERNELS; ++k) {
             double tot = 0.0;
             for (int j = 0; j < n_iter; ++j) {
                 float ms = 0.f;
-                PLS_HIP(hipEventElapsedTime(&ms, ev[(size_t)j * 8 + k], ev[(size_t)j * 8 + k + 1]));
+                PLS_HIP(hipEventElapsedTime(&ms, ev[(size_t)j * kEv + pair[k]],
+                                            ev[(size_t)j * kEv + pair[k] + 1]));
                 tot += ms;
             }
             kernel_ms[k] = tot;
