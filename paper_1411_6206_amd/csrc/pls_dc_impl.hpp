@@ -54,78 +54,116 @@ struct Dist {
 
 template <class G, bool STATS>
 __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
-    constexpr int Q = G::Q, P = G::P, NY = G::NY, NZ = G::NZ, PB = G::PB;
+    constexpr int Q = G::Q, P = G::P, NY = G::NY, NZ = G::NZ, PB = G::PB, T = G::T;
     constexpr int R0 = radix_in<G>();
     constexpr int RL = radix_out<G>();
     constexpr int AXL = G::NPZ > 0 ? 1 : 0;
+    // staged compact data of one coil (all planes of the batch), double-buffered
+    constexpr int NST = (PB * P < 1024) ? PB * P : 1024;
+    constexpr int NSTT = (NST + T - 1) / T;   // staged entries per thread
     using D0 = Dist<G, 0, R0>;
     using DL = Dist<G, AXL, RL>;
     __shared__ float2 lds[G::LDS_ELEMS];
     __shared__ float2 twy[NY];
     __shared__ float2 twz[NZ];
-    __shared__ double red[G::T / kWave];
+    __shared__ int16_t smap[P];               // sample index of (kz, ky) in this frame, or -1
+    __shared__ float2 dhs[2][NST];
+    __shared__ double red[T / kWave];
     const int tid = threadIdx.x;
-    for (int m = tid; m < NY; m += G::T) twy[m] = a.twy[m];
-    for (int m = tid; m < NZ; m += G::T) twz[m] = a.twz[m];
+    for (int m = tid; m < NY; m += T) twy[m] = a.twy[m];
+    for (int m = tid; m < NZ; m += T) twz[m] = a.twz[m];
 
-    const int t = blockIdx.x % a.nt;
-    const int x0 = (blockIdx.x / a.nt) * PB;
-    const int nvalid = a.nx - x0;              // planes of this batch that exist
+    // Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD works on a
+    // contiguous range of (x, t) planes and the coil maps of an x plane stay in its L2.
+    const int nb = gridDim.x;
+    const int lb = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+    const int t = lb % a.nt;
+    const int x0 = (lb / a.nt) * PB;
+    const int nvalid = a.nx - x0;              // planes of this batch that exist (>= 1)
+    const int pbv = nvalid < PB ? nvalid : PB;
     const int plane0 = (t * a.nx + x0) * P;    // element offset of plane (t, x0)
+    // Loads are issued unconditionally from always-valid addresses and blended with uniform
+    // selects, so the compiler can issue a whole group before waiting: absent operands read
+    // a valid stand-in array whose value is then discarded by a select (never multiplied,
+    // so whatever the stand-in holds cannot leak in).
     const bool has_y = (a.L != nullptr);
+    const bool has_s = has_y && (a.S != nullptr);
+    const bool has_sens = (a.sens != nullptr);
+    const float2* Lp = has_y ? a.L : a.C;
+    const float2* Sp = has_s ? a.S : Lp;
     const D0 d0(tid);
-    const DL dl(tid);
+    const int nst = a.ns[t];
+    const float2* dh_t = a.dh + a.dh_off[t];
+    const int16_t* sid_t = a.sidx + t * P;
+    for (int m = tid; m < P; m += T) smap[m] = sid_t[m];
+    // the compact data of coil c for the batch: entry pb * nst + s, contiguous in memory when
+    // PB == 1 (index (x * nc + c) * nst + s)
+    const bool staged = pbv * nst <= NST;
+    auto stage_load = [&](int c, float2 (&buf)[NSTT]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < NSTT; ++k) {
+            const int e0 = tid + k * T;
+            const bool in = staged && e0 < pbv * nst;
+            const int e = in ? e0 : 0;                 // unused entries read a valid address
+            const int pb = nst > 0 ? e / nst : 0;
+            const int s = e - pb * nst;
+            const float2 d = dh_t[((x0 + pb) * a.nc + c) * nst + s];
+            buf[k] = in ? d : make_float2(0.f, 0.f);
+        }
+    };
+    float2 dnext[NSTT];
+    stage_load(0, dnext);
 
     float2 Y[G::KEEPY ? Q : 1], acc[Q], v[Q];
     double dy2 = 0.0, y2 = 0.0;
 #pragma unroll
     for (int i = 0; i < D0::NB; ++i) {
-        const bool ok = has_y && d0.pb[i] < nvalid;
-        const int o = plane0 + d0.pb[i] * P + d0.rel[i];
+        const int pbc = min(d0.pb[i], nvalid - 1);
+        const int o = plane0 + pbc * P + d0.rel[i];
+        const bool ok = d0.pb[i] < nvalid;
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int q = i * R0 + r;
+            const int gi = o + r * D0::STEP;
             if constexpr (G::KEEPY || STATS) {
-                float2 yv = make_float2(0.f, 0.f);
-                if (ok) {
-                    const int gi = o + r * D0::STEP;
-                    yv = a.S ? cadd(a.L[gi], a.S[gi]) : a.L[gi];
-                    if constexpr (STATS) {
-                        const float2 yo = cadd(a.Lold[gi], a.Sold[gi]);
-                        const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
-                        dy2 += dx * dx + dyy * dyy;
-                        y2 += (double)yo.x * yo.x + (double)yo.y * yo.y;
-                    }
+                const float2 l = Lp[gi], sv = Sp[gi];
+                float2 yv = has_s ? cadd(l, sv) : l;
+                if (!has_y) yv = make_float2(0.f, 0.f);
+                if constexpr (STATS) {
+                    const float2 lo = a.Lold[gi], so = a.Sold[gi];
+                    const float2 yo = cadd(lo, so);
+                    const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
+                    const double w = ok ? 1.0 : 0.0;
+                    dy2 += w * (dx * dx + dyy * dyy);
+                    y2 += w * ((double)yo.x * yo.x + (double)yo.y * yo.y);
                 }
                 if constexpr (G::KEEPY) Y[q] = yv;
             }
             acc[q] = make_float2(0.f, 0.f);
         }
     }
-    // sample index of every element of the post-transform distribution (same for all coils)
-    int16_t sid[G::KEEPY ? Q : 1];
-    if constexpr (G::KEEPY) {
-#pragma unroll
-        for (int i = 0; i < DL::NB; ++i)
-#pragma unroll
-            for (int r = 0; r < RL; ++r)
-                sid[i * RL + r] = (dl.pb[i] < nvalid) ? a.sidx[t * P + dl.rel[i] + r * DL::STEP]
-                                                      : (int16_t)-1;
-    }
 
-    const int nst = a.ns[t];
-    const float2* dh_t = a.dh + a.dh_off[t];
     double res2 = 0.0;
-    __syncthreads();  // twiddle tables visible
+    __syncthreads();  // twiddle tables and sample map visible
     for (int c = 0; c < a.nc; ++c) {
         const int tidc = opaque(tid);
         const D0 e0(tidc);
         const DL el(tidc);
-        const float2* sc = a.sens ? a.sens + (c * a.nx + x0) * P : nullptr;
+        const int buf = c & 1;
+        // stage coil c's compact data (loaded one coil ahead) and fetch coil c + 1's; the
+        // buffer being written was last read two coils ago, before this coil's barriers
+#pragma unroll
+        for (int k = 0; k < NSTT; ++k) {
+            const int e = tidc + k * T;
+            if (e < NST) dhs[buf][e] = dnext[k];
+        }
+        if constexpr (G::NPZ == 0) __syncthreads();   // no block barrier inside the transform
+        if (c + 1 < a.nc) stage_load(c + 1, dnext);
+        const float2* sc = has_sens ? a.sens + (c * a.nx + x0) * P : Lp;
 #pragma unroll
         for (int i = 0; i < D0::NB; ++i) {
-            const bool ok = e0.pb[i] < nvalid;
-            const int o = e0.pb[i] * P + e0.rel[i];
+            const int pbc = min(e0.pb[i], nvalid - 1);
+            const int o = pbc * P + e0.rel[i];
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int q = i * R0 + r;
@@ -133,46 +171,49 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
                 if constexpr (G::KEEPY) {
                     yv = Y[q];
                 } else {
-                    yv = make_float2(0.f, 0.f);
-                    if (ok && has_y) {
-                        const int gi = plane0 + o + r * D0::STEP;
-                        yv = a.S ? cadd(a.L[gi], a.S[gi]) : a.L[gi];
-                    }
+                    const int gi = plane0 + o + r * D0::STEP;
+                    const float2 l = Lp[gi], sv = Sp[gi];
+                    yv = has_s ? cadd(l, sv) : l;
+                    if (!has_y) yv = make_float2(0.f, 0.f);
                 }
-                const float2 sv = (sc && ok) ? sc[o + r * D0::STEP] : make_float2(1.f, 0.f);
+                float2 sv = sc[o + r * D0::STEP];
+                if (!has_sens) sv = make_float2(1.f, 0.f);
                 v[q] = cmul(sv, yv);
             }
         }
         // rows of this wave were last read by this wave (previous inverse); the column
-        // phases of the previous coil ended at the barrier inside fft2_inv
+        // phases of the previous coil ended at the barrier inside fft2_inv, which also
+        // orders the staging writes above before the reads below
         fft2_fwd<G>(v, lds, twy, twz, tidc);
 #pragma unroll
         for (int i = 0; i < DL::NB; ++i) {
-            const float2* dh_p = dh_t + ((x0 + el.pb[i]) * a.nc + c) * nst;
+            const int pbc = min(el.pb[i], nvalid - 1);
+            const bool ok = el.pb[i] < nvalid;
+            const float2* dh_p = dh_t + ((x0 + pbc) * a.nc + c) * nst;
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int q = i * RL + r;
-                int s;
-                if constexpr (G::KEEPY) s = sid[q];
-                else s = (el.pb[i] < nvalid) ? a.sidx[t * P + el.rel[i] + r * DL::STEP] : -1;
-                float2 rv = make_float2(0.f, 0.f);
-                if (s >= 0) {
-                    const float2 d = dh_p[s];
-                    rv = make_float2(fmaf(v[q].x, a.inv_p, -d.x), fmaf(v[q].y, a.inv_p, -d.y));
-                    res2 += (double)rv.x * rv.x + (double)rv.y * rv.y;
-                }
+                int s = smap[el.rel[i] + r * DL::STEP];
+                s = ok ? s : -1;
+                const int sc0 = s < 0 ? 0 : s;
+                const float2 d = staged ? dhs[buf][pbc * nst + sc0] : dh_p[sc0];
+                const bool smp = s >= 0;
+                const float2 rv = make_float2(smp ? fmaf(v[q].x, a.inv_p, -d.x) : 0.f,
+                                              smp ? fmaf(v[q].y, a.inv_p, -d.y) : 0.f);
+                res2 = fma((double)rv.x, (double)rv.x, fma((double)rv.y, (double)rv.y, res2));
                 v[q] = rv;
             }
         }
         fft2_inv<G>(v, lds, twy, twz, tidc);
 #pragma unroll
         for (int i = 0; i < D0::NB; ++i) {
-            const bool ok = sc && e0.pb[i] < nvalid;
-            const int o = e0.pb[i] * P + e0.rel[i];
+            const int pbc = min(e0.pb[i], nvalid - 1);
+            const int o = pbc * P + e0.rel[i];
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int q = i * R0 + r;
-                const float2 sv = ok ? sc[o + r * D0::STEP] : make_float2(1.f, 0.f);
+                float2 sv = sc[o + r * D0::STEP];
+                if (!has_sens) sv = make_float2(1.f, 0.f);
                 acc[q] = cadd(acc[q], cmulc(v[q], sv));
             }
         }
@@ -185,7 +226,8 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
             for (int r = 0; r < R0; ++r) {
                 const int q = i * R0 + r;
                 const int gi = o + r * D0::STEP;
-                const float2 l = has_y ? a.L[gi] : make_float2(0.f, 0.f);
+                float2 l = Lp[gi];
+                if (!has_y) l = make_float2(0.f, 0.f);
                 a.C[gi] = csub(l, acc[q]);
             }
         }
@@ -197,10 +239,10 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
         s2 = block_sum<G::T>(y2, red);
     }
     if (tid == 0) {
-        a.part[blockIdx.x * 4 + 0] = s0;
-        a.part[blockIdx.x * 4 + 1] = s1;
-        a.part[blockIdx.x * 4 + 2] = s2;
-        a.part[blockIdx.x * 4 + 3] = 0.0;
+        a.part[lb * 4 + 0] = s0;
+        a.part[lb * 4 + 1] = s1;
+        a.part[lb * 4 + 2] = s2;
+        a.part[lb * 4 + 3] = 0.0;
     }
 }
 

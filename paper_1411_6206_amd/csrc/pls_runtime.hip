@@ -469,16 +469,17 @@ int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_p
     }
     loff[d.nt] = lines;
     if (total > (size_t)INT32_MAX) return fail(h, PRIOR_LS_ESHAPE, "sampled data exceed 2^31 entries");
-    if (total > h->dh_cap) {
+    if (total > h->dh_cap || !h->dh) {
         h->release(h->dh, h->dh_cap * sizeof(float2));
         h->dh = nullptr;
         h->dh_cap = 0;
         try {
-            h->dh = h->alloc<float2>(std::max<size_t>(total, 1) * sizeof(float2));
+            // +64: a clamped gather of an empty frame at the end still reads inside
+            h->dh = h->alloc<float2>((total + 64) * sizeof(float2));
         } catch (const std::bad_alloc&) {
             return fail(h, PRIOR_LS_ENOMEM, "cannot allocate the compact k-space (hbm_budget or device memory)");
         }
-        h->dh_cap = std::max<size_t>(total, 1);
+        h->dh_cap = total;
     }
     PLS_HIP(hipMemcpyAsync(h->dh_off, off.data(), d.nt * sizeof(int), hipMemcpyHostToDevice, s));
     PLS_HIP(hipMemcpyAsync(h->line_off, loff.data(), (d.nt + 1) * sizeof(int), hipMemcpyHostToDevice, s));
