@@ -190,6 +190,51 @@ __device__ __forceinline__ void rr_pair(int n, int r, int k, int& p, int& q) {
     }
 }
 
+// FP64 reciprocal and reciprocal square root: hardware approximations refined by two
+// Newton steps (each doubles the correct bits) instead of the IEEE division / sqrt
+// sequences.  Used for the Jacobi rotation parameters only.
+__device__ __forceinline__ double rcp64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * fma(-x, y, 2.0);
+    y = y * fma(-x, y, 2.0);
+    return y;
+}
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y;
+}
+
+// Jacobi rotation that zeroes the (p, q) entry of a Hermitian matrix with diagonal entries
+// app, aqq and off-diagonal entry (cr + i ci): J = [[cs, sn e], [-sn conj(e), cs]],
+// e = c / |c|, with the tangent t of the real symmetric rotation on |c|.  cs is formed as
+// 1 / sqrt(1 + t^2) and sn = t cs, so J is unitary to FP64 rounding whatever the accuracy
+// of t.
+__device__ __forceinline__ void jacobi_rot(double app, double aqq, double cr, double ci,
+                                           double& cs, double& sn, double& er, double& ei) {
+    const double ac2 = cr * cr + ci * ci;
+    cs = 1.0;
+    sn = 0.0;
+    er = 1.0;
+    ei = 0.0;
+    if (ac2 > 1e-300) {
+        const double inv_ac = rsq64(ac2);
+        const double th = (aqq - app) * 0.5 * inv_ac;
+        double t;
+        if (fabs(th) > 1e150) {
+            t = 0.5 * rcp64(th);
+        } else {
+            const double h = fma(th, th, 1.0);
+            t = (th >= 0 ? 1.0 : -1.0) * rcp64(fabs(th) + h * rsq64(h));
+        }
+        cs = rsq64(fma(t, t, 1.0));
+        sn = t * cs;
+        er = cr * inv_ac;
+        ei = ci * inv_ac;
+    }
+}
+
 __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
     __shared__ double Ar[kNMax][kNMax + 1], Ai[kNMax][kNMax + 1];
     __shared__ double Vr[kNMax][kNMax + 1], Vi[kNMax][kNMax + 1];
@@ -224,32 +269,30 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
         Vi[i][j] = vi;
     }
     __syncthreads();
-    if (a.warm) {
-        // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
-        for (int idx = tid; idx < ne * ne; idx += 256) {
-            const int i = idx / ne, j = idx % ne;
-            double sr = 0.0, si = 0.0;
-            for (int k = 0; k < ne; ++k) {
-                sr += Tr[i][k] * Vr[k][j] - Ti[i][k] * Vi[k][j];
-                si += Tr[i][k] * Vi[k][j] + Ti[i][k] * Vr[k][j];
-            }
-            Ar[i][j] = sr;
-            Ai[i][j] = si;
+    // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
+    for (int idx = tid; idx < ne * ne; idx += 256) {
+        const int i = idx / ne, j = idx % ne;
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < ne; ++k) {
+            sr += Tr[i][k] * Vr[k][j] - Ti[i][k] * Vi[k][j];
+            si += Tr[i][k] * Vi[k][j] + Ti[i][k] * Vr[k][j];
         }
-        __syncthreads();
-        for (int idx = tid; idx < ne * ne; idx += 256) {
-            const int i = idx / ne, j = idx % ne;
-            double sr = 0.0, si = 0.0;
-            for (int k = 0; k < ne; ++k) {
-                // conj(V[k][i]) * (GV)[k][j]
-                sr += Vr[k][i] * Ar[k][j] + Vi[k][i] * Ai[k][j];
-                si += Vr[k][i] * Ai[k][j] - Vi[k][i] * Ar[k][j];
-            }
-            Tr[i][j] = sr;
-            Ti[i][j] = si;
-        }
-        __syncthreads();
+        Ar[i][j] = sr;
+        Ai[i][j] = si;
     }
+    __syncthreads();
+    for (int idx = tid; idx < ne * ne; idx += 256) {
+        const int i = idx / ne, j = idx % ne;
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < ne; ++k) {
+            // conj(V[k][i]) * (GV)[k][j]
+            sr += Vr[k][i] * Ar[k][j] + Vi[k][i] * Ai[k][j];
+            si += Vr[k][i] * Ai[k][j] - Vi[k][i] * Ar[k][j];
+        }
+        Tr[i][j] = sr;
+        Ti[i][j] = si;
+    }
+    __syncthreads();
     for (int idx = tid; idx < ne * ne; idx += 256) {
         const int i = idx / ne, j = idx % ne;
         // symmetrise: A = (T + T^H) / 2
@@ -269,25 +312,14 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
         }
         off = block_sum<256>(off, red);
         dg = block_sum<256>(dg, red);
-        if (!(off > 1e-26 * dg)) break;   // off-diagonal below 1e-13 of the diagonal; NaN stops
+        // relative off-diagonal norm below 1e-10: far below the FP32 resolution of W
+        if (!(off > 1e-20 * dg)) break;   // also stops on NaN
         for (int r = 0; r < ne - 1; ++r) {
             if (tid < half) {
                 int p, q;
                 rr_pair(ne, r, tid, p, q);
-                const double app = Ar[p][p], aqq = Ar[q][q];
-                const double cr = Ar[p][q], ci = Ai[p][q];
-                const double ac = hypot(cr, ci);
-                double cs = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
-                if (ac > 1e-300) {
-                    const double th = (aqq - app) / (2.0 * ac);
-                    double t;
-                    if (fabs(th) > 1e150) t = 0.5 / th;
-                    else t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                    cs = 1.0 / sqrt(t * t + 1.0);
-                    sn = t * cs;
-                    er = cr / ac;
-                    ei = ci / ac;
-                }
+                double cs, sn, er, ei;
+                jacobi_rot(Ar[p][p], Ar[q][q], Ar[p][q], Ai[p][q], cs, sn, er, ei);
                 rc[tid] = cs;
                 rs[tid] = sn;
                 rer[tid] = er;
@@ -302,10 +334,9 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
                 const int p = rp[al], q = rq[al], u = rp[be], w = rq[be];
                 const double c1 = rc[al], s1 = rs[al], e1r = rer[al], e1i = rei[al];
                 const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
-                // J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
                 const double b00r = Ar[p][u], b00i = Ai[p][u], b01r = Ar[p][w], b01i = Ai[p][w];
                 const double b10r = Ar[q][u], b10i = Ai[q][u], b11r = Ar[q][w], b11i = Ai[q][w];
-                // X = J1^H B
+                // X = J1^H B, J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
                 const double x00r = c1 * b00r - s1 * (e1r * b10r - e1i * b10i);
                 const double x00i = c1 * b00i - s1 * (e1r * b10i + e1i * b10r);
                 const double x01r = c1 * b01r - s1 * (e1r * b11r - e1i * b11i);
@@ -314,8 +345,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
                 const double x10i = s1 * (e1r * b00i - e1i * b00r) + c1 * b10i;
                 const double x11r = s1 * (e1r * b01r + e1i * b01i) + c1 * b11r;
                 const double x11i = s1 * (e1r * b01i - e1i * b01r) + c1 * b11i;
-                // Y = X J2, J2 = [[c2, s2 e2], [-s2 conj(e2), c2]]
-                // Y[:,0] = X[:,0] c2 - X[:,1] s2 conj(e2);  Y[:,1] = X[:,0] s2 e2 + X[:,1] c2
+                // Y = X J2: Y[:,0] = X[:,0] c2 - X[:,1] s2 conj(e2); Y[:,1] = X[:,0] s2 e2 + X[:,1] c2
                 double y00r = c2 * x00r - s2 * (x01r * e2r + x01i * e2i);
                 double y00i = c2 * x00i - s2 * (x01i * e2r - x01r * e2i);
                 double y10r = c2 * x10r - s2 * (x11r * e2r + x11i * e2i);
@@ -347,9 +377,10 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
             __syncthreads();
         }
     }
+    double (*Acur)[kNMax + 1] = Ar;
 
     // spectrum, descending ranks (ties broken by index), thresholds
-    if (tid < n) sig[tid] = sqrt(fmax(Ar[tid][tid], 0.0));
+    if (tid < n) sig[tid] = sqrt(fmax(Acur[tid][tid], 0.0));
     __syncthreads();
     if (tid < n) {
         int rk = 0;
