@@ -9,6 +9,7 @@
 // B = Im C).  Only the tiles on and above the diagonal are formed.
 #include "pls_common.hpp"
 #include "pls_kernels.hpp"
+#include "prior_ls.h"
 
 namespace pls {
 
@@ -24,8 +25,54 @@ int gram_tiles(int nt) { return nt <= 16 ? npair<1>() : npair<2>(); }
 
 int gram_blocks(int N) {
     int vpb = (N + kGramBlocks - 1) / kGramBlocks;
-    vpb = (vpb + 63) / 64 * 64;
+    vpb = (vpb + 127) / 128 * 128;
     return (N + vpb - 1) / vpb;
+}
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Fixed-order sum of the 4 waves' FP32 16x16 accumulators, (w0 + w2) + (w1 + w3) in FP64,
+// stored as FP64 partial tiles; v_mfma_f32_16x16xK output: register r of a lane holds row
+// 4 (lane / 16) + r, column lane % 16.
+template <int NP, bool UNUSED>
+__device__ __forceinline__ void gram_block_store(const f4 (&acc)[NP], double (*red)[NP * 256],
+                                                 double* part, int lane, int wave) {
+    const int slot = lane;
+    double d[NP][4];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[p][r] = (double)acc[p][r];
+    if (wave >= 2) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[wave - 2][p * 256 + r * 64 + slot] = d[p][r];
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[p][r] += red[wave][p * 256 + r * 64 + slot];
+    }
+    __syncthreads();
+    if (wave == 1) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[0][p * 256 + r * 64 + slot] = d[p][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double* out = part + (size_t)blockIdx.x * NP * 256;
+        const int g = lane >> 4, i16 = lane & 15;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[p * 256 + (4 * g + r) * 16 + i16] = d[p][r] + red[0][p * 256 + r * 64 + slot];
+    }
 }
 
 // ---------------------------------------------------------------- FP64 MFMA Gram
@@ -116,17 +163,135 @@ __global__ void __launch_bounds__(256) pls_gram_f64_kernel(GramArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- FP32 MFMA Gram
+// Same lane mapping as the FP64 kernel with v_mfma_f32_16x16x4f32; FP32 accumulation within
+// a wave (a few hundred voxels per entry), FP64 across waves and blocks.
+template <int NB>
+__global__ void __launch_bounds__(256) pls_gram_f32_kernel(GramArgs a) {
+    constexpr int NT4 = 2 * NB;
+    constexpr int NP = npair<NB>();
+    __shared__ double red[2][NP * 256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, g = lane >> 4;
+    const size_t vb = (size_t)blockIdx.x * a.vox_per_block;
+    const size_t ve = min((size_t)a.N, vb + a.vox_per_block);
+    f4 acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
+    for (size_t cb = vb + wave * 16; cb < ve; cb += 64) {
+        const size_t v = cb + 4 * g;
+        float2 x[NB][4];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int f = nb * 16 + i16;
+            if (f < a.nt && v < ve) {
+                const float4* src = reinterpret_cast<const float4*>(a.C + (size_t)f * a.N + v);
+                const float4 u0 = src[0], u1 = src[1];
+                x[nb][0] = make_float2(u0.x, u0.y);
+                x[nb][1] = make_float2(u0.z, u0.w);
+                x[nb][2] = make_float2(u1.x, u1.y);
+                x[nb][3] = make_float2(u1.z, u1.w);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) x[nb][s] = make_float2(0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            float op[NT4];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                op[nb] = x[nb][s].x;
+                op[NB + nb] = x[nb][s].y;
+            }
+            int p = 0;
+#pragma unroll
+            for (int I = 0; I < NT4; ++I)
+#pragma unroll
+                for (int J = I; J < NT4; ++J, ++p)
+                    acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[I], op[J], acc[p], 0, 0, 0);
+        }
+    }
+    gram_block_store<NP, false>(acc, red, a.part, lane, wave);
+}
+
+// ---------------------------------------------------------------- split-BF16 Gram
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi); R^T R ~ hi^T hi + hi^T lo + lo^T hi on
+// v_mfma_f32_16x16x32_bf16 (the lo^T lo term, ~2^-16 relative, is dropped).  Lane (i, g)
+// holds 8 consecutive voxels 8g..8g+7 of a 32-voxel chunk for frames i and 16 + i; A and B
+// use the same (lane, element) -> voxel mapping, which is all a Gram needs.
+template <int NB>
+__global__ void __launch_bounds__(256) pls_gram_bf16x3_kernel(GramArgs a) {
+    constexpr int NT4 = 2 * NB;
+    constexpr int NP = npair<NB>();
+    __shared__ double red[2][NP * 256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, g = lane >> 4;
+    const size_t vb = (size_t)blockIdx.x * a.vox_per_block;
+    const size_t ve = min((size_t)a.N, vb + a.vox_per_block);
+    f4 acc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] = f4{0.f, 0.f, 0.f, 0.f};
+    for (size_t cb = vb + wave * 32; cb < ve; cb += 128) {
+        const size_t v = cb + 8 * g;
+        bf8 hi[NT4], lo[NT4];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int f = nb * 16 + i16;
+            float re[8], im[8];
+            if (f < a.nt && v < ve) {
+                const float4* src = reinterpret_cast<const float4*>(a.C + (size_t)f * a.N + v);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 u = src[k];
+                    re[2 * k] = u.x;
+                    im[2 * k] = u.y;
+                    re[2 * k + 1] = u.z;
+                    im[2 * k + 1] = u.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) re[k] = im[k] = 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const __bf16 hr = (__bf16)re[k], hm = (__bf16)im[k];
+                hi[nb][k] = hr;
+                lo[nb][k] = (__bf16)(re[k] - (float)hr);
+                hi[NB + nb][k] = hm;
+                lo[NB + nb][k] = (__bf16)(im[k] - (float)hm);
+            }
+        }
+        int p = 0;
+#pragma unroll
+        for (int I = 0; I < NT4; ++I)
+#pragma unroll
+            for (int J = I; J < NT4; ++J, ++p) {
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], hi[J], acc[p], 0, 0, 0);
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], lo[J], acc[p], 0, 0, 0);
+                acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[I], hi[J], acc[p], 0, 0, 0);
+            }
+    }
+    gram_block_store<NP, false>(acc, red, a.part, lane, wave);
+}
+
 int launch_gram(int mode, const GramArgs& a0, hipStream_t s) {
-    (void)mode;
     GramArgs a = a0;
     int vpb = (a.N + kGramBlocks - 1) / kGramBlocks;
-    vpb = (vpb + 63) / 64 * 64;
+    vpb = (vpb + 127) / 128 * 128;
     a.vox_per_block = vpb;
     const int grid = (a.N + vpb - 1) / vpb;
-    if (a.nt <= 16)
-        hipLaunchKernelGGL(pls_gram_f64_kernel<1>, dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(pls_gram_f64_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+    const bool one = a.nt <= 16;
+    if (mode == PRIOR_LS_GRAM_FP32) {
+        if (one) hipLaunchKernelGGL(pls_gram_f32_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(pls_gram_f32_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+    } else if (mode == PRIOR_LS_GRAM_BF16X3) {
+        if (one) hipLaunchKernelGGL(pls_gram_bf16x3_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(pls_gram_bf16x3_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+    } else {
+        if (one) hipLaunchKernelGGL(pls_gram_f64_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(pls_gram_f64_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+    }
     return grid;
 }
 

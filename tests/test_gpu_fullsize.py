@@ -22,16 +22,18 @@ import paper_1411_6206_amd as pls  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 TOL = 1e-4
+MODE_TOL = {"fp64": 1e-4, "fp32": 1e-4, "bf16x3": 1e-3}
 
 
-def run_fixture(name):
+def run_fixture(name, mode="fp64"):
     path = os.path.join(GOLDEN, f"{name}_oracle_samples.npz")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated")
     fx = np.load(path)
     p = synth.config(int(fx["config"]))
     t = pls.to_device(p)
-    with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=2) as h:
+    tol = MODE_TOL[mode]
+    with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=2, gram_mode=mode) as h:
         out, st = h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"],
                           lambda_L=p.lambda_L, lambda_S=p.lambda_S, max_iter=int(fx["iters"]),
                           check_every=10)
@@ -40,20 +42,22 @@ def run_fixture(name):
         g = out[k].reshape(-1)[idx].cpu().numpy().astype(np.complex128)
         want = fx[k]
         e = float(np.linalg.norm(g - want) / np.linalg.norm(want))
-        assert e < TOL, (name, k, e)
+        print(f"{name} {mode} {k}: sampled rel L2 vs FP64 oracle {e:.3e}")
+        assert e < tol, (name, mode, k, e)
         n = float(torch.linalg.vector_norm(out[k].to(torch.complex128)))
-        assert n == pytest.approx(float(fx[f"norm_{k}"]), rel=TOL), (name, k)
+        assert n == pytest.approx(float(fx[f"norm_{k}"]), rel=tol), (name, k)
     nX = float(torch.linalg.vector_norm(out["X"].to(torch.complex128)))
-    assert nX == pytest.approx(float(fx["norm_X"]), rel=TOL)
-    assert st["resid_norm"] == pytest.approx(float(fx["resid"]), rel=TOL)
-    assert st["nuclear_norm"] == pytest.approx(float(fx["nuclear"]), rel=TOL)
+    assert nX == pytest.approx(float(fx["norm_X"]), rel=tol)
+    assert st["resid_norm"] == pytest.approx(float(fx["resid"]), rel=tol)
+    assert st["nuclear_norm"] == pytest.approx(float(fx["nuclear"]), rel=tol)
     sig = np.array(st["sigma"])
-    np.testing.assert_allclose(sig, fx["sigma"], rtol=TOL, atol=TOL * fx["sigma"][0])
+    np.testing.assert_allclose(sig, fx["sigma"], rtol=tol, atol=tol * fx["sigma"][0])
 
 
 def test_c2_full_size_100_iterations():
     run_fixture("c2")
 
 
-def test_c3_full_size_30_iterations():
-    run_fixture("c3")
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "bf16x3"])
+def test_c3_full_size_30_iterations(mode):
+    run_fixture("c3", mode)

@@ -200,3 +200,27 @@ def test_config1_full(request):
     for k in ("L", "S", "X", "M"):
         e = rel(host(out[k]), r[k])
         assert e < TOL, (k, e)
+
+
+# Gram precision modes: FP64 MFMA (default, exact products), FP32 MFMA, split BF16 (hi+lo,
+# three products, FP32 accumulate).  The split-BF16 path is held to 1e-3.
+MODE_TOL = {"fp64": (1e-5, 1e-4), "fp32": (1e-4, 1e-4), "bf16x3": (1e-3, 1e-3)}
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_gram_modes_svt_and_solve(case, mode):
+    p, J = case
+    tol_op, tol = MODE_TOL[mode]
+    with handle(p, J, gram_mode=mode) as h:
+        load(h, p)
+        Cm = oracle.EH(p.kspace, p.mask, p.sens).astype(np.complex64).astype(np.complex128)
+        Lg, sig = h.op_svt(dev(Cm))
+        out, st = load(h, p, max_iter=7, check_every=7)
+    Lw, sw, _, _ = oracle.svt(oracle.cas(Cm), p.lambda_L)
+    e = rel(host(Lg), oracle.uncas(Lw, p.shape))
+    assert e < tol_op, (mode, e)
+    np.testing.assert_allclose(sig, sw, rtol=tol_op, atol=tol_op * sw[0])
+    r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=J, iters=7)
+    for k in ("L", "S", "X", "M"):
+        e = rel(host(out[k]), r[k])
+        assert e < tol, (mode, k, e)
