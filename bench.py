@@ -219,6 +219,38 @@ def main():
         "input_gen_s": gen_s,
     }
     h.close()
+
+    # Gram precision modes on the same problem: throughput, Gram time and, where the sampled
+    # FP64-oracle fixture of this workload (30 iterations) is present, the relative L2 error
+    # of L, S and X = L + S at its sample voxels
+    fx_path = os.path.join(ROOT, "tests", "golden", f"c{args.config}_oracle_samples.npz")
+    fx = np.load(fx_path) if os.path.exists(fx_path) else None
+    modes = {}
+    for mode in ("fp64", "fp32", "bf16x3"):
+        hm = pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=2, gram_mode=mode)
+        iters = int(fx["iters"]) if fx is not None else 0
+        outm, _ = hm.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], max_iter=iters,
+                           check_every=max(iters, 1), outputs=("L", "S", "X"), **solve_kw)
+        rec = {}
+        if fx is not None:
+            idx = torch.from_numpy(fx["idx"]).cuda()
+            want = {"L": fx["L"], "S": fx["S"], "X": fx["L"] + fx["S"]}
+            for k in ("L", "S", "X"):
+                g = outm[k].reshape(-1)[idx].cpu().numpy().astype(np.complex128)
+                rec[f"rel_l2_{k}_vs_fp64_oracle"] = float(np.linalg.norm(g - want[k]) /
+                                                          np.linalg.norm(want[k]))
+        del outm
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        km, _ = hm.step_timed(args.steps)
+        torch.cuda.synchronize()
+        rec["iterations_per_s"] = args.steps / (time.perf_counter() - a0)
+        rec["gram_ms"] = km["gram"] / args.steps
+        modes[mode] = rec
+        hm.close()
+    out["gram_modes"] = modes
+    out["gram_modes_sample"] = (f"{iters} iterations, {len(fx['idx'])} sampled voxels of the "
+                                f"committed FP64-oracle fixture") if fx is not None else None
     del t
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
