@@ -185,25 +185,37 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
         // phases of the previous coil ended at the barrier inside fft2_inv, which also
         // orders the staging writes above before the reads below
         fft2_fwd<G>(v, lds, twy, twz, tidc);
+        // residual on the sampled entries; the compact data come from LDS when staged, else
+        // from global memory (two copies of the loop under a block-uniform branch, so each
+        // uses plain LDS or global loads rather than generic ones)
+        auto residual = [&](auto stagedI) __attribute__((always_inline)) {
+            constexpr bool kStaged = decltype(stagedI)::value;
+            float r2 = 0.f;
 #pragma unroll
-        for (int i = 0; i < DL::NB; ++i) {
-            const int pbc = min(el.pb[i], nvalid - 1);
-            const bool ok = el.pb[i] < nvalid;
-            const float2* dh_p = dh_t + ((x0 + pbc) * a.nc + c) * nst;
+            for (int i = 0; i < DL::NB; ++i) {
+                const int pbc = min(el.pb[i], nvalid - 1);
+                const bool ok = el.pb[i] < nvalid;
+                const float2* dh_p = dh_t + ((x0 + pbc) * a.nc + c) * nst;
 #pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                const int q = i * RL + r;
-                int s = smap[el.rel[i] + r * DL::STEP];
-                s = ok ? s : -1;
-                const int sc0 = s < 0 ? 0 : s;
-                const float2 d = staged ? dhs[buf][pbc * nst + sc0] : dh_p[sc0];
-                const bool smp = s >= 0;
-                const float2 rv = make_float2(smp ? fmaf(v[q].x, a.inv_p, -d.x) : 0.f,
-                                              smp ? fmaf(v[q].y, a.inv_p, -d.y) : 0.f);
-                res2 = fma((double)rv.x, (double)rv.x, fma((double)rv.y, (double)rv.y, res2));
-                v[q] = rv;
+                for (int r = 0; r < RL; ++r) {
+                    const int q = i * RL + r;
+                    int s = smap[el.rel[i] + r * DL::STEP];
+                    s = ok ? s : -1;
+                    const int sc0 = s < 0 ? 0 : s;
+                    float2 d;
+                    if constexpr (kStaged) d = dhs[buf][pbc * nst + sc0];
+                    else d = dh_p[sc0];
+                    const bool smp = s >= 0;
+                    const float2 rv = make_float2(smp ? fmaf(v[q].x, a.inv_p, -d.x) : 0.f,
+                                                  smp ? fmaf(v[q].y, a.inv_p, -d.y) : 0.f);
+                    r2 = fmaf(rv.x, rv.x, fmaf(rv.y, rv.y, r2));
+                    v[q] = rv;
+                }
             }
-        }
+            res2 += (double)r2;
+        };
+        if (staged) residual(std::true_type{});
+        else residual(std::false_type{});
         fft2_inv<G>(v, lds, twy, twz, tidc);
 #pragma unroll
         for (int i = 0; i < D0::NB; ++i) {
