@@ -295,35 +295,44 @@ int launch_gram(int mode, const GramArgs& a0, hipStream_t s) {
     return grid;
 }
 
-// out[e] = sum over the per-block partials, in a fixed order: each of 8 row groups of a
-// block sums the partials b = g, g + 8, g + 16, ... of 32 entries, then the 8 group sums
-// are added in group order.
+// out[e] = sum over the per-block partials in a fixed order: a block covers 16 entries
+// (one 128-byte row segment per partial) with 16 row groups; group g sums the partials
+// b = g + 16 m into eight accumulators (m mod 8, so eight loads are in flight), adds them in
+// index order, and the 16 group sums are added in group order.
 __global__ void __launch_bounds__(256) pls_gram_reduce_kernel(const double* part, int blocks,
                                                               int entries, double* out) {
-    __shared__ double red[8][32];
-    const int le = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const int e = blockIdx.x * 32 + le;
-    double s0 = 0.0, s1 = 0.0;
-    if (e < entries) {
-        int b = g;
-        for (; b + 8 < blocks; b += 16) {
-            s0 += part[(size_t)b * entries + e];
-            s1 += part[(size_t)(b + 8) * entries + e];
-        }
-        if (b < blocks) s0 += part[(size_t)b * entries + e];
+    __shared__ double red[16][16];
+    // on the critical path while the sparse update shares the CUs: issue before its waves
+    __builtin_amdgcn_s_setprio(3);
+    const int le = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int e = blockIdx.x * 16 + le;
+    const int ec = e < entries ? e : entries - 1;
+    double s[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = 0.0;
+    int b = g;
+    for (; b + 7 * 16 < blocks; b += 8 * 16) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += part[(size_t)(b + 16 * k) * entries + ec];
     }
-    red[g][le] = s0 + s1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (b + 16 * k < blocks) s[k] += part[(size_t)(b + 16 * k) * entries + ec];
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t += s[k];
+    red[g][le] = t;
     __syncthreads();
     if (g == 0 && e < entries) {
-        double t = 0.0;
+        double u = 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) t += red[k][le];
-        out[e] = t;
+        for (int k = 0; k < 16; ++k) u += red[k][le];
+        out[e] = u;
     }
 }
 
 void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(pls_gram_reduce_kernel, dim3((entries + 31) / 32), dim3(256), 0, s, part,
+    hipLaunchKernelGGL(pls_gram_reduce_kernel, dim3((entries + 15) / 16), dim3(256), 0, s, part,
                        blocks, entries, out);
 }
 
@@ -409,6 +418,9 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
     __shared__ double red[4];
     __shared__ double sig[kNMax], phi[kNMax];
     __shared__ int rank_of[kNMax];
+    // one block on the critical path while the sparse update fills the other CUs (and
+    // possibly this one): its waves issue first
+    __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x;
     const int n = a.nt;
     const int ne = n + (n & 1);

@@ -25,16 +25,30 @@ __global__ void __launch_bounds__(256) pls_bp_kernel(BpArgs a) {
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) Areg[mb][ks] = a.Wop[(16 * mb + i16) * K2 + 4 * ks + g];
-    const size_t N = (size_t)a.N;
-    const size_t stride = (size_t)gridDim.x * 4 * 16;
-    for (size_t v0 = ((size_t)blockIdx.x * 4 + wave) * 16; v0 < N; v0 += stride) {
-        const size_t v = v0 + i16;
-        float2 cb[KH];
+    const int N = a.N;
+    const int stride = gridDim.x * 4 * 16;
+    // frames are clamped into range and voxels into the volume, so every load is valid and
+    // issued without a branch; out-of-range values are zeroed by selects
+    auto load_tile = [&](int v0, float2 (&cb)[KH]) __attribute__((always_inline)) {
+        const int v = v0 + i16;
+        const int vc = v < N ? v : N - 1;
 #pragma unroll
         for (int kk = 0; kk < KH; ++kk) {
             const int f = 4 * kk + g;
-            cb[kk] = (f < a.nt && v < N) ? a.C[(size_t)f * N + v] : make_float2(0.f, 0.f);
+            const int fc = f < a.nt ? f : a.nt - 1;
+            const float2 x = a.C[fc * N + vc];
+            cb[kk] = (f < a.nt && v < N) ? x : make_float2(0.f, 0.f);
         }
+    };
+    int v0 = (blockIdx.x * 4 + wave) * 16;
+    if (v0 >= N) return;
+    float2 cb[KH];
+    load_tile(v0, cb);
+    for (; v0 < N; v0 += stride) {
+        // fetch the next tile before this one's products (software pipelining)
+        float2 nb[KH];
+        const int vn = v0 + stride;
+        load_tile(vn < N ? vn : v0, nb);
         f4 acc[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[mb] = f4{0.f, 0.f, 0.f, 0.f};
@@ -45,15 +59,18 @@ __global__ void __launch_bounds__(256) pls_bp_kernel(BpArgs a) {
             for (int mb = 0; mb < MB; ++mb)
                 acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Areg[mb][ks], b, acc[mb], 0, 0, 0);
         }
+        const int v = v0 + i16;
         if (v < N) {
 #pragma unroll
             for (int mb = 0; mb < MB / 2; ++mb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int f = 16 * mb + 4 * g + r;
-                    if (f < a.nt) a.L[(size_t)f * N + v] = make_float2(acc[mb][r], acc[mb + MB / 2][r]);
+                    if (f < a.nt) a.L[f * N + v] = make_float2(acc[mb][r], acc[mb + MB / 2][r]);
                 }
         }
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) cb[kk] = nb[kk];
     }
 }
 
@@ -134,41 +151,50 @@ __global__ void __launch_bounds__(256) pls_sparse_kernel(SparseArgs a) {
     const int y = yt * 4 * YW + wave * YW + yl;
     const int z = zt * ZW + zl;
     const bool valid = y < a.ny;
-    float2 v[XW];
-    size_t gi[XW];
+    // Every lane loads from a valid address (y clamped into the volume, absent arrays
+    // replaced by C) and discards with selects, so the loads of all XW rows and all arrays
+    // are in flight together.
+    const int yc = valid ? y : a.ny - 1;
+    const bool has_s = a.S != nullptr, has_w = a.w != nullptr;
+    const float2* Sp = has_s ? a.S : a.C;
+    const uint8_t* wp = has_w ? a.w : reinterpret_cast<const uint8_t*>(a.C);
+    float2 v[XW], sv[XW], lv[XW];
+    int gi[XW];
+    uint8_t wq[XW];
 #pragma unroll
     for (int k = 0; k < XW; ++k) {
-        gi[k] = (((size_t)t * a.nx + xt * XW + k) * a.nz + z) * a.ny + y;
-        float2 u = make_float2(0.f, 0.f);
-        if (valid) {
-            u = a.C[gi[k]];
-            if (a.S) u = cadd(u, a.S[gi[k]]);
-            u = csub(u, a.Lp[gi[k]]);
-        }
-        v[k] = u;
+        gi[k] = ((t * a.nx + xt * XW + k) * a.nz + z) * a.ny + yc;
+        v[k] = a.C[gi[k]];
+        sv[k] = Sp[gi[k]];
+        lv[k] = a.Lp[gi[k]];
+        wq[k] = wp[gi[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < XW; ++k) {
+        const float2 u = has_s ? cadd(v[k], sv[k]) : v[k];
+        v[k] = valid ? csub(u, lv[k]) : make_float2(0.f, 0.f);
     }
     for (int l = 0; l < J; ++l) haar_level<J, ZA>(v, l, yl, zl, lane);
-    double l1 = 0.0;
+    float l1 = 0.f;
 #pragma unroll
     for (int k = 0; k < XW; ++k) {
-        const float w = (a.w && valid) ? (float)a.w[gi[k]] * (1.0f / 255.0f) : 0.0f;
-        const float tau = a.lambda_S * (1.0f - w);
+        // soft threshold of the complex magnitude: u (1 - tau / |u|) where |u| > tau
+        const float wk = has_w ? (float)wq[k] * (1.0f / 255.0f) : 0.0f;
+        const float tau = a.lambda_S * (1.0f - wk);
         const float2 u = v[k];
-        const float mag = sqrtf(fmaf(u.x, u.x, u.y * u.y));
-        float2 o = make_float2(0.f, 0.f);
-        if (mag > tau) {
-            const float sc = (mag - tau) / mag;
-            o = make_float2(u.x * sc, u.y * sc);
-        }
-        v[k] = o;
-        if (valid) l1 += (double)(1.0f - w) * (double)sqrtf(fmaf(o.x, o.x, o.y * o.y));
+        const float m2 = fmaf(u.x, u.x, u.y * u.y);
+        const bool keep = valid && m2 > tau * tau;
+        const float rm = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
+        const float sc = fmaf(-tau, rm, 1.0f);
+        v[k] = keep ? make_float2(u.x * sc, u.y * sc) : make_float2(0.f, 0.f);
+        l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
     }
     for (int l = J - 1; l >= 0; --l) haar_level<J, ZA>(v, l, yl, zl, lane);
     if (valid) {
 #pragma unroll
         for (int k = 0; k < XW; ++k) a.Sout[gi[k]] = v[k];
     }
-    const double s = block_sum<256>(l1, red);
+    const double s = block_sum<256>((double)l1, red);
     if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 

@@ -234,8 +234,8 @@ bool is_device_ptr(const void* p) {
 // one iteration of Algorithm 1 on the resident state (see the schedule in the header)
 // One iteration of Algorithm 1 on the resident state.  Steps (1)-(2) (Gram, eigensolve,
 // back-projection) run on the main stream while step (3) (sparse update) runs on the side
-// stream; both only read C = M - S, S and L of the previous iterate, and step (4) (data
-// consistency) joins them.  ev (optional): 2 timing events around each of the 7 kernels,
+// stream from the end of the Gram pass on; both only read C = M - S, S and L of the
+// previous iterate, and step (4) (data consistency) joins them.  ev (optional): 2 timing events around each of the 7 kernels,
 // recorded on the stream the kernel runs on.
 void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev = nullptr) {
     const prior_ls_dims& d = h->d;
@@ -246,9 +246,16 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     auto mark = [&](int k, hipStream_t st) {
         if (ev) PLS_HIP(hipEventRecord(ev[k], st));
     };
+    // steps (1)-(2): Gram, eigensolve, W, L_k = C W   [main stream]
+    mark(0, s);
+    pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0};
+    const int gb = pls::launch_gram(d.gram_mode, ga, s);
+    mark(1, s);
     PLS_HIP(hipEventRecord(h->ev_fork, s));
     PLS_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
-    // step (3): S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)   [side stream]
+    // step (3), forked after the Gram pass so that it fills the GPU beside the one-block
+    // eigensolve rather than competing with the Gram for bandwidth:
+    // S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)   [side stream]
     pls::SparseArgs sa{};
     sa.C = h->C;
     sa.S = h->S[p];
@@ -265,11 +272,6 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     const int spb = pls::launch_sparse(d.wavelet_levels, sa, s2);
     mark(7, s2);
     PLS_HIP(hipEventRecord(h->ev_join, s2));
-    // steps (1)-(2): Gram, eigensolve, W, L_k = C W   [main stream]
-    mark(0, s);
-    pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0};
-    const int gb = pls::launch_gram(d.gram_mode, ga, s);
-    mark(1, s);
     mark(2, s);
     pls::launch_gram_reduce(h->gpart, gb, sz.gentries, h->gred, s);
     mark(3, s);
