@@ -154,6 +154,29 @@ int prior_ls_solve(prior_ls_handle *h, const prior_ls_inputs *in, const prior_ls
 int prior_ls_step(prior_ls_handle *h, int32_t n_iter, const prior_ls_outputs *out,
                   prior_ls_stats *stats);
 
+/* The priori L+S scheme over a time sequence (Section 3, Fig. 2), as a sliding window.
+ * After prior_ls_solve (the first time instance: plain L+S, i.e. no prior_w and
+ * lambda_p = 0) or a previous append, the handle holds the result of a window of nt frames.
+ * prior_ls_append drops the window's oldest frame, takes the new frame as the newest, and
+ * runs params->max_iter iterations of Algorithm 1 on the new window:
+ *   - warm start: L and S shifted by one frame, the new frame starting from the previous
+ *     newest frame, then one data-consistency step (step (0) of a warm start);
+ *   - a-priori knowledge from the previous window's result: the support T^(t-1) of T(S)
+ *     (the coefficients that survived the last shrinkage; shifted the same way, the new
+ *     frame taking the previous newest frame's support) as weights w = 1, and the singular
+ *     values of L as sigma_prev for step (2) (used when params->lambda_p > 0).
+ * kspace_frame: device, complex64 [nc][nz][ny][nx] (entries off the mask are ignored);
+ * mask_frame: device, uint8 [nz][ny].  Both may be freed when the call returns.  Outputs
+ * and stats as for prior_ls_step; stats.iters counts this window's iterations.  The
+ * compact k-space keeps one slot per frame and grows when a frame has more samples than
+ * any frame of the window before it.
+ * Errors: EINVAL (NULL or host pointers, no window loaded, bad params), ESHAPE (sampled
+ * data beyond 2^31 entries), ENOMEM (growing the compact k-space failed), EHIP,
+ * ENONFINITE. */
+int prior_ls_append(prior_ls_handle *h, const void *kspace_frame, const uint8_t *mask_frame,
+                    const prior_ls_params *params, const prior_ls_outputs *out,
+                    prior_ls_stats *stats);
+
 /* Release every resource of the handle.  NULL is a no-op. */
 void prior_ls_destroy(prior_ls_handle *h);
 

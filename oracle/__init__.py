@@ -8,4 +8,4 @@ unpinned": the paper prints no values for them.
 """
 from .priori_ls import (E, EH, fft3, ifft3, soft, haar_fwd, haar_inv, cas, uncas,  # noqa: F401
                         sv_targets, svt, svt_gram, sparse_step, dc_step, solve, plain_ls,
-                        psnr, rel_l2, NULL_REL)
+                        psnr, rel_l2, NULL_REL, shift_window, append_frame)

@@ -223,8 +223,11 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
     first sparse update sees X_0 - L_0 = 0.  A warm start (L0, S0) instead takes
     X_0 = Y - A^{-1}(A(Y) - d) with Y = L0 + S0 (one data-consistency step).
 
-    Returns a dict with L, S, X = L + S, M (the data-consistent iterate X_it) and
-    per-iteration statistics."""
+    Returns a dict with L, S, X = L + S, M (the data-consistent iterate X_it),
+    per-iteration statistics, and what the next time instance takes as a-priori
+    knowledge (Section 3): supp, 255 on the support of T(S) (the coefficients that survive
+    the last shrinkage, canonical layout; all 0 when no iteration ran) and sigma_L, the
+    singular values of the returned L (descending; zeros when no iteration ran)."""
     svt_fn = svt if svt_fn is None else svt_fn
     d = np.asarray(d, np.complex128)
     shape = d.shape[1:]
@@ -238,6 +241,8 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
         M, _ = dc_step(L + S, d, mask, sens)
     w = None if prior_w is None else prior_w.astype(np.float64) / 255.0
     hist = dict(rel_change=[], resid=[], nuclear=[], l1w=[], objective=[], sigma=[], tau_L=[])
+    supp = np.zeros(shape, np.uint8)
+    sigma_L = np.zeros(shape[0])
     it = 0
     for it in range(1, iters + 1):
         Y_prev = L + S
@@ -248,6 +253,8 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
         # step (3)
         S_new, Zs = sparse_step(M, L, prior_w, lambda_S, levels)
         L, S = L_new, S_new
+        supp = np.where(Zs != 0, 255, 0).astype(np.uint8)
+        sigma_L = sig_t
         # step (4)
         Y = L + S
         M, R = dc_step(Y, d, mask, sens)
@@ -266,7 +273,42 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
         hist["tau_L"].append(tau_L)
         if tol > 0 and rel < tol:
             break
-    return dict(L=L, S=S, X=L + S, M=M, iters=it, **{k: np.array(v) for k, v in hist.items()})
+    return dict(L=L, S=S, X=L + S, M=M, iters=it, supp=supp, sigma_L=np.asarray(sigma_L),
+                **{k: np.array(v) for k, v in hist.items()})
+
+
+# --------------------------------------------------------------------------------------
+# The priori L+S scheme over a time sequence (Section 3, Fig. 2): each time instance is
+# reconstructed by Algorithm 1 with the previous instance's L and S as a-priori knowledge;
+# the first instance uses plain L+S (solve() with no weights and lambda_p = 0).
+# Reading: a time instance is a window of nt frames that slides by one frame, so the new
+# window shares nt - 1 frames with the previous one, and
+#   * data and masks drop the oldest frame and take the new one last;
+#   * the support prior T^(t-1) and the singular values Sigma(L^(t-1)) are those of the
+#     previous window's result, its support map shifted with the frames and the new frame
+#     given the previous last frame's support (adjacent frames share their support);
+#   * the iteration is warm-started from the previous L and S, shifted the same way (the
+#     new frame starts from the previous last frame).
+# --------------------------------------------------------------------------------------
+def shift_window(a, new):
+    """Frames 1..nt-1 of a (axis 0) followed by `new` (one frame)."""
+    return np.concatenate([np.asarray(a)[1:], np.asarray(new)[None]], axis=0)
+
+
+def append_frame(prev, d, mask, sens, d_new, mask_new, lambda_L, lambda_S, lambda_p=0.0,
+                 levels=2, iters=20, tol=0.0, lambda_L_relative=True):
+    """One step of the sequence: prev is the result of solve() (or append_frame) for the
+    window (d, mask); d_new [nc][nz][ny][nx] and mask_new [nz][ny] are the new frame.
+    Returns (result of the new window, its data, its mask)."""
+    d_next = np.concatenate([np.asarray(d)[:, 1:], np.asarray(d_new)[:, None]], axis=1)
+    mask_next = shift_window(mask, mask_new)
+    L0 = shift_window(prev["L"], prev["L"][-1])
+    S0 = shift_window(prev["S"], prev["S"][-1])
+    w = shift_window(prev["supp"], prev["supp"][-1])
+    r = solve(d_next, mask_next, sens, w, lambda_L, lambda_S, lambda_p=lambda_p,
+              sigma_prev=prev["sigma_L"], levels=levels, iters=iters, tol=tol, L0=L0, S0=S0,
+              lambda_L_relative=lambda_L_relative)
+    return r, d_next, mask_next
 
 
 def plain_ls(d, mask, sens, lambda_L, lambda_S, levels=2, iters=50):

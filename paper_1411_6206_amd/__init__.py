@@ -28,7 +28,8 @@ MAX_NT = 32
 # every symbol include/prior_ls.h declares
 EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destroy",
            "prior_ls_strerror", "prior_ls_last_error", "prior_ls_plan_bytes",
-           "prior_ls_op_dc", "prior_ls_op_svt", "prior_ls_op_sparse", "prior_ls_step_timed")
+           "prior_ls_op_dc", "prior_ls_op_svt", "prior_ls_op_sparse", "prior_ls_step_timed",
+           "prior_ls_append")
 NKERNELS = 7
 KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats")
 
@@ -118,6 +119,9 @@ def lib():
     L.prior_ls_step_timed.argtypes = [H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                       C.POINTER(Stats)]
     L.prior_ls_step_timed.restype = C.c_int
+    L.prior_ls_append.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(Params),
+                                  C.POINTER(Outputs), C.POINTER(Stats)]
+    L.prior_ls_append.restype = C.c_int
     _lib = L
     return L
 
@@ -194,6 +198,25 @@ class PriorLS:
         rc = lib().prior_ls_solve(self._h, C.byref(ins), C.byref(prm), C.byref(o), C.byref(st))
         torch.cuda.current_stream().synchronize()
         self._check(rc, "prior_ls_solve")
+        return outs, st.as_dict()
+
+    def append(self, kspace_frame, mask_frame, lambda_L=0.01, lambda_S=0.01, lambda_p=0.0,
+               lambda_L_relative=True, max_iter=20, tol=0.0, check_every=10, use_graph=True,
+               outputs=("L", "S", "X", "M")):
+        """prior_ls_append: slide the window by one frame (kspace_frame complex64
+        [nc][nz][ny][nx], mask_frame uint8 [nz][ny]) and iterate with the previous window's
+        support and singular values as a-priori knowledge."""
+        import torch
+        prm = Params(C.sizeof(Params), float(lambda_L), float(lambda_S), float(lambda_p),
+                     float(tol), 1 if lambda_L_relative else 0, int(max_iter), int(check_every),
+                     1 if use_graph else 0)
+        outs, o = self._outputs(outputs)
+        st = Stats()
+        st.struct_size = C.sizeof(Stats)
+        rc = lib().prior_ls_append(self._h, _ptr(kspace_frame), _ptr(mask_frame), C.byref(prm),
+                                   C.byref(o), C.byref(st))
+        torch.cuda.current_stream().synchronize()
+        self._check(rc, "prior_ls_append")
         return outs, st.as_dict()
 
     def step(self, n_iter, outputs=("L", "S", "X", "M")):

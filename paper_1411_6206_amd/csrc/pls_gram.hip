@@ -579,6 +579,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
         phi[tid] = sg > 0.0 ? tgt / sg : 0.0;
         nuc_part = tgt;
         a.stat[16 + rank_of[tid]] = sg;
+        if (a.sigL) a.sigL[rank_of[tid]] = tgt;
     }
     __syncthreads();
     // nuclear norm summed in rank order for determinism

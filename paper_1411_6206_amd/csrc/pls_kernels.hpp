@@ -86,6 +86,7 @@ struct EigArgs {
     double* Wd;            // W = V diag(phi) V^H, complex [nt][nt] (FP64 copy)
     const double* sigma_prev;  // [nt] descending, zero padded
     double* stat;          // per-iteration record (see pls_stats layout in the runtime)
+    double* sigL;          // [nt] singular values of the new L by rank (descending), or NULL
     int nt;
     double lambda_L, lambda_p;
     int relative;
@@ -106,6 +107,8 @@ struct SparseArgs {
     const float2* Lp;      // previous L
     const uint8_t* w;      // internal block-local weights or NULL
     float2* Sout;
+    uint8_t* supp;         // 255 where a coefficient survives the shrinkage, else 0 (same
+                           // layout as w), or NULL
     double* part;          // per block: weighted l1 of the shrunk coefficients
     int nx, ny, nz, nt;
     float lambda_S;

@@ -188,6 +188,7 @@ __global__ void __launch_bounds__(256) pls_sparse_kernel(SparseArgs a) {
         const float sc = fmaf(-tau, rm, 1.0f);
         v[k] = keep ? make_float2(u.x * sc, u.y * sc) : make_float2(0.f, 0.f);
         l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
+        if (a.supp && valid) a.supp[gi[k]] = keep ? 255 : 0;
     }
     for (int l = J - 1; l >= 0; --l) haar_level<J, ZA>(v, l, yl, zl, lane);
     if (valid) {

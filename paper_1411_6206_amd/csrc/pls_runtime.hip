@@ -120,7 +120,8 @@ Sizes sizes_of(const prior_ls_dims& d) {
     uint64_t b = 0;
     b += 5 * s.I * 8;                                   // C, L[2], S[2]
     if (d.nc > 1) b += (uint64_t)d.nc * s.N * 8;        // sensitivities
-    b += s.I;                                           // weights
+    b += 2 * s.I;                                       // weights, support of T(S)
+    b += (uint64_t)2 * d.nt * s.P + 64 * 8;             // masks (two copies), sigma of L
     b += (uint64_t)d.nt * s.P * (2 + 4) + 3 * (d.nt + 1) * 4;  // sidx, plist, ns, offsets
     b += (uint64_t)(d.nx + d.ny + d.nz) * 8;            // twiddles
     b += (uint64_t)s.gblocks * s.gentries * 8 + s.gentries * 8;
@@ -152,6 +153,15 @@ struct prior_ls_handle {
     bool has_w = false, has_sens = false;
     float2* dh = nullptr;
     size_t dh_cap = 0;
+    // the compact k-space is a ring of nt frame slots of slot_cap entries each; logical
+    // frame t lives in slot slot_of[t] (dh_off[t] = slot_of[t] * slot_cap), so a new
+    // frame replaces the oldest one in place
+    size_t slot_cap = 0;
+    std::vector<int> slot_of;
+    uint8_t* mask_d = nullptr;       // [nt][P] masks of the window, logical frame order
+    uint8_t* mask_tmp = nullptr;
+    uint8_t* supp = nullptr;         // support of T(S) of the last sparse update (0 / 255)
+    double* sigL = nullptr;          // singular values of the last L, by rank
     int *dh_off = nullptr, *ns = nullptr, *plist = nullptr, *line_off = nullptr;
     int16_t* sidx = nullptr;
     float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
@@ -262,6 +272,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     sa.Lp = h->L[p];
     sa.w = h->has_w ? h->w : nullptr;
     sa.Sout = h->S[q];
+    sa.supp = h->supp;
     sa.part = h->sp_part;
     sa.nx = d.nx;
     sa.ny = d.ny;
@@ -283,6 +294,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     ea.Wd = h->Wd;
     ea.sigma_prev = h->sigma_prev;
     ea.stat = rec;
+    ea.sigL = h->sigL;
     ea.nt = d.nt;
     ea.lambda_L = h->params.lambda_L;
     ea.lambda_p = h->params.lambda_p;
@@ -461,18 +473,25 @@ int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_p
     std::vector<int> ns(d.nt), off(d.nt), loff(d.nt + 1);
     PLS_HIP(hipMemcpyAsync(ns.data(), h->ns, d.nt * sizeof(int), hipMemcpyDeviceToHost, s));
     PLS_HIP(hipStreamSynchronize(s));
-    size_t total = 0;
-    int lines = 0;
+    int lines = 0, ns_max = 1;
     for (int t = 0; t < d.nt; ++t) {
-        off[t] = (int)total;
         loff[t] = lines;
-        total += (size_t)d.nx * d.nc * ns[t];
         lines += d.nc * ns[t];
+        ns_max = std::max(ns_max, ns[t]);
     }
     loff[d.nt] = lines;
+    const size_t slot = (size_t)d.nx * d.nc * ns_max;
+    const size_t total = slot * d.nt;
     if (total > (size_t)INT32_MAX) return fail(h, PRIOR_LS_ESHAPE, "sampled data exceed 2^31 entries");
+    h->slot_cap = slot;
+    h->slot_of.resize(d.nt);
+    for (int t = 0; t < d.nt; ++t) {
+        h->slot_of[t] = t;
+        off[t] = (int)(slot * t);
+    }
+    PLS_HIP(hipMemcpyAsync(h->mask_d, in->mask, (size_t)d.nt * sz.P, hipMemcpyDeviceToDevice, s));
     if (total > h->dh_cap || !h->dh) {
-        h->release(h->dh, h->dh_cap * sizeof(float2));
+        h->release(h->dh, (h->dh_cap + 64) * sizeof(float2));
         h->dh = nullptr;
         h->dh_cap = 0;
         try {
@@ -515,6 +534,8 @@ int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_p
     }
     PLS_HIP(hipMemcpyAsync(h->sigma_prev, sp.data(), d.nt * sizeof(double), hipMemcpyHostToDevice, s));
     set_identity_V(h, h->V);
+    PLS_HIP(hipMemsetAsync(h->supp, 0, sz.I, s));
+    PLS_HIP(hipMemsetAsync(h->sigL, 0, 64 * sizeof(double), s));
     // step (0)
     h->cur = 0;
     if (in->L0) {
@@ -565,6 +586,28 @@ int guarded(prior_ls_handle* h, F&& f) {
     } catch (const std::bad_alloc&) {
         return fail(h, PRIOR_LS_ENOMEM, "device allocation failed or hbm_budget exceeded");
     }
+}
+
+// Grows every frame slot of the compact k-space to `cap` entries, keeping the data of the
+// frames in them (the buffer moves, so captured graphs are dropped).
+void grow_slots(prior_ls_handle* h, size_t cap) {
+    const int nt = h->d.nt;
+    float2* nd = h->alloc<float2>((cap * nt + 64) * sizeof(float2));
+    for (int k = 0; k < nt; ++k)
+        PLS_HIP(hipMemcpyAsync(nd + k * cap, h->dh + k * h->slot_cap, h->slot_cap * sizeof(float2),
+                               hipMemcpyDeviceToDevice, h->stream));
+    PLS_HIP(hipStreamSynchronize(h->stream));
+    h->release(h->dh, (h->dh_cap + 64) * sizeof(float2));
+    h->dh = nd;
+    h->dh_cap = cap * nt;
+    h->slot_cap = cap;
+    h->clear_graphs();
+}
+
+// The parameters an iteration graph captures by value; a change drops the graphs.
+bool same_captured_params(const prior_ls_params& a, const prior_ls_params& b) {
+    return a.lambda_L == b.lambda_L && a.lambda_S == b.lambda_S && a.lambda_p == b.lambda_p &&
+           a.lambda_L_relative == b.lambda_L_relative && a.use_graph == b.use_graph;
 }
 
 }  // namespace
@@ -636,6 +679,10 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
         }
         if (d.nc > 1) h->sens = h->alloc<float2>((size_t)d.nc * sz.N * sizeof(float2));
         h->w = h->alloc<uint8_t>(sz.I);
+        h->supp = h->alloc<uint8_t>(sz.I);
+        h->mask_d = h->alloc<uint8_t>((size_t)d.nt * sz.P);
+        h->mask_tmp = h->alloc<uint8_t>((size_t)d.nt * sz.P);
+        h->sigL = h->alloc<double>(64 * sizeof(double));
         h->sidx = h->alloc<int16_t>((size_t)d.nt * sz.P * sizeof(int16_t));
         h->plist = h->alloc<int>((size_t)d.nt * sz.P * sizeof(int));
         h->ns = h->alloc<int>((d.nt + 1) * sizeof(int));
@@ -743,6 +790,108 @@ int prior_ls_step(prior_ls_handle* h, int32_t n_iter, const prior_ls_outputs* ou
         write_outputs(h, out);
         leave(h);
         PLS_HIP(hipStreamSynchronize(h->stream));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        fill_stats(h, stats, conv, ms);
+        return r;
+    });
+}
+
+int prior_ls_append(prior_ls_handle* h, const void* kspace_frame, const uint8_t* mask_frame,
+                    const prior_ls_params* params, const prior_ls_outputs* out,
+                    prior_ls_stats* stats) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!h->loaded) return fail(h, PRIOR_LS_EINVAL, "append before solve");
+    int rc = check_params(h, params);
+    if (rc) return rc;
+    if (stats && stats->struct_size != sizeof(prior_ls_stats))
+        return fail(h, PRIOR_LS_EINVAL, "stats.struct_size mismatch");
+    if (!kspace_frame || !mask_frame) return fail(h, PRIOR_LS_EINVAL, "kspace_frame and mask_frame are required");
+    if (!is_device_ptr(kspace_frame) || !is_device_ptr(mask_frame))
+        return fail(h, PRIOR_LS_EINVAL, "input array is not device memory");
+    if (out) {
+        const void* o[] = {out->L, out->S, out->X, out->M};
+        for (const void* p : o)
+            if (p && !is_device_ptr(p)) return fail(h, PRIOR_LS_EINVAL, "output array is not device memory");
+    }
+    return guarded(h, [&]() -> int {
+        const prior_ls_dims& d = h->d;
+        const Sizes& sz = h->sz;
+        const int nt = d.nt;
+        const size_t P = sz.P, N = sz.N;
+        hipStream_t s = h->stream;
+        enter(h);
+        // masks of the new window: frames 1..nt-1, then the new one
+        if (nt > 1)
+            PLS_HIP(hipMemcpyAsync(h->mask_tmp, h->mask_d + P, (nt - 1) * P, hipMemcpyDeviceToDevice, s));
+        PLS_HIP(hipMemcpyAsync(h->mask_tmp + (nt - 1) * P, mask_frame, P, hipMemcpyDeviceToDevice, s));
+        std::swap(h->mask_d, h->mask_tmp);
+        pls::launch_mask_scan(h->mask_d, d.ny, d.nz, nt, h->sidx, h->plist, h->ns, s);
+        PLS_HIP(hipGetLastError());
+        int ns_new = 0;
+        PLS_HIP(hipMemcpyAsync(&ns_new, h->ns + (nt - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+        PLS_HIP(hipStreamSynchronize(s));
+        // the new frame takes the slot of the dropped one
+        const size_t need = (size_t)d.nx * d.nc * ns_new;
+        if (need * nt > (size_t)INT32_MAX) return fail(h, PRIOR_LS_ESHAPE, "sampled data exceed 2^31 entries");
+        if (need > h->slot_cap) {
+            try {
+                grow_slots(h, need);
+            } catch (const std::bad_alloc&) {
+                return fail(h, PRIOR_LS_ENOMEM, "cannot grow the compact k-space (hbm_budget or device memory)");
+            }
+        }
+        std::rotate(h->slot_of.begin(), h->slot_of.begin() + 1, h->slot_of.end());
+        std::vector<int> off(nt);
+        for (int t = 0; t < nt; ++t) off[t] = (int)(h->slot_of[t] * h->slot_cap);
+        const int loff[2] = {0, d.nc * ns_new};
+        PLS_HIP(hipMemcpyAsync(h->dh_off, off.data(), nt * sizeof(int), hipMemcpyHostToDevice, s));
+        PLS_HIP(hipMemcpyAsync(h->line_off, loff, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+        // kx inverse DFT of the new frame's sampled lines into its slot
+        pls::XiArgs xa{};
+        xa.kspace = (const float2*)kspace_frame;
+        xa.plist = h->plist + (size_t)(nt - 1) * P;
+        xa.line_off = h->line_off;
+        xa.ns = h->ns + (nt - 1);
+        xa.dh_off = h->dh_off + (nt - 1);
+        xa.dh = h->dh;
+        xa.twx = h->twx;
+        xa.nx = d.nx;
+        xa.nt = 1;
+        xa.nc = d.nc;
+        xa.P = (int)P;
+        xa.total_lines = loff[1];
+        xa.scale = (float)(1.0 / std::sqrt((double)d.nx * (double)P));
+        pls::launch_xifft(d.nx, xa, s);
+        // warm start: L and S shifted by one frame, the new frame from the previous newest
+        const int p = h->cur, q = 1 - p;
+        const size_t fb = N * sizeof(float2);
+        for (float2** A : {h->L, h->S}) {
+            if (nt > 1)
+                PLS_HIP(hipMemcpyAsync(A[q], A[p] + N, (nt - 1) * fb, hipMemcpyDeviceToDevice, s));
+            PLS_HIP(hipMemcpyAsync(A[q] + (nt - 1) * N, A[p] + (nt - 1) * N, fb, hipMemcpyDeviceToDevice, s));
+        }
+        h->cur = q;
+        // a-priori knowledge: support of T(S) shifted the same way, singular values of L
+        if (nt > 1) PLS_HIP(hipMemcpyAsync(h->w, h->supp + N, (nt - 1) * N, hipMemcpyDeviceToDevice, s));
+        PLS_HIP(hipMemcpyAsync(h->w + (nt - 1) * N, h->supp + (nt - 1) * N, N, hipMemcpyDeviceToDevice, s));
+        PLS_HIP(hipMemcpyAsync(h->sigma_prev, h->sigL, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (!h->has_w || !same_captured_params(h->params, *params)) h->clear_graphs();
+        h->has_w = true;
+        h->params = *params;
+        set_identity_V(h, h->V);
+        // step (0) of the new window: one data-consistency step from Y = L + S
+        DcArgs da = dc_args(h, h->L[h->cur], h->S[h->cur], h->C);
+        pls::launch_dc(d.ny, d.nz, false, da, s);
+        PLS_HIP(hipGetLastError());
+        h->iters = 0;
+        std::memset(h->last, 0, sizeof(h->last));
+        bool conv = false;
+        const int r = iterate(h, params->max_iter, conv);
+        write_outputs(h, out);
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(s));
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         fill_stats(h, stats, conv, ms);
         return r;

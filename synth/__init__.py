@@ -371,3 +371,64 @@ def small(nx=16, ny=16, nz=4, nt=6, nc=2, accel=3, snr_db=40.0, rank=2, nblobs=3
     """A small instance for tests (a few tiles, ragged where the shape allows)."""
     return make_problem(nx=nx, ny=ny, nz=nz, nt=nt, nc=nc, accel=accel, snr_db=snr_db,
                         rank=rank, nblobs=nblobs, seed=seed, **kw)
+
+
+@dataclasses.dataclass
+class Sequence:
+    """A recursive real-time acquisition: a first window of nt frames followed by
+    n_append frames that arrive one at a time (all arrays complex128 / uint8)."""
+    nx: int
+    ny: int
+    nz: int
+    nt: int
+    nc: int
+    n_append: int
+    kspace: np.ndarray          # [nc][nt + n_append][nz][ny][nx], zero off the mask
+    mask: np.ndarray            # [nt + n_append][nz][ny]
+    sens: Optional[np.ndarray]  # [nc][nz][ny][nx] or None
+    L_true: np.ndarray          # [nt + n_append][nz][ny][nx]
+    S_true: np.ndarray
+    lambda_L: float = 0.01
+    lambda_S: float = 0.01
+    lambda_p: float = 0.0
+
+    @property
+    def X_true(self) -> np.ndarray:
+        return self.L_true + self.S_true
+
+    def first_window(self):
+        """(kspace [nc][nt]..., mask [nt]...) of frames 0..nt-1."""
+        return (np.ascontiguousarray(self.kspace[:, :self.nt]),
+                np.ascontiguousarray(self.mask[:self.nt]))
+
+    def frame(self, j):
+        """(kspace [nc][nz][ny][nx], mask [nz][ny]) of appended frame j (0-based)."""
+        f = self.nt + j
+        return (np.ascontiguousarray(self.kspace[:, f]), np.ascontiguousarray(self.mask[f]))
+
+
+def sequence(nx, ny, nz, nt, n_append, nc, accel, seed, accel_first=2.0, snr_db=40.0,
+             rank=2, nblobs=3, lambda_L=0.01, lambda_S=0.01, lambda_p=0.0, centre=None):
+    """A seeded sequence for the sliding-window recursion.  The first window is sampled
+    at accel_first (the first time instance is densely sampled, 50% by default) and every
+    appended frame at accel.  snr_db None gives noiseless data."""
+    r_bg, r_blob, r_mask, r_coil, r_noise, r_first = _rngs(seed, 6)
+    nf = nt + n_append
+    L, a = background(r_bg, nx, ny, nz, nf, rank)
+    peak = float(np.abs(L).max())
+    blobs = _make_blobs(r_blob, nx, ny, nz, nf, nblobs, nz > 1, peak)
+    S = np.stack([_render_blobs(blobs, t, nf, nx, ny, nz) for t in range(nf)])
+    scale = 1.0 / float(np.abs(L + S).max())
+    L *= scale
+    S *= scale
+    m = masks(r_mask, ny, nz, nf, accel, centre)
+    m[:nt] = masks(r_first, ny, nz, nt, accel_first, centre)
+    sens = coils(r_coil, nx, ny, nz, nc) if nc > 1 else None
+    d = sample(L + S, m, sens)
+    if snr_db is not None:
+        noise = _cgauss(r_noise, d.shape) * m[None, :, :, :, None]
+        noise *= np.linalg.norm(d) / (np.linalg.norm(noise) * 10 ** (snr_db / 20.0))
+        d = d + noise
+    return Sequence(nx=nx, ny=ny, nz=nz, nt=nt, nc=nc, n_append=n_append, kspace=d, mask=m,
+                    sens=sens, L_true=L, S_true=S, lambda_L=lambda_L, lambda_S=lambda_S,
+                    lambda_p=lambda_p)
