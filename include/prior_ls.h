@@ -218,6 +218,84 @@ int prior_ls_op_svt(prior_ls_handle *h, const void *C, void *L, double *sigma);
 /* Step (3): S = T^{-1} soft(T(Xm - Lp), lambda_S (1 - w)) with the handle's weights. */
 int prior_ls_op_sparse(prior_ls_handle *h, const void *Xm, const void *Lp, void *S);
 
+/* ---- Serving: continuous batching of recursive reconstructions (the priori L+S scheme of
+ * Section 3 / Fig. 2 applied to many sequences at once).
+ *
+ * A request is one sequence: its first window of nt frames is reconstructed by plain L+S
+ * (prior_ls_solve with no prior weights and lambda_p = 0), then n_append frames are appended
+ * one at a time (prior_ls_append).  The server runs up to max_active sequences at once, each
+ * on its own host worker and streams, so their kernels overlap on the GPU.  A request is
+ * admitted when the device bytes it needs (prior_ls_plan_bytes plus the compact k-space of
+ * its most sampled frame, in nt slots) fit in hbm_budget beside every resident handle.
+ * Handles of finished sequences stay resident and are reused by later requests of the same
+ * geometry; idle ones are destroyed, oldest first, when an admission needs their room.
+ * Among pending requests the oldest one that fits is admitted first.  Results do not depend
+ * on what else runs: every reduction has a fixed order.
+ * Threads: submit, wait and info may be called from any thread. ---- */
+typedef struct prior_ls_server prior_ls_server;
+
+typedef struct {
+    size_t   struct_size;       /* = sizeof(prior_ls_server_config) */
+    uint64_t hbm_budget;        /* device bytes for resident sequence state; 0 = 90% of the
+                                   free device memory at create */
+    int32_t  max_active;        /* sequences in flight at once, 1..64 */
+    int32_t  reserved;          /* must be 0 */
+} prior_ls_server_config;
+
+typedef struct {
+    size_t            struct_size;    /* = sizeof(prior_ls_request) */
+    prior_ls_dims     dims;           /* window geometry; dims.hbm_budget is ignored */
+    prior_ls_params   first;          /* first window (lambda_p is taken as 0) */
+    prior_ls_params   next;           /* every appended frame */
+    int32_t           n_append;       /* >= 0 */
+    int32_t           reserved;       /* must be 0 */
+    const void       *kspace0;        /* device complex64 [nc][nt][nz][ny][nx] */
+    const uint8_t    *mask0;          /* device uint8 [nt][nz][ny] */
+    const void       *kspace_frames;  /* device complex64 [n_append][nc][nz][ny][nx] */
+    const uint8_t    *mask_frames;    /* device uint8 [n_append][nz][ny] */
+    const void       *sens;           /* device complex64 [nc][nz][ny][nx]; NULL iff nc == 1 */
+    prior_ls_outputs  out;            /* the final window's outputs (device, NULL = skip) */
+    prior_ls_stats   *stats;          /* host [n_append + 1] per-window statistics, or NULL */
+    double           *latency_ms;     /* host [n_append + 1] per-window call latency, or NULL */
+} prior_ls_request;
+
+typedef struct {
+    size_t   struct_size;       /* = sizeof(prior_ls_result), set by the caller */
+    int32_t  status;            /* PRIOR_LS_OK or the error that ended the sequence */
+    int32_t  reused_plan;       /* 1 when a resident handle of the same geometry was reused */
+    double   queue_ms;          /* submit -> admission */
+    double   run_ms;            /* admission -> last window done */
+    double   total_ms;          /* submit -> last window done */
+    uint64_t state_bytes;       /* device bytes held while running */
+    char     message[160];      /* error message, "" on success */
+} prior_ls_result;
+
+typedef struct {
+    size_t   struct_size;       /* = sizeof(prior_ls_server_stats), set by the caller */
+    uint64_t budget, used, peak_used;   /* bytes: admission budget, resident now, peak */
+    int64_t  submitted, completed, failed, reused, evicted;
+    int32_t  queued, active, peak_active, resident_idle;
+} prior_ls_server_stats;
+
+/* Start the workers on the current HIP device.  EINVAL (bad config), EHIP (no device). */
+int prior_ls_server_create(const prior_ls_server_config *cfg, prior_ls_server **out);
+
+/* Queue a request; returns at once with a ticket.  Every array of the request must stay
+ * valid, and its contents ready (producing work complete), until prior_ls_server_wait
+ * returns for the ticket.  EINVAL (bad or host pointers, struct sizes), ESHAPE (dims),
+ * ENOMEM (the request alone exceeds the budget), EHIP. */
+int prior_ls_server_submit(prior_ls_server *s, const prior_ls_request *req, int64_t *ticket);
+
+/* Block until the request of `ticket` has finished, then fill *result and forget the ticket
+ * (each ticket is waited for once).  EINVAL for an unknown ticket. */
+int prior_ls_server_wait(prior_ls_server *s, int64_t ticket, prior_ls_result *result);
+
+/* Counters of the server (a consistent snapshot). */
+int prior_ls_server_info(prior_ls_server *s, prior_ls_server_stats *info);
+
+/* Finish every queued request, then release the workers and resident handles. */
+void prior_ls_server_destroy(prior_ls_server *s);
+
 #ifdef __cplusplus
 }
 #endif

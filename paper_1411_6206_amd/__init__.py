@@ -29,7 +29,8 @@ MAX_NT = 32
 EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destroy",
            "prior_ls_strerror", "prior_ls_last_error", "prior_ls_plan_bytes",
            "prior_ls_op_dc", "prior_ls_op_svt", "prior_ls_op_sparse", "prior_ls_step_timed",
-           "prior_ls_append")
+           "prior_ls_append", "prior_ls_server_create", "prior_ls_server_submit",
+           "prior_ls_server_wait", "prior_ls_server_info", "prior_ls_server_destroy")
 NKERNELS = 7
 KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats")
 
@@ -83,6 +84,34 @@ class Stats(C.Structure):
         return d
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("hbm_budget", C.c_uint64),
+                ("max_active", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("dims", Dims), ("first", Params), ("next", Params),
+                ("n_append", C.c_int32), ("reserved", C.c_int32),
+                ("kspace0", C.c_void_p), ("mask0", C.c_void_p),
+                ("kspace_frames", C.c_void_p), ("mask_frames", C.c_void_p),
+                ("sens", C.c_void_p), ("out", Outputs), ("stats", C.POINTER(Stats)),
+                ("latency_ms", C.POINTER(C.c_double))]
+
+
+class Result(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("status", C.c_int32), ("reused_plan", C.c_int32),
+                ("queue_ms", C.c_double), ("run_ms", C.c_double), ("total_ms", C.c_double),
+                ("state_bytes", C.c_uint64), ("message", C.c_char * 160)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("budget", C.c_uint64), ("used", C.c_uint64),
+                ("peak_used", C.c_uint64), ("submitted", C.c_int64), ("completed", C.c_int64),
+                ("failed", C.c_int64), ("reused", C.c_int64), ("evicted", C.c_int64),
+                ("queued", C.c_int32), ("active", C.c_int32), ("peak_active", C.c_int32),
+                ("resident_idle", C.c_int32)]
+
+
 _lib = None
 
 
@@ -122,6 +151,17 @@ def lib():
     L.prior_ls_append.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(Params),
                                   C.POINTER(Outputs), C.POINTER(Stats)]
     L.prior_ls_append.restype = C.c_int
+    S = C.c_void_p
+    L.prior_ls_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(S)]
+    L.prior_ls_server_create.restype = C.c_int
+    L.prior_ls_server_submit.argtypes = [S, C.POINTER(Request), C.POINTER(C.c_int64)]
+    L.prior_ls_server_submit.restype = C.c_int
+    L.prior_ls_server_wait.argtypes = [S, C.c_int64, C.POINTER(Result)]
+    L.prior_ls_server_wait.restype = C.c_int
+    L.prior_ls_server_info.argtypes = [S, C.POINTER(ServerStats)]
+    L.prior_ls_server_info.restype = C.c_int
+    L.prior_ls_server_destroy.argtypes = [S]
+    L.prior_ls_server_destroy.restype = None
     _lib = L
     return L
 
@@ -294,3 +334,92 @@ def to_device(problem, device="cuda"):
 
     return dict(kspace=c64(problem.kspace), mask=u8(problem.mask), sens=c64(problem.sens),
                 prior_w=u8(problem.prior_w))
+
+
+def make_params(lambda_L=0.01, lambda_S=0.01, lambda_p=0.0, lambda_L_relative=True, max_iter=20,
+                tol=0.0, check_every=10, use_graph=True):
+    return Params(C.sizeof(Params), float(lambda_L), float(lambda_S), float(lambda_p),
+                  float(tol), 1 if lambda_L_relative else 0, int(max_iter), int(check_every),
+                  1 if use_graph else 0)
+
+
+class Server:
+    """prior_ls_server_*: continuous batching of recursive reconstructions.
+
+    submit() queues one sequence (first window + appended frames, CUDA tensors) and returns
+    a ticket; the tensors are kept referenced until wait(ticket) returns its result."""
+
+    def __init__(self, hbm_budget=0, max_active=4):
+        self._s = C.c_void_p()
+        cfg = ServerConfig(C.sizeof(ServerConfig), int(hbm_budget), int(max_active), 0)
+        rc = lib().prior_ls_server_create(C.byref(cfg), C.byref(self._s))
+        if rc != OK:
+            raise PriorLSError(rc, "prior_ls_server_create")
+        self._live = {}
+
+    def submit(self, dims, kspace0, mask0, kspace_frames=None, mask_frames=None, sens=None,
+               first=None, append_params=None, outputs=("L", "S", "X", "M")):
+        """dims: a Dims (make_dims); kspace0 complex64 [nc][nt][nz][ny][nx], mask0 uint8
+        [nt][nz][ny], kspace_frames complex64 [n][nc][nz][ny][nx], mask_frames uint8
+        [n][nz][ny]; first / append_params: Params (make_params)."""
+        import torch
+        n = 0 if kspace_frames is None else int(kspace_frames.shape[0])
+        shape = (dims.nt, dims.nz, dims.ny, dims.nx)
+        outs = {k: torch.empty(shape, dtype=torch.complex64, device="cuda") for k in outputs}
+        stats = (Stats * (n + 1))()
+        for st in stats:
+            st.struct_size = C.sizeof(Stats)
+        lat = (C.c_double * (n + 1))()
+        req = Request(C.sizeof(Request), dims, first or make_params(max_iter=50),
+                      append_params or make_params(max_iter=20), n, 0,
+                      _ptr(kspace0), _ptr(mask0), _ptr(kspace_frames), _ptr(mask_frames),
+                      _ptr(sens), Outputs(*(_ptr(outs.get(k)) for k in ("L", "S", "X", "M"))),
+                      C.cast(stats, C.POINTER(Stats)), C.cast(lat, C.POINTER(C.c_double)))
+        torch.cuda.current_stream().synchronize()      # inputs ready before the workers run
+        t = C.c_int64()
+        rc = lib().prior_ls_server_submit(self._s, C.byref(req), C.byref(t))
+        if rc != OK:
+            raise PriorLSError(rc, "prior_ls_server_submit")
+        self._live[t.value] = (req, outs, stats, lat,
+                               (kspace0, mask0, kspace_frames, mask_frames, sens))
+        return t.value
+
+    def wait(self, ticket):
+        """Blocks until the request is done; returns (outputs, result dict)."""
+        r = Result()
+        r.struct_size = C.sizeof(Result)
+        rc = lib().prior_ls_server_wait(self._s, int(ticket), C.byref(r))
+        if rc != OK:
+            raise PriorLSError(rc, "prior_ls_server_wait")
+        req, outs, stats, lat, _ = self._live.pop(ticket)
+        res = {"status": r.status, "reused_plan": bool(r.reused_plan), "queue_ms": r.queue_ms,
+               "run_ms": r.run_ms, "total_ms": r.total_ms, "state_bytes": r.state_bytes,
+               "message": r.message.decode(), "latency_ms": list(lat),
+               "windows": [st.as_dict() for st in stats]}
+        return outs, res
+
+    def info(self):
+        st = ServerStats()
+        st.struct_size = C.sizeof(ServerStats)
+        rc = lib().prior_ls_server_info(self._s, C.byref(st))
+        if rc != OK:
+            raise PriorLSError(rc, "prior_ls_server_info")
+        return {k: getattr(st, k) for k, _ in st._fields_ if k != "struct_size"}
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            lib().prior_ls_server_destroy(self._s)
+            self._s = C.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -40,6 +40,64 @@ def test_struct_sizes_match_header():
     assert C.sizeof(pls.Stats) == 8 + 24 + 6 * 8 + 32 * 8 + 8
 
 
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    # sizeof and the offset of the last field of every ABI struct, as gcc lays them out
+    structs = {"prior_ls_dims": pls.Dims, "prior_ls_params": pls.Params,
+               "prior_ls_inputs": pls.Inputs, "prior_ls_outputs": pls.Outputs,
+               "prior_ls_stats": pls.Stats, "prior_ls_server_config": pls.ServerConfig,
+               "prior_ls_request": pls.Request, "prior_ls_result": pls.Result,
+               "prior_ls_server_stats": pls.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "prior_ls.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        last = py._fields_[-1][0]
+        lines.append(f'  printf("{cname} %zu %zu\\n", sizeof({cname}), offsetof({cname}, {last}));')
+    lines.append('  return 0; }')
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.strip().splitlines():
+        cname, size, off = line.split()
+        py = structs[cname]
+        assert C.sizeof(py) == int(size), cname
+        assert getattr(py, py._fields_[-1][0]).offset == int(off), cname
+
+
+def test_null_server_and_append_calls():
+    L = pls.lib()
+    L.prior_ls_server_destroy(None)
+    assert L.prior_ls_append(None, None, None, None, None, None) == pls.EINVAL
+    assert L.prior_ls_server_create(None, None) == pls.EINVAL
+    s = C.c_void_p()
+    assert L.prior_ls_server_create(None, C.byref(s)) == pls.EINVAL
+    bad = pls.ServerConfig(C.sizeof(pls.ServerConfig), 0, 0, 0)       # max_active 0
+    assert L.prior_ls_server_create(C.byref(bad), C.byref(s)) == pls.EINVAL
+    bad = pls.ServerConfig(C.sizeof(pls.ServerConfig) + 1, 0, 1, 0)   # struct_size
+    assert L.prior_ls_server_create(C.byref(bad), C.byref(s)) == pls.EINVAL
+    t = C.c_int64()
+    assert L.prior_ls_server_submit(None, None, C.byref(t)) == pls.EINVAL
+    r = pls.Result()
+    r.struct_size = C.sizeof(pls.Result)
+    assert L.prior_ls_server_wait(None, 1, C.byref(r)) == pls.EINVAL
+    st = pls.ServerStats()
+    st.struct_size = C.sizeof(pls.ServerStats)
+    assert L.prior_ls_server_info(None, C.byref(st)) == pls.EINVAL
+
+
+def test_server_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(pls.PriorLSError) as e:
+        pls.Server(max_active=2)
+    assert e.value.status == pls.EHIP
+
+
 def _create(**kw):
     base = dict(nx=64, ny=64, nz=1, nt=16, nc=1, wavelet_levels=2)
     base.update(kw)
