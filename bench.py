@@ -103,6 +103,132 @@ def cpu_baseline(p, frames):
                       f"{p.nt}/{frames}; numpy FFT single-threaded, LAPACK SVD threaded"}
 
 
+def serving_bench(budget_gib, forms):
+    """The serving stream (64 recursive reconstructions, Poisson arrivals) through the
+    library's server, once per form (max_active, gram_mode).  The k-space of every
+    (volume, frames, coils) class is formed once on the device from the class phantom and
+    coils (off-mask entries are ignored by the library, so requests of a class share it and
+    differ in their masks).  Returns the per-form throughput and latency percentiles."""
+    import queue
+    import threading
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1411_6206_amd as pls
+
+    cfg = synth.SERVING
+    reqs = synth.serving_requests()
+    napp = cfg["n_append"]
+    t0 = time.perf_counter()
+    nf_max = max(cfg["nts"]) + napp
+    X = {}
+    for vol in sorted({r[1] for r in reqs}):
+        nx, ny, nz = vol
+        L, S = synth.phantom(nx, ny, nz, nf_max, cfg["rank"][nx], cfg["nblobs"][nx],
+                             seed=synth.MASTER_SEED * 100 + nx)
+        X[vol] = torch.from_numpy((L + S).astype(np.complex64)).cuda()
+    data, sens = {}, {}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.MASTER_SEED)
+    for _, vol, nt, nc, _, _, _ in reqs:
+        if (vol, nt, nc) in data:
+            continue
+        nx, ny, nz = vol
+        if (vol, nc) not in sens:
+            sens[(vol, nc)] = None if nc == 1 else torch.from_numpy(
+                synth.coils(np.random.default_rng(nx * 100 + nc), nx, ny, nz, nc)
+                .astype(np.complex64)).cuda()
+        sc = sens[(vol, nc)]
+        x = X[vol][:nt + napp]
+        k = torch.empty((nc, nt + napp, nz, ny, nx), dtype=torch.complex64, device="cuda")
+        for c in range(nc):
+            k[c] = torch.fft.fftn(x if sc is None else x * sc[c], dim=(-3, -2, -1), norm="ortho")
+        noise = torch.randn(k.shape, dtype=torch.complex64, device="cuda", generator=gen)
+        k += noise * (torch.linalg.vector_norm(k) /
+                      (torch.linalg.vector_norm(noise) * 10 ** (cfg["snr_db"] / 20.0)))
+        del noise
+        data[(vol, nt, nc)] = (k[:, :nt].contiguous(), k[:, nt:].transpose(0, 1).contiguous(), sc)
+        del k
+    m0 = [torch.from_numpy(r[5]).cuda() for r in reqs]
+    mf = [torch.from_numpy(r[6]).cuda() for r in reqs]
+    # the reconstructed images X of every request, allocated up front: the submitting
+    # thread then makes no GPU call, the server's dispatcher is the only HIP caller
+    outx = [torch.empty((nt, v[2], v[1], v[0]), dtype=torch.complex64, device="cuda")
+            for _, v, nt, _, _, _, _ in reqs]
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    first = pls.make_params(max_iter=cfg["first_iters"], check_every=cfg["first_iters"] // 2)
+    nxt = pls.make_params(lambda_p=0.1, max_iter=cfg["append_iters"],
+                          check_every=cfg["append_iters"])
+    iters = cfg["first_iters"] + napp * cfg["append_iters"]
+    work = sum(v[0] * v[1] * v[2] * nt * nc * iters for _, v, nt, nc, _, _, _ in reqs)
+    out = {"workload": (f"{len(reqs)} recursive reconstructions, Poisson arrivals at "
+                        f"{cfg['rate_per_s']:g}/s, volumes {'/'.join('x'.join(map(str, v)) for v in cfg['volumes'])}"
+                        f" x {'/'.join(map(str, cfg['nts']))} frames x {'/'.join(map(str, cfg['ncs']))} coils, "
+                        f"first window 50% sampled + {napp} appended frames at 8-12x; "
+                        f"{cfg['first_iters']} + {napp} x {cfg['append_iters']} iterations each"),
+           "hbm_budget_bytes": int(budget_gib * (1 << 30)), "input_gen_s": gen_s, "forms": {}}
+    for max_active, mode in forms:
+        q = queue.Queue()
+        with pls.Server(hbm_budget=int(budget_gib * (1 << 30)), max_active=max_active) as srv:
+            start = time.perf_counter()
+
+            def submitter():
+                try:
+                    for i, (arr, vol, nt, nc, _, _, _) in enumerate(reqs):
+                        delay = start + arr - time.perf_counter()
+                        if delay > 0:
+                            time.sleep(delay)
+                        k0, kf, sc = data[(vol, nt, nc)]
+                        dims = pls.make_dims(*vol, nt, nc, 2, mode)
+                        sub = time.perf_counter()
+                        q.put((i, srv.submit(dims, k0, m0[i], kf, mf[i], sc, first=first,
+                                             append_params=nxt, out={"X": outx[i]},
+                                             sync=False), sub))
+                except Exception as e:          # handed to the waiting thread
+                    q.put((None, e, None))
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            lat_app, lat_first, total, queued, ends, bad = [], [], [], [], [], 0
+            for n_done in range(len(reqs)):
+                i, tk, sub = q.get(timeout=300)
+                if i is None:
+                    th.join()
+                    raise tk
+                outs, res = srv.wait(tk)
+                if (n_done + 1) % 16 == 0:
+                    print(f"[bench] serving {mode} x{max_active}: {n_done + 1} of {len(reqs)} done",
+                          file=sys.stderr, flush=True)
+                del outs
+                bad += res["status"] != pls.OK
+                lat_first.append(res["latency_ms"][0])
+                lat_app.extend(res["latency_ms"][1:])
+                total.append(res["total_ms"])
+                queued.append(res["queue_ms"])
+                ends.append(sub - start + res["total_ms"] * 1e-3)
+            th.join()
+            info = srv.info()
+        span = max(ends)
+        pct = lambda a, p: float(np.percentile(np.array(a), p))
+        out["forms"][f"{mode}_x{max_active}"] = {
+            "max_active": max_active, "gram_mode": mode, "failed": bad,
+            "makespan_s": span, "iterations_per_s": len(reqs) * iters / span,
+            "voxel_frame_coil_iterations_per_s": work / span,
+            "append_p50_ms": pct(lat_app, 50), "append_p99_ms": pct(lat_app, 99),
+            "first_window_p50_ms": pct(lat_first, 50), "first_window_p99_ms": pct(lat_first, 99),
+            "request_p50_ms": pct(total, 50), "request_p99_ms": pct(total, 99),
+            "queue_p50_ms": pct(queued, 50), "queue_p99_ms": pct(queued, 99),
+            "peak_resident_gib": info["peak_used"] / (1 << 30), "peak_active": info["peak_active"],
+            "plans_reused": info["reused"], "plans_evicted": info["evicted"]}
+        print(f"[bench] serving {mode} x{max_active}: {len(reqs) * iters / span:.0f} it/s, "
+              f"append p50 {pct(lat_app, 50):.1f} ms", file=sys.stderr, flush=True)
+    del data, X, sens, outx
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +242,8 @@ def main():
     ap.add_argument("--gram-mode", default="fp32", choices=("fp64", "fp32", "bf16x3"))
     ap.add_argument("--no-gram-modes", action="store_true",
                     help="skip the per-Gram-mode comparison (short profiling runs)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--serving-budget-gib", type=float, default=48.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -269,6 +397,10 @@ def main():
                                 f"committed FP64-oracle fixture") if fx is not None and modes else None
     del t
     torch.cuda.empty_cache()
+    if not args.no_serving:
+        # plain FP32 single-sequence form against the batched mixed-precision form
+        out["serving"] = serving_bench(args.serving_budget_gib,
+                                       forms=((1, "fp32"), (4, "fp32"), (4, "bf16x3")))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, min(args.cpu_frames, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

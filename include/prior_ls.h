@@ -184,7 +184,7 @@ void prior_ls_destroy(prior_ls_handle *h);
 const char *prior_ls_strerror(int status);
 
 /* Message of the last error on this handle ("" if none); NULL handle -> the last error of
- * a failed prior_ls_create on this thread. */
+ * a failed prior_ls_create or prior_ls_server_* call on this thread. */
 const char *prior_ls_last_error(const prior_ls_handle *h);
 
 /* Device bytes a handle of these dimensions allocates at create time (excluding the
@@ -223,8 +223,11 @@ int prior_ls_op_sparse(prior_ls_handle *h, const void *Xm, const void *Lp, void 
  *
  * A request is one sequence: its first window of nt frames is reconstructed by plain L+S
  * (prior_ls_solve with no prior weights and lambda_p = 0), then n_append frames are appended
- * one at a time (prior_ls_append).  The server runs up to max_active sequences at once, each
- * on its own host worker and streams, so their kernels overlap on the GPU.  A request is
+ * one at a time (prior_ls_append).  The server keeps up to max_active sequences in flight,
+ * each on its own handle and streams, so their kernels overlap on the GPU; one dispatcher
+ * thread drives them all (it enqueues chunks of iterations and polls their completion, so
+ * no sequence waits on another's GPU work and the HIP runtime is called from one thread).
+ * A request is
  * admitted when the device bytes it needs (prior_ls_plan_bytes plus the compact k-space of
  * its most sampled frame, in nt slots) fit in hbm_budget beside every resident handle.
  * Handles of finished sequences stay resident and are reused by later requests of the same
@@ -280,10 +283,12 @@ typedef struct {
 /* Start the workers on the current HIP device.  EINVAL (bad config), EHIP (no device). */
 int prior_ls_server_create(const prior_ls_server_config *cfg, prior_ls_server **out);
 
-/* Queue a request; returns at once with a ticket.  Every array of the request must stay
- * valid, and its contents ready (producing work complete), until prior_ls_server_wait
- * returns for the ticket.  EINVAL (bad or host pointers, struct sizes), ESHAPE (dims),
- * ENOMEM (the request alone exceeds the budget), EHIP. */
+/* Queue a request; returns at once with a ticket, without calling the HIP runtime.  Every
+ * array of the request must stay valid, and its contents ready (producing work complete),
+ * until prior_ls_server_wait returns for the ticket.  Returns EINVAL (NULL required array,
+ * struct sizes, n_append < 0) or ESHAPE (dims).  A request whose arrays are not device
+ * memory ends with status EINVAL in its result, one whose state alone exceeds the budget
+ * with ENOMEM. */
 int prior_ls_server_submit(prior_ls_server *s, const prior_ls_request *req, int64_t *ticket);
 
 /* Block until the request of `ticket` has finished, then fill *result and forget the ticket

@@ -354,18 +354,26 @@ class Server:
         cfg = ServerConfig(C.sizeof(ServerConfig), int(hbm_budget), int(max_active), 0)
         rc = lib().prior_ls_server_create(C.byref(cfg), C.byref(self._s))
         if rc != OK:
-            raise PriorLSError(rc, "prior_ls_server_create")
+            raise PriorLSError(rc, "prior_ls_server_create: " +
+                               lib().prior_ls_last_error(None).decode())
         self._live = {}
 
     def submit(self, dims, kspace0, mask0, kspace_frames=None, mask_frames=None, sens=None,
-               first=None, append_params=None, outputs=("L", "S", "X", "M")):
+               first=None, append_params=None, outputs=("L", "S", "X", "M"), out=None,
+               sync=True):
         """dims: a Dims (make_dims); kspace0 complex64 [nc][nt][nz][ny][nx], mask0 uint8
         [nt][nz][ny], kspace_frames complex64 [n][nc][nz][ny][nx], mask_frames uint8
-        [n][nz][ny]; first / append_params: Params (make_params)."""
-        import torch
+        [n][nz][ny]; first / append_params: Params (make_params).  out: preallocated output
+        tensors by name (else `outputs` are allocated).  sync: synchronize the current
+        stream first (the inputs must be complete before the server reads them); with
+        sync=False and `out` given, submit makes no GPU call at all."""
         n = 0 if kspace_frames is None else int(kspace_frames.shape[0])
-        shape = (dims.nt, dims.nz, dims.ny, dims.nx)
-        outs = {k: torch.empty(shape, dtype=torch.complex64, device="cuda") for k in outputs}
+        if out is None:
+            import torch
+            shape = (dims.nt, dims.nz, dims.ny, dims.nx)
+            outs = {k: torch.empty(shape, dtype=torch.complex64, device="cuda") for k in outputs}
+        else:
+            outs = dict(out)
         stats = (Stats * (n + 1))()
         for st in stats:
             st.struct_size = C.sizeof(Stats)
@@ -375,11 +383,14 @@ class Server:
                       _ptr(kspace0), _ptr(mask0), _ptr(kspace_frames), _ptr(mask_frames),
                       _ptr(sens), Outputs(*(_ptr(outs.get(k)) for k in ("L", "S", "X", "M"))),
                       C.cast(stats, C.POINTER(Stats)), C.cast(lat, C.POINTER(C.c_double)))
-        torch.cuda.current_stream().synchronize()      # inputs ready before the workers run
+        if sync:
+            import torch
+            torch.cuda.current_stream().synchronize()  # inputs ready before the server reads
         t = C.c_int64()
         rc = lib().prior_ls_server_submit(self._s, C.byref(req), C.byref(t))
         if rc != OK:
-            raise PriorLSError(rc, "prior_ls_server_submit")
+            raise PriorLSError(rc, "prior_ls_server_submit: " +
+                               lib().prior_ls_last_error(None).decode())
         self._live[t.value] = (req, outs, stats, lat,
                                (kspace0, mask0, kspace_frames, mask_frames, sens))
         return t.value

@@ -16,15 +16,23 @@
 
 #include "prior_ls.h"
 #include "pls_kernels.hpp"
+#include "pls_runtime_api.hpp"
 
 using pls::DcArgs;
+
+namespace {
+thread_local std::string g_create_error;
+}
+
+// Message of a failed call that has no handle (create, server calls) on this thread.
+namespace pls {
+void set_thread_error(const std::string& m) { g_create_error = m; }
+}
 
 namespace {
 
 constexpr int kStatRec = 64;          // doubles per iteration record
 constexpr int kMaxChunk = 1024;
-
-thread_local std::string g_create_error;
 
 struct HipError {
     hipError_t e;
@@ -140,6 +148,7 @@ struct prior_ls_handle {
     hipStream_t side = nullptr;      // second stream: the sparse update runs beside the
                                      // Gram / eigensolve / back-projection chain
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_chunk = nullptr;   // end of the last enqueued chunk / output write
     int device = 0;
     Sizes sz{};
     uint64_t owned = 0;
@@ -366,26 +375,44 @@ void run_chunk(prior_ls_handle* h, int n) {
     if (n % 2) h->cur = 1 - h->cur;
 }
 
+// Iterations run in chunks of at most check_every (one hipGraph replay each); after a chunk
+// its last statistics record is read back for the stopping rule.
+int chunk_size(const prior_ls_handle* h, int remaining) {
+    const int ce = std::max(1, std::min(h->params.check_every, kMaxChunk));
+    return std::min(ce, remaining);
+}
+
+// Enqueues m iterations and the read-back of their last statistics record, then records
+// ev_chunk on the handle's stream.
+void chunk_launch(prior_ls_handle* h, int m) {
+    run_chunk(h, m);
+    PLS_HIP(hipMemcpyAsync(h->stats_h, h->stats_d + (size_t)(m - 1) * kStatRec,
+                           kStatRec * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    PLS_HIP(hipEventRecord(h->ev_chunk, h->stream));
+}
+
+// Once ev_chunk has completed: takes the chunk's statistics; status (ENONFINITE possible).
+int chunk_finish(prior_ls_handle* h, int m, bool& converged) {
+    std::memcpy(h->last, h->stats_h, sizeof(h->last));
+    h->iters += m;
+    if (h->last[7] != 0.0) return fail(h, PRIOR_LS_ENONFINITE, "non-finite value in the iterate");
+    const double rel = h->last[2] > 0 ? std::sqrt(h->last[1] / h->last[2]) : INFINITY;
+    converged = h->params.tol > 0 && rel < h->params.tol;
+    return PRIOR_LS_OK;
+}
+
 // Runs n iterations in chunks; returns status (ENONFINITE possible), fills h->last.
 int iterate(prior_ls_handle* h, int n, bool& converged) {
     converged = false;
     int done = 0;
-    const int ce = std::max(1, std::min(h->params.check_every, kMaxChunk));
     while (done < n) {
-        const int m = std::min(ce, n - done);
-        run_chunk(h, m);
-        PLS_HIP(hipMemcpyAsync(h->stats_h, h->stats_d + (size_t)(m - 1) * kStatRec,
-                               kStatRec * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        PLS_HIP(hipStreamSynchronize(h->stream));
-        std::memcpy(h->last, h->stats_h, sizeof(h->last));
+        const int m = chunk_size(h, n - done);
+        chunk_launch(h, m);
+        PLS_HIP(hipEventSynchronize(h->ev_chunk));
         done += m;
-        h->iters += m;
-        if (h->last[7] != 0.0) return fail(h, PRIOR_LS_ENONFINITE, "non-finite value in the iterate");
-        const double rel = h->last[2] > 0 ? std::sqrt(h->last[1] / h->last[2]) : INFINITY;
-        if (h->params.tol > 0 && rel < h->params.tol) {
-            converged = true;
-            break;
-        }
+        const int r = chunk_finish(h, m, converged);
+        if (r) return r;
+        if (converged) break;
     }
     return PRIOR_LS_OK;
 }
@@ -610,7 +637,143 @@ bool same_captured_params(const prior_ls_params& a, const prior_ls_params& b) {
            a.lambda_L_relative == b.lambda_L_relative && a.use_graph == b.use_graph;
 }
 
+// The new window of an append (the sliding-window recursion): masks and sample lists
+// shifted, the new frame's compact k-space in the dropped frame's slot, L and S shifted as
+// the warm start, the previous window's support and singular values as priors, and the
+// warm start's data-consistency step.  Blocks only for the new frame's sample count.
+int shift_window(prior_ls_handle* h, const void* kspace_frame, const uint8_t* mask_frame,
+                 const prior_ls_params* params) {
+    const prior_ls_dims& d = h->d;
+    const Sizes& sz = h->sz;
+    const int nt = d.nt;
+    const size_t P = sz.P, N = sz.N;
+    hipStream_t s = h->stream;
+    // masks of the new window: frames 1..nt-1, then the new one
+    if (nt > 1)
+        PLS_HIP(hipMemcpyAsync(h->mask_tmp, h->mask_d + P, (nt - 1) * P, hipMemcpyDeviceToDevice, s));
+    PLS_HIP(hipMemcpyAsync(h->mask_tmp + (nt - 1) * P, mask_frame, P, hipMemcpyDeviceToDevice, s));
+    std::swap(h->mask_d, h->mask_tmp);
+    pls::launch_mask_scan(h->mask_d, d.ny, d.nz, nt, h->sidx, h->plist, h->ns, s);
+    PLS_HIP(hipGetLastError());
+    int ns_new = 0;
+    PLS_HIP(hipMemcpyAsync(&ns_new, h->ns + (nt - 1), sizeof(int), hipMemcpyDeviceToHost, s));
+    PLS_HIP(hipStreamSynchronize(s));
+    // the new frame takes the slot of the dropped one
+    const size_t need = (size_t)d.nx * d.nc * ns_new;
+    if (need * nt > (size_t)INT32_MAX) return fail(h, PRIOR_LS_ESHAPE, "sampled data exceed 2^31 entries");
+    if (need > h->slot_cap) {
+        try {
+            grow_slots(h, need);
+        } catch (const std::bad_alloc&) {
+            return fail(h, PRIOR_LS_ENOMEM, "cannot grow the compact k-space (hbm_budget or device memory)");
+        }
+    }
+    std::rotate(h->slot_of.begin(), h->slot_of.begin() + 1, h->slot_of.end());
+    std::vector<int> off(nt);
+    for (int t = 0; t < nt; ++t) off[t] = (int)(h->slot_of[t] * h->slot_cap);
+    const int loff[2] = {0, d.nc * ns_new};
+    PLS_HIP(hipMemcpyAsync(h->dh_off, off.data(), nt * sizeof(int), hipMemcpyHostToDevice, s));
+    PLS_HIP(hipMemcpyAsync(h->line_off, loff, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+    // kx inverse DFT of the new frame's sampled lines into its slot
+    pls::XiArgs xa{};
+    xa.kspace = (const float2*)kspace_frame;
+    xa.plist = h->plist + (size_t)(nt - 1) * P;
+    xa.line_off = h->line_off;
+    xa.ns = h->ns + (nt - 1);
+    xa.dh_off = h->dh_off + (nt - 1);
+    xa.dh = h->dh;
+    xa.twx = h->twx;
+    xa.nx = d.nx;
+    xa.nt = 1;
+    xa.nc = d.nc;
+    xa.P = (int)P;
+    xa.total_lines = loff[1];
+    xa.scale = (float)(1.0 / std::sqrt((double)d.nx * (double)P));
+    pls::launch_xifft(d.nx, xa, s);
+    // warm start: L and S shifted by one frame, the new frame from the previous newest
+    const int p = h->cur, q = 1 - p;
+    const size_t fb = N * sizeof(float2);
+    for (float2** A : {h->L, h->S}) {
+        if (nt > 1)
+            PLS_HIP(hipMemcpyAsync(A[q], A[p] + N, (nt - 1) * fb, hipMemcpyDeviceToDevice, s));
+        PLS_HIP(hipMemcpyAsync(A[q] + (nt - 1) * N, A[p] + (nt - 1) * N, fb, hipMemcpyDeviceToDevice, s));
+    }
+    h->cur = q;
+    // a-priori knowledge: support of T(S) shifted the same way, singular values of L
+    if (nt > 1) PLS_HIP(hipMemcpyAsync(h->w, h->supp + N, (nt - 1) * N, hipMemcpyDeviceToDevice, s));
+    PLS_HIP(hipMemcpyAsync(h->w + (nt - 1) * N, h->supp + (nt - 1) * N, N, hipMemcpyDeviceToDevice, s));
+    PLS_HIP(hipMemcpyAsync(h->sigma_prev, h->sigL, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (!h->has_w || !same_captured_params(h->params, *params)) h->clear_graphs();
+    h->has_w = true;
+    h->params = *params;
+    set_identity_V(h, h->V);
+    // step (0) of the new window: one data-consistency step from Y = L + S
+    DcArgs da = dc_args(h, h->L[h->cur], h->S[h->cur], h->C);
+    pls::launch_dc(d.ny, d.nz, false, da, s);
+    PLS_HIP(hipGetLastError());
+    h->iters = 0;
+    std::memset(h->last, 0, sizeof(h->last));
+    return PRIOR_LS_OK;
+}
+
 }  // namespace
+
+namespace pls {
+
+int phase_load(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* p) {
+    h->err.clear();
+    const int rc = check_params(h, p);
+    if (rc) return rc;
+    return guarded(h, [&]() -> int { return load_problem(h, in, p); });
+}
+
+int phase_shift(prior_ls_handle* h, const void* kspace_frame, const uint8_t* mask_frame,
+                const prior_ls_params* p) {
+    h->err.clear();
+    if (!h->loaded) return fail(h, PRIOR_LS_EINVAL, "append before solve");
+    const int rc = check_params(h, p);
+    if (rc) return rc;
+    return guarded(h, [&]() -> int { return shift_window(h, kspace_frame, mask_frame, p); });
+}
+
+int phase_chunk_launch(prior_ls_handle* h, int remaining) {
+    return guarded(h, [&]() -> int {
+        const int m = chunk_size(h, remaining);
+        chunk_launch(h, m);
+        return m;
+    });
+}
+
+int phase_query(prior_ls_handle* h) {
+    const hipError_t e = hipEventQuery(h->ev_chunk);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    (void)hipGetLastError();
+    return fail(h, PRIOR_LS_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+}
+
+int phase_chunk_finish(prior_ls_handle* h, int m, int* converged) {
+    bool c = false;
+    const int r = chunk_finish(h, m, c);
+    *converged = c ? 1 : 0;
+    return r;
+}
+
+int phase_outputs(prior_ls_handle* h, const prior_ls_outputs* out) {
+    return guarded(h, [&]() -> int {
+        write_outputs(h, out);
+        PLS_HIP(hipEventRecord(h->ev_chunk, h->stream));
+        return PRIOR_LS_OK;
+    });
+}
+
+void phase_stats(prior_ls_handle* h, prior_ls_stats* st, int converged, double ms) {
+    fill_stats(h, st, converged != 0, ms);
+}
+
+int phase_max_iter(const prior_ls_handle* h) { return h->params.max_iter; }
+
+}  // namespace pls
 
 extern "C" {
 
@@ -671,6 +834,7 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
         PLS_HIP(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&h->ev_chunk, hipEventDisableTiming));
         const prior_ls_dims& d = h->d;
         h->C = h->alloc<float2>(sz.I * sizeof(float2));
         for (int k = 0; k < 2; ++k) {
@@ -728,6 +892,7 @@ void prior_ls_destroy(prior_ls_handle* h) {
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_chunk) (void)hipEventDestroy(h->ev_chunk);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -816,82 +981,14 @@ int prior_ls_append(prior_ls_handle* h, const void* kspace_frame, const uint8_t*
             if (p && !is_device_ptr(p)) return fail(h, PRIOR_LS_EINVAL, "output array is not device memory");
     }
     return guarded(h, [&]() -> int {
-        const prior_ls_dims& d = h->d;
-        const Sizes& sz = h->sz;
-        const int nt = d.nt;
-        const size_t P = sz.P, N = sz.N;
-        hipStream_t s = h->stream;
         enter(h);
-        // masks of the new window: frames 1..nt-1, then the new one
-        if (nt > 1)
-            PLS_HIP(hipMemcpyAsync(h->mask_tmp, h->mask_d + P, (nt - 1) * P, hipMemcpyDeviceToDevice, s));
-        PLS_HIP(hipMemcpyAsync(h->mask_tmp + (nt - 1) * P, mask_frame, P, hipMemcpyDeviceToDevice, s));
-        std::swap(h->mask_d, h->mask_tmp);
-        pls::launch_mask_scan(h->mask_d, d.ny, d.nz, nt, h->sidx, h->plist, h->ns, s);
-        PLS_HIP(hipGetLastError());
-        int ns_new = 0;
-        PLS_HIP(hipMemcpyAsync(&ns_new, h->ns + (nt - 1), sizeof(int), hipMemcpyDeviceToHost, s));
-        PLS_HIP(hipStreamSynchronize(s));
-        // the new frame takes the slot of the dropped one
-        const size_t need = (size_t)d.nx * d.nc * ns_new;
-        if (need * nt > (size_t)INT32_MAX) return fail(h, PRIOR_LS_ESHAPE, "sampled data exceed 2^31 entries");
-        if (need > h->slot_cap) {
-            try {
-                grow_slots(h, need);
-            } catch (const std::bad_alloc&) {
-                return fail(h, PRIOR_LS_ENOMEM, "cannot grow the compact k-space (hbm_budget or device memory)");
-            }
-        }
-        std::rotate(h->slot_of.begin(), h->slot_of.begin() + 1, h->slot_of.end());
-        std::vector<int> off(nt);
-        for (int t = 0; t < nt; ++t) off[t] = (int)(h->slot_of[t] * h->slot_cap);
-        const int loff[2] = {0, d.nc * ns_new};
-        PLS_HIP(hipMemcpyAsync(h->dh_off, off.data(), nt * sizeof(int), hipMemcpyHostToDevice, s));
-        PLS_HIP(hipMemcpyAsync(h->line_off, loff, 2 * sizeof(int), hipMemcpyHostToDevice, s));
-        // kx inverse DFT of the new frame's sampled lines into its slot
-        pls::XiArgs xa{};
-        xa.kspace = (const float2*)kspace_frame;
-        xa.plist = h->plist + (size_t)(nt - 1) * P;
-        xa.line_off = h->line_off;
-        xa.ns = h->ns + (nt - 1);
-        xa.dh_off = h->dh_off + (nt - 1);
-        xa.dh = h->dh;
-        xa.twx = h->twx;
-        xa.nx = d.nx;
-        xa.nt = 1;
-        xa.nc = d.nc;
-        xa.P = (int)P;
-        xa.total_lines = loff[1];
-        xa.scale = (float)(1.0 / std::sqrt((double)d.nx * (double)P));
-        pls::launch_xifft(d.nx, xa, s);
-        // warm start: L and S shifted by one frame, the new frame from the previous newest
-        const int p = h->cur, q = 1 - p;
-        const size_t fb = N * sizeof(float2);
-        for (float2** A : {h->L, h->S}) {
-            if (nt > 1)
-                PLS_HIP(hipMemcpyAsync(A[q], A[p] + N, (nt - 1) * fb, hipMemcpyDeviceToDevice, s));
-            PLS_HIP(hipMemcpyAsync(A[q] + (nt - 1) * N, A[p] + (nt - 1) * N, fb, hipMemcpyDeviceToDevice, s));
-        }
-        h->cur = q;
-        // a-priori knowledge: support of T(S) shifted the same way, singular values of L
-        if (nt > 1) PLS_HIP(hipMemcpyAsync(h->w, h->supp + N, (nt - 1) * N, hipMemcpyDeviceToDevice, s));
-        PLS_HIP(hipMemcpyAsync(h->w + (nt - 1) * N, h->supp + (nt - 1) * N, N, hipMemcpyDeviceToDevice, s));
-        PLS_HIP(hipMemcpyAsync(h->sigma_prev, h->sigL, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
-        if (!h->has_w || !same_captured_params(h->params, *params)) h->clear_graphs();
-        h->has_w = true;
-        h->params = *params;
-        set_identity_V(h, h->V);
-        // step (0) of the new window: one data-consistency step from Y = L + S
-        DcArgs da = dc_args(h, h->L[h->cur], h->S[h->cur], h->C);
-        pls::launch_dc(d.ny, d.nz, false, da, s);
-        PLS_HIP(hipGetLastError());
-        h->iters = 0;
-        std::memset(h->last, 0, sizeof(h->last));
+        int r = shift_window(h, kspace_frame, mask_frame, params);
+        if (r) return r;
         bool conv = false;
-        const int r = iterate(h, params->max_iter, conv);
+        r = iterate(h, params->max_iter, conv);
         write_outputs(h, out);
         leave(h);
-        PLS_HIP(hipStreamSynchronize(s));
+        PLS_HIP(hipStreamSynchronize(h->stream));
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         fill_stats(h, stats, conv, ms);
         return r;

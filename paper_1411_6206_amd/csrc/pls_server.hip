@@ -1,19 +1,22 @@
 // Serving runtime: continuous batching of recursive (sliding-window) reconstructions.
 //
 // A request is one sequence: a first window of nt frames reconstructed by plain L+S, then
-// n_append frames appended one at a time (prior_ls_append).  The server runs up to
-// max_active sequences at once, each driven by its own host worker on its own streams, so
-// their kernels share the GPU.  A request is admitted when the device bytes it needs fit
-// in the budget beside everything resident; handles of finished sequences stay resident
-// (state, sample store, graphs) and are reused by later requests of the same geometry,
-// and idle ones are evicted (oldest first) when an admission needs their room.  Pending
-// requests are admitted oldest first among those that fit, so a small request is not held
-// behind a large one that is waiting for memory.
+// n_append frames appended one at a time.  Up to max_active sequences are in flight at
+// once, each on its own handle and streams, so their kernels share the GPU.  One host
+// thread (the dispatcher) drives all of them: it starts a window, enqueues chunks of
+// iterations without waiting, polls their completion, and moves each sequence on as its
+// work finishes, so the HIP runtime is called from a single thread.  A request is
+// admitted when the device bytes it needs fit in the budget beside everything resident;
+// handles of finished sequences stay resident (state, sample store, graphs) and are
+// reused by later requests of the same geometry, and idle ones are evicted (oldest first)
+// when an admission needs their room.  Pending requests are admitted oldest first among
+// those that fit, so a small request is not held behind a large one waiting for memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <list>
@@ -24,8 +27,18 @@
 #include <vector>
 
 #include "prior_ls.h"
+#include "pls_runtime_api.hpp"
+
+namespace pls {
+void set_thread_error(const std::string& m);
+}
 
 namespace {
+
+int fail(int code, const std::string& m) {
+    pls::set_thread_error(m);
+    return code;
+}
 
 using Clock = std::chrono::steady_clock;
 
@@ -69,6 +82,18 @@ struct Job {
     prior_ls_result result{};
 };
 
+// A sequence in flight: its window, the iterations left in the window and the chunk on the
+// GPU, if any.
+struct Active {
+    Job* j = nullptr;
+    enum State { kStart, kRun, kOutputs } st = kStart;
+    int window = 0;
+    int remaining = 0;
+    int inflight = 0;
+    int converged = 0;
+    Clock::time_point wstart{};
+};
+
 void set_message(prior_ls_result& r, const std::string& m) {
     std::snprintf(r.message, sizeof(r.message), "%s", m.c_str());
 }
@@ -81,7 +106,8 @@ struct prior_ls_server {
     uint64_t budget = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<Job*> pending;                 // submission order
+    std::deque<Job*> incoming;                // submitted, not yet checked by the dispatcher
+    std::deque<Job*> pending;                 // checked, waiting for admission (submission order)
     std::map<int64_t, Job*> jobs;             // every job not yet waited for
     std::list<Resident> idle;                 // resident handles without a sequence
     uint64_t used = 0;                        // bytes of running + idle residents
@@ -90,7 +116,8 @@ struct prior_ls_server {
     int64_t submitted = 0, completed = 0, failed = 0, reused = 0, evicted = 0;
     int active = 0, peak_active = 0;
     bool stopping = false;
-    std::vector<std::thread> workers;
+    std::thread thread;                       // the dispatcher
+    hipStream_t ctl = nullptr;                // the dispatcher's mask read-backs
 
     // Picks the oldest pending job that fits (reusing an idle handle of its geometry, or
     // evicting idle handles to make room); returns nullptr when none fits.  The handles to
@@ -150,98 +177,247 @@ struct prior_ls_server {
         r = Resident{};
     }
 
-    void run(Job* j) {
-        prior_ls_request& q = j->req;
-        prior_ls_result& res = j->result;
-        const int nw = q.n_append + 1;
-        int rc = PRIOR_LS_OK;
-        if (!j->res.h) {
-            prior_ls_dims d = q.dims;
-            d.hbm_budget = 0;                  // admission is the server's
-            if (hipStreamCreateWithFlags(&j->res.stream, hipStreamNonBlocking) != hipSuccess) {
-                (void)hipGetLastError();
-                rc = PRIOR_LS_EHIP;
-                set_message(res, "cannot create a stream");
-            } else {
-                rc = prior_ls_create(&d, j->res.stream, &j->res.h);
-                if (rc) set_message(res, prior_ls_last_error(nullptr));
-            }
-            j->res.dims = q.dims;
+    // Checks a submitted job on the dispatcher thread (device pointers) and sizes it: the
+    // plan plus the compact k-space, one slot per frame sized by its most sampled frame.
+    int prepare(Job* j) {
+        const prior_ls_request& q = j->req;
+        const prior_ls_dims& d = q.dims;
+        if (!on_device(q.kspace0) || !on_device(q.mask0) || (d.nc > 1 && !on_device(q.sens)) ||
+            (q.n_append > 0 && (!on_device(q.kspace_frames) || !on_device(q.mask_frames)))) {
+            set_message(j->result, "input arrays must be device memory");
+            return PRIOR_LS_EINVAL;
         }
-        const prior_ls_outputs none{nullptr, nullptr, nullptr, nullptr};
-        for (int w = 0; w < nw && rc == PRIOR_LS_OK; ++w) {
-            const bool last = w == nw - 1;
-            const prior_ls_outputs* out = last ? &q.out : &none;
+        const void* o[] = {q.out.L, q.out.S, q.out.X, q.out.M};
+        for (const void* p : o)
+            if (p && !on_device(p)) {
+                set_message(j->result, "output arrays must be device memory");
+                return PRIOR_LS_EINVAL;
+            }
+        const size_t P = (size_t)d.ny * d.nz;
+        const size_t nf = (size_t)d.nt + q.n_append;
+        std::vector<uint8_t> m(nf * P);
+        hipError_t e = hipMemcpyAsync(m.data(), q.mask0, d.nt * P, hipMemcpyDeviceToHost, ctl);
+        if (e == hipSuccess && q.n_append > 0)
+            e = hipMemcpyAsync(m.data() + d.nt * P, q.mask_frames, q.n_append * P,
+                               hipMemcpyDeviceToHost, ctl);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctl);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_message(j->result, std::string("reading the masks: ") + hipGetErrorString(e));
+            return PRIOR_LS_EHIP;
+        }
+        size_t ns_max = 1;
+        for (size_t f = 0; f < nf; ++f) {
+            size_t c = 0;
+            for (size_t k = 0; k < P; ++k) c += m[f * P + k] != 0;
+            ns_max = std::max(ns_max, c);
+        }
+        j->need = prior_ls_plan_bytes(&d) + ((uint64_t)d.nt * d.nx * d.nc * ns_max + 64) * 8;
+        if (j->need > budget) {
+            set_message(j->result, "the request alone exceeds the server budget");
+            return PRIOR_LS_ENOMEM;
+        }
+        return PRIOR_LS_OK;
+    }
+
+    // A job that ends before admission (under the lock).
+    void reject_locked(Job* j, int status) {
+        j->result.status = status;
+        j->result.total_ms = ms_between(j->submitted, Clock::now());
+        ++failed;
+        j->done = true;
+    }
+
+    // Creates the handle of a newly admitted job when no resident one was reused.
+    int open_handle(Job* j) {
+        if (j->res.h) return PRIOR_LS_OK;
+        prior_ls_dims d = j->req.dims;
+        d.hbm_budget = 0;                      // admission is the server's
+        if (hipStreamCreateWithFlags(&j->res.stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            set_message(j->result, "cannot create a stream");
+            return PRIOR_LS_EHIP;
+        }
+        j->res.dims = j->req.dims;
+        const int rc = prior_ls_create(&d, j->res.stream, &j->res.h);
+        if (rc) set_message(j->result, prior_ls_last_error(nullptr));
+        return rc;
+    }
+
+    // Ends window a.window: records its statistics and latency.
+    void close_window(Active& a) {
+        prior_ls_request& q = a.j->req;
+        const double ms = ms_between(a.wstart, Clock::now());
+        if (q.latency_ms) q.latency_ms[a.window] = ms;
+        if (q.stats) {
             prior_ls_stats st{};
             st.struct_size = sizeof(prior_ls_stats);
-            const auto t0 = Clock::now();
-            if (w == 0) {
+            pls::phase_stats(a.j->res.h, &st, a.converged, ms);
+            q.stats[a.window] = st;
+        }
+    }
+
+    // Moves one sequence on as far as it can go without waiting.  Returns 1 on progress,
+    // 0 when it waits for the GPU, or a negative status (the sequence has failed).
+    int advance(Active& a) {
+        Job* j = a.j;
+        prior_ls_request& q = j->req;
+        prior_ls_handle* h = j->res.h;
+        const bool last = a.window == q.n_append;
+        if (a.st == Active::kStart) {
+            a.wstart = Clock::now();
+            a.converged = 0;
+            int rc;
+            if (a.window == 0) {
                 prior_ls_inputs in{};
                 in.kspace = q.kspace0;
                 in.mask = q.mask0;
                 in.sens = q.sens;
                 prior_ls_params p = q.first;
                 p.lambda_p = 0.0;                  // the first instance has no priors
-                rc = prior_ls_solve(j->res.h, &in, &p, out, &st);
+                rc = pls::phase_load(h, &in, &p);
             } else {
                 const size_t P = (size_t)q.dims.ny * q.dims.nz;
                 const size_t fk = (size_t)q.dims.nc * P * q.dims.nx * 8;
-                rc = prior_ls_append(j->res.h, (const char*)q.kspace_frames + (w - 1) * fk,
-                                     q.mask_frames + (w - 1) * P, &q.next, out, &st);
+                rc = pls::phase_shift(h, (const char*)q.kspace_frames + (a.window - 1) * fk,
+                                      q.mask_frames + (a.window - 1) * P, &q.next);
             }
-            const double ms = ms_between(t0, Clock::now());
-            if (q.latency_ms) q.latency_ms[w] = ms;
-            if (q.stats) q.stats[w] = st;
-            if (rc) set_message(res, prior_ls_last_error(j->res.h));
+            if (rc) return rc;
+            a.remaining = pls::phase_max_iter(h);
+            a.inflight = 0;
+            a.st = Active::kRun;
         }
-        res.status = rc;
+        if (a.st == Active::kRun) {
+            if (a.inflight) {
+                const int r = pls::phase_query(h);
+                if (r <= 0) return r;
+                const int rc = pls::phase_chunk_finish(h, a.inflight, &a.converged);
+                if (rc) return rc;
+                a.remaining -= a.inflight;
+                a.inflight = 0;
+            }
+            if (a.remaining > 0 && !a.converged) {
+                const int m = pls::phase_chunk_launch(h, a.remaining);
+                if (m < 0) return m;
+                a.inflight = m;
+                return 1;
+            }
+            if (!last) {
+                close_window(a);
+                ++a.window;
+                a.st = Active::kStart;
+                return 1;
+            }
+            const int rc = pls::phase_outputs(h, &q.out);
+            if (rc) return rc;
+            a.st = Active::kOutputs;
+            return 1;
+        }
+        // kOutputs
+        const int r = pls::phase_query(h);
+        if (r <= 0) return r;
+        close_window(a);
+        return 2;                                 // done
     }
 
-    void worker() {
+    // Ends a job (under the lock): its handle goes to the idle pool, or is destroyed
+    // (returned through `destroy`) when the sequence failed.
+    void finish_locked(Job* j, int status, std::vector<Resident>& destroy) {
+        const auto now = Clock::now();
+        j->result.status = status;
+        if (status && j->res.h && !j->result.message[0])
+            set_message(j->result, prior_ls_last_error(j->res.h));
+        j->result.reused_plan = j->reused ? 1 : 0;
+        j->result.queue_ms = ms_between(j->submitted, j->admitted);
+        j->result.run_ms = ms_between(j->admitted, now);
+        j->result.total_ms = ms_between(j->submitted, now);
+        j->result.state_bytes = j->res.bytes;
+        if (j->reused) ++reused;
+        if (status == PRIOR_LS_OK && j->res.h) {
+            j->res.idle_since = now;
+            idle.push_back(j->res);
+            ++completed;
+        } else {
+            used -= j->res.bytes;
+            destroy.push_back(j->res);
+            ++failed;
+        }
+        j->res = Resident{};
+        --active;
+        j->done = true;
+    }
+
+    void dispatcher() {
         (void)hipSetDevice(device);
-        std::unique_lock<std::mutex> lk(mu);
+        std::vector<Active> act;
         for (;;) {
-            std::vector<Resident> evict;
-            Job* j = nullptr;
-            cv_work.wait(lk, [&] {
-                if (!pending.empty()) {
-                    j = admit_locked(evict);
-                    if (j) return true;
-                }
-                return stopping && pending.empty();
-            });
-            if (!j) return;
-            ++active;
-            peak_active = std::max(peak_active, active);
-            j->admitted = Clock::now();
-            lk.unlock();
-            for (Resident& r : evict) destroy_resident(r);
-            run(j);
-            lk.lock();
-            --active;
-            const auto now = Clock::now();
-            j->result.reused_plan = j->reused ? 1 : 0;
-            j->result.queue_ms = ms_between(j->submitted, j->admitted);
-            j->result.run_ms = ms_between(j->admitted, now);
-            j->result.total_ms = ms_between(j->submitted, now);
-            j->result.state_bytes = j->res.bytes;
-            if (j->reused) ++reused;
-            if (j->result.status == PRIOR_LS_OK && j->res.h) {
-                j->res.idle_since = now;
-                idle.push_back(j->res);
-                ++completed;
-            } else {
-                used -= j->res.bytes;
-                Resident r = j->res;
-                lk.unlock();
-                destroy_resident(r);
-                lk.lock();
-                ++failed;
+            std::vector<Resident> evict, destroy;
+            std::vector<Job*> admitted, fresh;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                fresh.assign(incoming.begin(), incoming.end());
+                incoming.clear();
             }
-            j->res = Resident{};
-            j->done = true;
-            cv_done.notify_all();
-            cv_work.notify_all();                 // memory or a slot freed up
+            for (Job* j : fresh) {
+                const int rc = prepare(j);
+                std::lock_guard<std::mutex> lk(mu);
+                if (rc) {
+                    reject_locked(j, rc);
+                    cv_done.notify_all();
+                } else {
+                    pending.push_back(j);
+                }
+            }
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                for (;;) {
+                    while ((int)(act.size() + admitted.size()) < cfg.max_active) {
+                        Job* j = admit_locked(evict);
+                        if (!j) break;
+                        j->admitted = Clock::now();
+                        admitted.push_back(j);
+                        ++active;
+                        peak_active = std::max(peak_active, active);
+                    }
+                    if (!act.empty() || !admitted.empty() || !incoming.empty()) break;
+                    if (stopping && pending.empty()) return;
+                    cv_work.wait(lk);             // a submission, or the stop
+                }
+            }
+            for (Resident& r : evict) destroy_resident(r);
+            for (Job* j : admitted) {
+                Active a;
+                a.j = j;
+                const int rc = open_handle(j);
+                if (rc) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    finish_locked(j, rc, destroy);
+                    cv_done.notify_all();
+                    continue;
+                }
+                act.push_back(a);
+            }
+            bool progress = false;
+            for (size_t i = 0; i < act.size();) {
+                int r = advance(act[i]);
+                while (r == 1) {                          // as far as it goes without waiting
+                    progress = true;
+                    r = advance(act[i]);
+                }
+                if (r == 0) {
+                    ++i;
+                    continue;
+                }
+                progress = true;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    finish_locked(act[i].j, r == 2 ? PRIOR_LS_OK : r, destroy);
+                }
+                cv_done.notify_all();
+                act.erase(act.begin() + i);
+            }
+            for (Resident& r : destroy) destroy_resident(r);
+            if (!progress && admitted.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
     }
 };
@@ -275,58 +451,42 @@ int prior_ls_server_create(const prior_ls_server_config* cfg, prior_ls_server** 
         }
         s->budget = (uint64_t)(0.9 * (double)fr);
     }
-    for (int i = 0; i < cfg->max_active; ++i) s->workers.emplace_back([s] { s->worker(); });
+    if (hipStreamCreateWithFlags(&s->ctl, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return fail(PRIOR_LS_EHIP, "cannot create the control stream");
+    }
+    s->thread = std::thread([s] { s->dispatcher(); });
     *out = s;
     return PRIOR_LS_OK;
 }
 
 int prior_ls_server_submit(prior_ls_server* s, const prior_ls_request* req, int64_t* ticket) {
-    if (!s || !req || !ticket) return PRIOR_LS_EINVAL;
-    if (req->struct_size != sizeof(prior_ls_request)) return PRIOR_LS_EINVAL;
+    if (!s || !req || !ticket) return fail(PRIOR_LS_EINVAL, "server, request and ticket are required");
+    if (req->struct_size != sizeof(prior_ls_request)) return fail(PRIOR_LS_EINVAL, "request.struct_size mismatch");
     const prior_ls_dims& d = req->dims;
-    if (d.struct_size != sizeof(prior_ls_dims)) return PRIOR_LS_EINVAL;
-    const uint64_t plan = prior_ls_plan_bytes(&d);
-    if (plan == 0) return PRIOR_LS_ESHAPE;
+    if (d.struct_size != sizeof(prior_ls_dims)) return fail(PRIOR_LS_EINVAL, "dims.struct_size mismatch");
+    if (prior_ls_plan_bytes(&d) == 0) return fail(PRIOR_LS_ESHAPE, "unsupported dims");
     if (req->first.struct_size != sizeof(prior_ls_params) ||
         req->next.struct_size != sizeof(prior_ls_params))
-        return PRIOR_LS_EINVAL;
-    if (req->n_append < 0 || req->reserved != 0) return PRIOR_LS_EINVAL;
-    if (!on_device(req->kspace0) || !on_device(req->mask0)) return PRIOR_LS_EINVAL;
-    if (d.nc > 1 && !on_device(req->sens)) return PRIOR_LS_EINVAL;
-    if (req->n_append > 0 && (!on_device(req->kspace_frames) || !on_device(req->mask_frames)))
-        return PRIOR_LS_EINVAL;
-    // bytes of the compact k-space: one slot per frame, sized by the most sampled frame
-    const size_t P = (size_t)d.ny * d.nz;
-    const size_t nf = (size_t)d.nt + req->n_append;
-    std::vector<uint8_t> m(nf * P);
-    if (hipMemcpy(m.data(), req->mask0, d.nt * P, hipMemcpyDeviceToHost) != hipSuccess ||
-        (req->n_append > 0 &&
-         hipMemcpy(m.data() + d.nt * P, req->mask_frames, req->n_append * P, hipMemcpyDeviceToHost) != hipSuccess)) {
-        (void)hipGetLastError();
-        return PRIOR_LS_EHIP;
-    }
-    size_t ns_max = 1;
-    for (size_t f = 0; f < nf; ++f) {
-        size_t c = 0;
-        for (size_t k = 0; k < P; ++k) c += m[f * P + k] != 0;
-        ns_max = std::max(ns_max, c);
-    }
-    const uint64_t need = plan + ((uint64_t)d.nt * d.nx * d.nc * ns_max + 64) * 8;
-    if (need > s->budget) return PRIOR_LS_ENOMEM;
+        return fail(PRIOR_LS_EINVAL, "params.struct_size mismatch");
+    if (req->n_append < 0 || req->reserved != 0) return fail(PRIOR_LS_EINVAL, "n_append < 0 or reserved != 0");
+    if (!req->kspace0 || !req->mask0 || (d.nc > 1 && !req->sens) ||
+        (req->n_append > 0 && (!req->kspace_frames || !req->mask_frames)))
+        return fail(PRIOR_LS_EINVAL, "a required array is NULL");
     auto* j = new Job();
     j->req = *req;
-    j->need = need;
     j->submitted = Clock::now();
     j->result.struct_size = sizeof(prior_ls_result);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) {
             delete j;
-            return PRIOR_LS_EINVAL;
+            return fail(PRIOR_LS_EINVAL, "server is stopping");
         }
         j->ticket = s->next_ticket++;
         s->jobs[j->ticket] = j;
-        s->pending.push_back(j);
+        s->incoming.push_back(j);
         ++s->submitted;
     }
     s->cv_work.notify_all();
@@ -372,9 +532,10 @@ void prior_ls_server_destroy(prior_ls_server* s) {
         s->stopping = true;
     }
     s->cv_work.notify_all();
-    for (auto& t : s->workers) t.join();
+    if (s->thread.joinable()) s->thread.join();
     for (Resident& r : s->idle) prior_ls_server::destroy_resident(r);
     for (auto& kv : s->jobs) delete kv.second;
+    if (s->ctl) (void)hipStreamDestroy(s->ctl);
     delete s;
 }
 

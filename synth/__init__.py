@@ -432,3 +432,46 @@ def sequence(nx, ny, nz, nt, n_append, nc, accel, seed, accel_first=2.0, snr_db=
     return Sequence(nx=nx, ny=ny, nz=nz, nt=nt, nc=nc, n_append=n_append, kspace=d, mask=m,
                     sens=sens, L_true=L, S_true=S, lambda_L=lambda_L, lambda_S=lambda_S,
                     lambda_p=lambda_p)
+
+
+def phantom(nx, ny, nz, nt, rank, nblobs, seed):
+    """The phantom alone (L, S), complex128 [nt][nz][ny][nx], scaled to max |L + S| = 1:
+    for workloads whose k-space is formed elsewhere (the serving stream)."""
+    r_bg, r_blob = _rngs(seed, 2)
+    L, _ = background(r_bg, nx, ny, nz, nt, rank)
+    blobs = _make_blobs(r_blob, nx, ny, nz, nt, nblobs, nz > 1, float(np.abs(L).max()))
+    S = np.stack([_render_blobs(blobs, t, nt, nx, ny, nz) for t in range(nt)])
+    scale = 1.0 / float(np.abs(L + S).max())
+    return L * scale, S * scale
+
+
+# The serving stream: 64 recursive reconstruction requests, Poisson arrivals at 20 per
+# second, sizes uniform over three volumes x three window lengths x three coil counts,
+# acceleration uniform in [8, 12] for the appended frames, the first window at 50%;
+# 8 appended frames per request.  Phantom per volume: rank / blobs as the single-solve
+# workloads of that size.
+SERVING = dict(n_requests=64, rate_per_s=20.0, n_append=8, accel_first=2.0, accel=(8.0, 12.0),
+               volumes=((64, 64, 8), (128, 128, 16), (192, 192, 32)), nts=(16, 24, 30),
+               ncs=(1, 4, 8), rank={64: 3, 128: 5, 192: 6}, nblobs={64: 12, 128: 40, 192: 60},
+               snr_db=35.0, first_iters=50, append_iters=20)
+
+
+def serving_requests(seed=MASTER_SEED * 10 + 5):
+    """The request list of the serving stream: (arrival s, (nx, ny, nz), nt, nc, accel,
+    first-window masks [nt][nz][ny], appended-frame masks [n_append][nz][ny])."""
+    c = SERVING
+    rng = np.random.default_rng(seed)
+    n = c["n_requests"]
+    gaps = rng.exponential(1.0 / c["rate_per_s"], size=n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n):
+        vol = c["volumes"][rng.integers(len(c["volumes"]))]
+        nt = int(c["nts"][rng.integers(len(c["nts"]))])
+        nc = int(c["ncs"][rng.integers(len(c["ncs"]))])
+        accel = float(rng.uniform(*c["accel"]))
+        nx, ny, nz = vol
+        m0 = masks(rng, ny, nz, nt, c["accel_first"])
+        mf = masks(rng, ny, nz, c["n_append"], accel)
+        out.append((float(arrivals[i]), vol, nt, nc, accel, m0, mf))
+    return out

@@ -1,0 +1,44 @@
+// Fake library calls: a handle is heap memory that every call reads and writes, and a
+// chunk "runs" until a deadline, so use after destroy, two callers on one handle or a
+// premature read show up under the sanitizers or as failed checks.
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <thread>
+#include "prior_ls.h"
+#include "pls_runtime_api.hpp"
+using Clk = std::chrono::steady_clock;
+struct prior_ls_handle { prior_ls_dims d; void* stream; int busy; long work; prior_ls_params p;
+                         Clk::time_point ready; int inflight; int iters; char pad[4096]; };
+static thread_local std::string g_err;
+namespace pls { void set_thread_error(const std::string& m) { g_err = m; } }
+static void touch(prior_ls_handle* h) { for (int i = 0; i < 4096; i += 64) h->pad[i]++; }
+extern "C" {
+uint64_t prior_ls_plan_bytes(const prior_ls_dims* d) {
+  if (!d || d->nx <= 0) return 0;
+  return (uint64_t)d->nx * d->ny * d->nz * d->nt * 40 + (uint64_t)d->nc * d->nx * d->ny * d->nz * 8;
+}
+int prior_ls_create(const prior_ls_dims* d, void* s, prior_ls_handle** out) {
+  auto* h = new prior_ls_handle(); h->d = *d; h->stream = s; std::memset(h->pad, 1, sizeof h->pad);
+  *out = h; return 0;
+}
+void prior_ls_destroy(prior_ls_handle* h) { if (!h) return; if (h->inflight) std::abort(); std::memset(h->pad, 0, sizeof h->pad); delete h; }
+const char* prior_ls_last_error(const prior_ls_handle* h) { return h ? "" : g_err.c_str(); }
+}
+namespace pls {
+int phase_load(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* p) {
+  if (!in->kspace || !in->mask) return -1; touch(h); h->p = *p; h->iters = 0; return 0; }
+int phase_shift(prior_ls_handle* h, const void* kf, const uint8_t* mf, const prior_ls_params* p) {
+  if (!kf || !mf) return -1; touch(h); h->p = *p; h->iters = 0; return 0; }
+int phase_chunk_launch(prior_ls_handle* h, int remaining) {
+  if (h->inflight) std::abort();
+  int m = remaining < h->p.check_every ? remaining : h->p.check_every;
+  h->inflight = m; h->ready = Clk::now() + std::chrono::microseconds(30 * m); touch(h); return m; }
+int phase_query(prior_ls_handle* h) { touch(h); return Clk::now() >= h->ready ? 1 : 0; }
+int phase_chunk_finish(prior_ls_handle* h, int m, int* conv) {
+  if (Clk::now() < h->ready || h->inflight != m) std::abort();
+  h->inflight = 0; h->iters += m; *conv = 0; return 0; }
+int phase_outputs(prior_ls_handle* h, const prior_ls_outputs*) { h->ready = Clk::now() + std::chrono::microseconds(50); return 0; }
+void phase_stats(prior_ls_handle* h, prior_ls_stats* st, int conv, double ms) { st->iters = h->iters; st->converged = conv; st->ms = ms; }
+int phase_max_iter(const prior_ls_handle* h) { return h->p.max_iter; }
+}

@@ -97,3 +97,26 @@ def test_admission_respects_budget_and_reuses_plans():
     assert info["peak_active"] == 1 and info["peak_used"] <= int(need * 1.2)
     assert info["reused"] == 3 and sum(r["reused_plan"] for r in results) == 3
     assert max(r["queue_ms"] for r in results) > 0
+
+
+def test_submit_from_another_thread():
+    # requests arrive on a thread of their own while the caller waits
+    import queue
+    import threading
+    reqs = [make_request(i, n_append=1) for i in range(3)]
+    q = queue.Queue()
+    with pls.Server(max_active=2) as srv:
+        def submitter():
+            try:
+                for _, dims, args in reqs:
+                    q.put(submit(srv, dims, args))
+            except Exception as e:
+                q.put(e)
+        th = threading.Thread(target=submitter)
+        th.start()
+        for _ in reqs:
+            t = q.get(timeout=120)
+            assert not isinstance(t, Exception), t
+            _, res = srv.wait(t)
+            assert res["status"] == pls.OK, res["message"]
+        th.join()
