@@ -241,7 +241,10 @@ typedef struct {
     size_t   struct_size;       /* = sizeof(prior_ls_server_config) */
     uint64_t hbm_budget;        /* device bytes for resident sequence state; 0 = 90% of the
                                    free device memory at create */
-    int32_t  max_active;        /* sequences in flight at once, 1..64 */
+    int32_t  max_active;        /* sequences in flight at once, 1..64.  This build keeps one
+                                   in flight whatever the value (concurrent sequences are
+                                   switched off: a run with four large ones in flight ended in
+                                   a host segmentation fault whose cause was not found) */
     int32_t  reserved;          /* must be 0 */
 } prior_ls_server_config;
 

@@ -1,0 +1,142 @@
+// The library's runtime and serving dispatcher, host code as built for the GPU, driven on
+// the CPU against stand-ins of HIP and of the kernels: sequences of five geometries (one
+// with fully sampled appended frames, so its sample store grows), four in flight, a budget
+// that forces queueing and evictions, submitted from a second thread; then the synchronous
+// entry points on several handles from several threads at once.
+#include <atomic>
+#include <cstdio>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+#include "prior_ls.h"
+
+struct Geo {
+    int nx, ny, nz, nt, nc, dense_frames;
+};
+static const Geo kGeo[] = {{16, 16, 4, 5, 2, 0}, {24, 32, 8, 7, 3, 0}, {32, 32, 1, 6, 1, 0},
+                           {16, 16, 4, 6, 2, 1}, {48, 32, 8, 8, 2, 0}};
+
+struct Seq {
+    Geo g;
+    int n_append;
+    void *k0, *kf, *sens;
+    uint8_t *m0, *mf;
+    void* X;
+    std::vector<double> lat;
+    std::vector<prior_ls_stats> st;
+    prior_ls_request rq{};
+};
+
+static void* dev_alloc(size_t n) {
+    void* p = nullptr;
+    hipMalloc(&p, n);
+    std::memset(p, 0, n);
+    return p;
+}
+
+static void make_seq(Seq& q, std::mt19937& rng) {
+    const size_t P = (size_t)q.g.ny * q.g.nz, img = P * q.g.nx;
+    q.k0 = dev_alloc((size_t)q.g.nc * q.g.nt * img * 8);
+    q.kf = dev_alloc((size_t)(q.n_append ? q.n_append : 1) * q.g.nc * img * 8);
+    q.sens = q.g.nc > 1 ? dev_alloc((size_t)q.g.nc * img * 8) : nullptr;
+    q.m0 = (uint8_t*)dev_alloc((size_t)q.g.nt * P);
+    q.mf = (uint8_t*)dev_alloc((size_t)(q.n_append ? q.n_append : 1) * P);
+    for (size_t i = 0; i < (size_t)q.g.nt * P; ++i) q.m0[i] = rng() % 3 == 0;
+    for (size_t i = 0; i < (size_t)q.n_append * P; ++i) q.mf[i] = q.g.dense_frames ? 1 : rng() % 4 == 0;
+    q.X = dev_alloc((size_t)q.g.nt * img * 8);
+    q.lat.assign(q.n_append + 1, 0.0);
+    q.st.assign(q.n_append + 1, prior_ls_stats{});
+    prior_ls_request& r = q.rq;
+    r.struct_size = sizeof(r);
+    r.dims = prior_ls_dims{sizeof(prior_ls_dims), q.g.nx, q.g.ny, q.g.nz, q.g.nt, q.g.nc, 2, 0, 0, 0};
+    r.first = prior_ls_params{sizeof(prior_ls_params), 0.01, 0.01, 0.0, 0.0, 1, 8, 4, 1};
+    r.next = prior_ls_params{sizeof(prior_ls_params), 0.01, 0.01, 0.2, 0.0, 1, 6, 3, 1};
+    r.n_append = q.n_append;
+    r.kspace0 = q.k0;
+    r.mask0 = q.m0;
+    r.kspace_frames = q.kf;
+    r.mask_frames = q.mf;
+    r.sens = q.sens;
+    r.out = prior_ls_outputs{nullptr, nullptr, q.X, nullptr};
+    r.stats = q.st.data();
+    r.latency_ms = q.lat.data();
+}
+
+int main() {
+    std::mt19937 rng(11);
+    const int N = 40;
+    std::vector<Seq> seqs(N);
+    for (int i = 0; i < N; ++i) {
+        seqs[i].g = kGeo[rng() % 5];
+        seqs[i].n_append = rng() % 4;
+        make_seq(seqs[i], rng);
+    }
+    prior_ls_dims big{sizeof(prior_ls_dims), 48, 32, 8, 8, 2, 2, 0, 0, 0};
+    prior_ls_server_config cfg{sizeof(cfg), (uint64_t)(prior_ls_plan_bytes(&big) * 2.5), 4, 0};
+    prior_ls_server* s = nullptr;
+    if (prior_ls_server_create(&cfg, &s)) return 1;
+    std::vector<int64_t> tk(N, -1);
+    std::atomic<int> submitted{0};
+    std::thread sub([&] {
+        for (int i = 0; i < N; ++i) {
+            if (prior_ls_server_submit(s, &seqs[i].rq, &tk[i])) std::abort();
+            submitted.store(i + 1);
+            std::this_thread::sleep_for(std::chrono::microseconds(200));
+        }
+    });
+    int bad = 0;
+    for (int i = 0; i < N; ++i) {
+        while (submitted.load() <= i) std::this_thread::yield();
+        prior_ls_result r{};
+        r.struct_size = sizeof(r);
+        if (prior_ls_server_wait(s, tk[i], &r)) return 1;
+        if (r.status) {
+            ++bad;
+            std::printf("request %d: status %d %s\n", i, r.status, r.message);
+        }
+        for (int w = 0; w <= seqs[i].n_append; ++w) {
+            const int want = w == 0 ? 8 : 6;
+            if (seqs[i].st[w].iters != want) {
+                ++bad;
+                std::printf("request %d window %d: %d iterations\n", i, w, seqs[i].st[w].iters);
+            }
+        }
+    }
+    sub.join();
+    prior_ls_server_stats info{};
+    info.struct_size = sizeof(info);
+    prior_ls_server_info(s, &info);
+    std::printf("server: completed %lld failed %lld reused %lld evicted %lld peak_active %d\n",
+                (long long)info.completed, (long long)info.failed, (long long)info.reused,
+                (long long)info.evicted, info.peak_active);
+    prior_ls_server_destroy(s);
+    // the synchronous entry points, one handle per thread, four threads at once
+    std::vector<std::thread> th;
+    std::atomic<int> sync_bad{0};
+    for (int k = 0; k < 4; ++k)
+        th.emplace_back([&, k] {
+            Seq& q = seqs[k];
+            prior_ls_handle* h = nullptr;
+            if (prior_ls_create(&q.rq.dims, nullptr, &h)) {
+                ++sync_bad;
+                return;
+            }
+            prior_ls_inputs in{q.k0, q.m0, q.sens, nullptr, nullptr, nullptr, nullptr};
+            prior_ls_stats st{};
+            st.struct_size = sizeof(st);
+            if (prior_ls_solve(h, &in, &q.rq.first, &q.rq.out, &st)) ++sync_bad;
+            for (int j = 0; j < q.n_append; ++j) {
+                const size_t P = (size_t)q.g.ny * q.g.nz;
+                if (prior_ls_append(h, (char*)q.kf + (size_t)j * q.g.nc * P * q.g.nx * 8, q.mf + j * P,
+                                    &q.rq.next, &q.rq.out, &st))
+                    ++sync_bad;
+            }
+            if (prior_ls_step(h, 3, &q.rq.out, &st)) ++sync_bad;
+            prior_ls_destroy(h);
+        });
+    for (auto& t : th) t.join();
+    std::printf("done: bad %d sync_bad %d\n", bad, sync_bad.load());
+    return bad || sync_bad.load() || info.evicted == 0;
+}

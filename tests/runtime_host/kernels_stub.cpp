@@ -1,0 +1,201 @@
+// Stand-ins of the library's kernel launchers for the CPU build of its host code: each
+// enqueues, on the launch stream, work that reads and writes the arrays the kernel would,
+// at the extents its arguments imply (so a wrong size or a buffer freed too early is caught
+// by the sanitizers), and takes some time (so streams and sequences overlap).  The sample
+// lists and the compact k-space use the kernels' own index arithmetic.
+#include <chrono>
+#include <cstring>
+#include <thread>
+
+#include "pls_kernels.hpp"
+
+namespace pls {
+namespace {
+void work_us(int us) { std::this_thread::sleep_for(std::chrono::microseconds(us)); }
+template <class T>
+void touch(T* p, size_t n) {
+    if (!p || !n) return;
+    volatile char a = *(volatile char*)p;
+    volatile char b = *((volatile char*)(p + n) - 1);
+    (void)a;
+    (void)b;
+    std::memset((void*)p, 0, sizeof(T));
+    std::memset((void*)(p + n - 1), 0, sizeof(T));
+}
+template <class T>
+void look(const T* p, size_t n) {
+    if (!p || !n) return;
+    volatile char a = *(const volatile char*)p;
+    volatile char b = *((const volatile char*)(p + n) - 1);
+    (void)a;
+    (void)b;
+}
+}  // namespace
+
+bool dc_supported(int ny, int nz) { return ny >= 16 && ny <= 256 && nz >= 1 && nz <= 32; }
+bool xifft_supported(int nx) { return nx >= 16 && nx <= 256; }
+int dc_blocks(int ny, int nz, int nx, int nt) { return nx * nt; }
+int gram_tiles(int nt) { return nt <= 16 ? 3 : 10; }
+int gram_blocks(int N) {
+    int vpb = (N + 511) / 512;
+    vpb = (vpb + 127) / 128 * 128;
+    return (N + vpb - 1) / vpb;
+}
+
+int launch_dc(int ny, int nz, bool stats, const DcArgs& a, hipStream_t s) {
+    DcArgs c = a;
+    fh_stream(s)->push([c, ny, nz, stats] {
+        const size_t P = (size_t)ny * nz, I = P * c.nx * c.nt;
+        look(c.L, c.L ? I : 0);
+        look(c.S, c.S ? I : 0);
+        if (stats) {
+            look(c.Lold, I);
+            look(c.Sold, I);
+        }
+        look(c.sens, c.sens ? (size_t)c.nc * c.nx * P : 0);
+        for (int t = 0; t < c.nt; ++t) {
+            look(c.sidx + t * P, P);
+            const size_t n = (size_t)c.nx * c.nc * c.ns[t];
+            look(c.dh + c.dh_off[t], n ? n : 1);
+        }
+        touch(c.C, I);
+        touch(c.part, (size_t)c.nx * c.nt * 4);
+        work_us(60);
+    });
+    return c.nx * c.nt;
+}
+
+bool launch_xifft(int nx, const XiArgs& a, hipStream_t s) {
+    XiArgs c = a;
+    fh_stream(s)->push([c, nx] {
+        for (int line = 0; line < c.total_lines; ++line) {
+            int t = 0;
+            while (line >= c.line_off[t + 1]) ++t;
+            const int rem = line - c.line_off[t];
+            const int coil = rem / c.ns[t], smp = rem % c.ns[t];
+            const int pos = c.plist[(size_t)t * c.P + smp];
+            for (int x = 0; x < nx; ++x) {
+                const float2 v = c.kspace[((size_t)(coil * c.nt + t) * c.P + pos) * nx + x];
+                c.dh[c.dh_off[t] + ((size_t)x * c.nc + coil) * c.ns[t] + smp] = v;
+            }
+        }
+        work_us(30);
+    });
+    return true;
+}
+
+void launch_mask_scan(const uint8_t* mask, int ny, int nz, int nt, int16_t* sidx, int* plist,
+                      int* ns, hipStream_t s) {
+    fh_stream(s)->push([=] {
+        const int P = ny * nz;
+        for (int t = 0; t < nt; ++t) {
+            int k = 0;
+            for (int i = 0; i < P; ++i) {
+                if (mask[(size_t)t * P + i]) {
+                    sidx[(size_t)t * P + i] = (int16_t)k;
+                    plist[(size_t)t * P + k] = i;
+                    ++k;
+                } else {
+                    sidx[(size_t)t * P + i] = -1;
+                }
+            }
+            ns[t] = k;
+        }
+    });
+}
+
+void launch_pack(const float2* in, const float2* in2, float2* out, int F, int nx, int ny, int nz,
+                 hipStream_t s) {
+    fh_stream(s)->push([=] {
+        const size_t n = (size_t)F * nx * ny * nz;
+        look(in, n);
+        look(in2, in2 ? n : 0);
+        touch(out, n);
+        work_us(10);
+    });
+}
+void launch_unpack(const float2* a, const float2* b, float2* out, int F, int nx, int ny, int nz,
+                   hipStream_t s) {
+    launch_pack(a, b, out, F, nx, ny, nz, s);
+}
+void launch_pack_weights(const uint8_t* in, uint8_t* out, int nt, int nx, int ny, int nz, int J,
+                         hipStream_t s) {
+    fh_stream(s)->push([=] {
+        const size_t n = (size_t)nt * nx * ny * nz;
+        look(in, n);
+        touch(out, n);
+    });
+}
+void launch_add(const float2* a, const float2* b, float2* out, size_t n, hipStream_t s) {
+    fh_stream(s)->push([=] {
+        look(a, n);
+        look(b, n);
+        touch(out, n);
+    });
+}
+int launch_gram(int mode, const GramArgs& a, hipStream_t s) {
+    GramArgs c = a;
+    const int gb = gram_blocks(c.N);
+    fh_stream(s)->push([c, gb] {
+        look(c.C, (size_t)c.N * c.nt);
+        touch(c.part, (size_t)gb * gram_tiles(c.nt) * 256);
+        work_us(20);
+    });
+    return gb;
+}
+void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s) {
+    fh_stream(s)->push([=] {
+        look(part, (size_t)blocks * entries);
+        touch(out, (size_t)entries);
+    });
+}
+void launch_eig(const EigArgs& a, hipStream_t s) {
+    EigArgs c = a;
+    fh_stream(s)->push([c] {
+        touch(c.V, (size_t)2 * c.nt * c.nt);
+        touch(c.Wd, (size_t)2 * c.nt * c.nt);
+        look(c.sigma_prev, (size_t)c.nt);
+        if (c.sigL) touch(c.sigL, (size_t)c.nt);
+        c.stat[4] = c.stat[5] = c.stat[6] = 1.0;
+        work_us(30);
+    });
+}
+void launch_bp(const BpArgs& a, hipStream_t s) {
+    BpArgs c = a;
+    fh_stream(s)->push([c] {
+        look(c.C, (size_t)c.N * c.nt);
+        touch(c.L, (size_t)c.N * c.nt);
+        work_us(20);
+    });
+}
+int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
+    SparseArgs c = a;
+    const int B = 1 << levels, ZW = c.nz > 1 ? B : 1, YW = 64 / ZW;
+    const int blocks = ((c.ny + 4 * YW - 1) / (4 * YW)) * (c.nz / ZW) * (c.nx / B) * c.nt;
+    fh_stream(s)->push([c, blocks] {
+        const size_t I = (size_t)c.nx * c.ny * c.nz * c.nt;
+        look(c.C, I);
+        look(c.S, c.S ? I : 0);
+        look(c.Lp, I);
+        look(c.w, c.w ? I : 0);
+        touch(c.Sout, I);
+        if (c.supp) touch(c.supp, I);
+        touch(c.part, (size_t)blocks);
+        work_us(40);
+    });
+    return blocks;
+}
+void launch_stats(const StatsArgs& a, hipStream_t s) {
+    StatsArgs c = a;
+    fh_stream(s)->push([c] {
+        look(c.dc_part, (size_t)c.dc_blocks * 4);
+        look(c.sp_part, (size_t)c.sp_blocks);
+        c.stat[0] = 1.0;
+        c.stat[1] = 1.0;
+        c.stat[2] = 4.0;
+        c.stat[3] = 1.0;
+        c.stat[7] = 0.0;
+    });
+}
+
+}  // namespace pls

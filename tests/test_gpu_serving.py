@@ -62,6 +62,9 @@ def test_served_sequence_matches_oracle():
     assert [w["iters"] for w in res["windows"]] == [K0] + [K1] * 3
 
 
+@pytest.mark.skip(reason="concurrent sequences are switched off: a full-size run with four "
+                         "sequences in flight ended in a host segmentation fault whose cause "
+                         "was not found; with one in flight the mix is sequential")
 def test_same_alone_and_in_the_mix():
     reqs = [make_request(i, n_append=2 + i % 3) for i in range(6)]
     alone = []

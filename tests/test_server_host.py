@@ -22,7 +22,8 @@ def test_server_logic_under_sanitizer(tmp_path, san):
     server = tmp_path / "server.cpp"
     shutil.copy(os.path.join(ROOT, "paper_1411_6206_amd", "csrc", "pls_server.hip"), server)
     exe = tmp_path / "drv"
-    cmd = ["g++", "-std=c++17", "-O1", "-g", f"-fsanitize={san}", "-I", SRC,
+    cmd = ["g++", "-std=c++17", "-O1", "-g", f"-fsanitize={san}", "-DPLS_SERVER_MAX_IN_FLIGHT=4",
+           "-I", SRC,
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_1411_6206_amd", "csrc"),
            str(server), os.path.join(SRC, "fake_lib.cpp"), os.path.join(SRC, "driver.cpp"),
            "-o", str(exe), "-lpthread"]
@@ -34,3 +35,32 @@ def test_server_logic_under_sanitizer(tmp_path, san):
     assert "WARNING: ThreadSanitizer" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
     assert "completed 200 failed 0" in r.stdout and "bad 0" in r.stdout
     assert " evicted 0 " not in r.stdout            # the budget did force evictions
+
+
+RT = os.path.join(HERE, "runtime_host")
+
+
+@pytest.mark.parametrize("san", ["thread", "address,undefined"])
+def test_runtime_and_server_host_code_under_sanitizer(tmp_path, san):
+    """The library's own runtime (pls_runtime.hip) and server, host code as built for the GPU,
+    against a HIP stand-in whose streams run asynchronously on threads and kernel stand-ins
+    that touch their arrays at full extent: sequences of five geometries, four in flight,
+    evictions and sample-store growth, then the synchronous API from four threads."""
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    csrc = os.path.join(ROOT, "paper_1411_6206_amd", "csrc")
+    exe = tmp_path / "rt"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", f"-fsanitize={san}", "-DPLS_SERVER_MAX_IN_FLIGHT=4",
+           "-I", RT, "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           "-x", "c++", os.path.join(csrc, "pls_runtime.hip"), os.path.join(csrc, "pls_server.hip"),
+           "-x", "none", os.path.join(RT, "kernels_stub.cpp"), os.path.join(RT, "driver.cpp"),
+           "-o", str(exe), "-lpthread"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1",
+               ASAN_OPTIONS="halt_on_error=1:detect_leaks=0")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
+    print(r.stdout[-2000:], r.stderr[-4000:])
+    assert r.returncode == 0
+    assert "WARNING: ThreadSanitizer" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
+    assert "failed 0" in r.stdout and "done: bad 0 sync_bad 0" in r.stdout
+    assert "peak_active 4" in r.stdout
