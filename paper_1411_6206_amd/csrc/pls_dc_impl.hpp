@@ -164,6 +164,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
         for (int i = 0; i < D0::NB; ++i) {
             const int pbc = min(e0.pb[i], nvalid - 1);
             const int o = pbc * P + e0.rel[i];
+            const bool own = e0.pb[i] < nvalid;
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int q = i * R0 + r;
@@ -171,10 +172,18 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
                 if constexpr (G::KEEPY) {
                     yv = Y[q];
                 } else {
+                    // Y = L + S is formed at the first coil and parked in the output array
+                    // (each thread rereads only the entries it wrote), so the later coils
+                    // read one array instead of two
                     const int gi = plane0 + o + r * D0::STEP;
-                    const float2 l = Lp[gi], sv = Sp[gi];
-                    yv = has_s ? cadd(l, sv) : l;
-                    if (!has_y) yv = make_float2(0.f, 0.f);
+                    if (c == 0) {
+                        const float2 l = Lp[gi], sv = Sp[gi];
+                        yv = has_s ? cadd(l, sv) : l;
+                        if (!has_y) yv = make_float2(0.f, 0.f);
+                        if (own) a.C[gi] = yv;
+                    } else {
+                        yv = a.C[gi];
+                    }
                 }
                 float2 sv = sc[o + r * D0::STEP];
                 if (!has_sens) sv = make_float2(1.f, 0.f);

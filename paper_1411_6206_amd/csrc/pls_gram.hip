@@ -341,6 +341,7 @@ void launch_gram_reduce(const double* part, int blocks, int entries, double* out
 // rotations of a round applied at once), warm-started from the previous iteration's
 // eigenvectors: A = V^H G V is then nearly diagonal and one or two sweeps suffice.
 constexpr int kNMax = 32;
+constexpr int kEigThreads = 256;    // one block of four waves: it shares its CU with the sparse update
 constexpr int kMaxSweeps = 30;
 
 __device__ __forceinline__ double gram_real(const double* red, int NB, int c1, int c2) {
@@ -409,15 +410,15 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double cr, do
     }
 }
 
-__global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
+__global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
     __shared__ double Ar[kNMax][kNMax + 1], Ai[kNMax][kNMax + 1];
     __shared__ double Vr[kNMax][kNMax + 1], Vi[kNMax][kNMax + 1];
     __shared__ double Tr[kNMax][kNMax + 1], Ti[kNMax][kNMax + 1];
     __shared__ double rc[kNMax / 2], rs[kNMax / 2], rer[kNMax / 2], rei[kNMax / 2];
     __shared__ int rp[kNMax / 2], rq[kNMax / 2];
-    __shared__ double red[4];
+    __shared__ double red[kEigThreads / 64];
     __shared__ double sig[kNMax], phi[kNMax];
-    __shared__ int rank_of[kNMax];
+    __shared__ int rank_of[kNMax], by_rank[kNMax];
     // one block on the critical path while the sparse update fills the other CUs (and
     // possibly this one): its waves issue first
     __builtin_amdgcn_s_setprio(3);
@@ -428,7 +429,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
     const int NTP = 16 * NB;
 
     // G (complex Hermitian, n x n; padded index decoupled)
-    for (int idx = tid; idx < ne * ne; idx += 256) {
+    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
         const int i = idx / ne, j = idx % ne;
         double gr = 0.0, gi = 0.0;
         if (i < n && j < n) {
@@ -447,7 +448,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
     }
     __syncthreads();
     // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
-    for (int idx = tid; idx < ne * ne; idx += 256) {
+    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
         const int i = idx / ne, j = idx % ne;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < ne; ++k) {
@@ -458,7 +459,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
         Ai[i][j] = si;
     }
     __syncthreads();
-    for (int idx = tid; idx < ne * ne; idx += 256) {
+    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
         const int i = idx / ne, j = idx % ne;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < ne; ++k) {
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
         Ti[i][j] = si;
     }
     __syncthreads();
-    for (int idx = tid; idx < ne * ne; idx += 256) {
+    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
         const int i = idx / ne, j = idx % ne;
         // symmetrise: A = (T + T^H) / 2
         Ar[i][j] = 0.5 * (Tr[i][j] + Tr[j][i]);
@@ -482,15 +483,16 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
     int sweeps = 0;
     for (; sweeps < kMaxSweeps && ne > 1; ++sweeps) {
         double off = 0.0, dg = 0.0;
-        for (int idx = tid; idx < ne * ne; idx += 256) {
+        for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
             const int i = idx / ne, j = idx % ne;
             if (i == j) dg += Ar[i][i] * Ar[i][i];
             else off += Ar[i][j] * Ar[i][j] + Ai[i][j] * Ai[i][j];
         }
-        off = block_sum<256>(off, red);
-        dg = block_sum<256>(dg, red);
-        // relative off-diagonal norm below 1e-10: far below the FP32 resolution of W
-        if (!(off > 1e-20 * dg)) break;   // also stops on NaN
+        off = block_sum<kEigThreads>(off, red);
+        dg = block_sum<kEigThreads>(dg, red);
+        // relative off-diagonal norm below 1e-8: eigenvector errors of that order (times
+        // the inverse gap) are far below the FP32 resolution of W
+        if (!(off > 1e-16 * dg)) break;   // also stops on NaN
         for (int r = 0; r < ne - 1; ++r) {
             if (tid < half) {
                 int p, q;
@@ -506,50 +508,54 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
             }
             __syncthreads();
             // A <- J^H A J on every 2x2 block; J = [[cs, sn e], [-sn conj(e), cs]]
-            for (int idx = tid; idx < half * half; idx += 256) {
-                const int al = idx / half, be = idx % half;
-                const int p = rp[al], q = rq[al], u = rp[be], w = rq[be];
-                const double c1 = rc[al], s1 = rs[al], e1r = rer[al], e1i = rei[al];
-                const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
-                const double b00r = Ar[p][u], b00i = Ai[p][u], b01r = Ar[p][w], b01i = Ai[p][w];
-                const double b10r = Ar[q][u], b10i = Ai[q][u], b11r = Ar[q][w], b11i = Ai[q][w];
-                // X = J1^H B, J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
-                const double x00r = c1 * b00r - s1 * (e1r * b10r - e1i * b10i);
-                const double x00i = c1 * b00i - s1 * (e1r * b10i + e1i * b10r);
-                const double x01r = c1 * b01r - s1 * (e1r * b11r - e1i * b11i);
-                const double x01i = c1 * b01i - s1 * (e1r * b11i + e1i * b11r);
-                const double x10r = s1 * (e1r * b00r + e1i * b00i) + c1 * b10r;
-                const double x10i = s1 * (e1r * b00i - e1i * b00r) + c1 * b10i;
-                const double x11r = s1 * (e1r * b01r + e1i * b01i) + c1 * b11r;
-                const double x11i = s1 * (e1r * b01i - e1i * b01r) + c1 * b11i;
-                // Y = X J2: Y[:,0] = X[:,0] c2 - X[:,1] s2 conj(e2); Y[:,1] = X[:,0] s2 e2 + X[:,1] c2
-                double y00r = c2 * x00r - s2 * (x01r * e2r + x01i * e2i);
-                double y00i = c2 * x00i - s2 * (x01i * e2r - x01r * e2i);
-                double y10r = c2 * x10r - s2 * (x11r * e2r + x11i * e2i);
-                double y10i = c2 * x10i - s2 * (x11i * e2r - x11r * e2i);
-                double y01r = s2 * (x00r * e2r - x00i * e2i) + c2 * x01r;
-                double y01i = s2 * (x00r * e2i + x00i * e2r) + c2 * x01i;
-                double y11r = s2 * (x10r * e2r - x10i * e2i) + c2 * x11r;
-                double y11i = s2 * (x10r * e2i + x10i * e2r) + c2 * x11i;
-                if (al == be) {
-                    y01r = y01i = y10r = y10i = 0.0;
-                    y00i = y11i = 0.0;
+            // one pass: items [0, half^2) update A, items [half^2, half^2 + ne half) update V
+            for (int it = tid; it < half * half + ne * half; it += kEigThreads) {
+                if (it < half * half) {
+                    const int idx = it;
+                    const int al = idx / half, be = idx % half;
+                    const int p = rp[al], q = rq[al], u = rp[be], w = rq[be];
+                    const double c1 = rc[al], s1 = rs[al], e1r = rer[al], e1i = rei[al];
+                    const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
+                    const double b00r = Ar[p][u], b00i = Ai[p][u], b01r = Ar[p][w], b01i = Ai[p][w];
+                    const double b10r = Ar[q][u], b10i = Ai[q][u], b11r = Ar[q][w], b11i = Ai[q][w];
+                    // X = J1^H B, J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
+                    const double x00r = c1 * b00r - s1 * (e1r * b10r - e1i * b10i);
+                    const double x00i = c1 * b00i - s1 * (e1r * b10i + e1i * b10r);
+                    const double x01r = c1 * b01r - s1 * (e1r * b11r - e1i * b11i);
+                    const double x01i = c1 * b01i - s1 * (e1r * b11i + e1i * b11r);
+                    const double x10r = s1 * (e1r * b00r + e1i * b00i) + c1 * b10r;
+                    const double x10i = s1 * (e1r * b00i - e1i * b00r) + c1 * b10i;
+                    const double x11r = s1 * (e1r * b01r + e1i * b01i) + c1 * b11r;
+                    const double x11i = s1 * (e1r * b01i - e1i * b01r) + c1 * b11i;
+                    // Y = X J2: Y[:,0] = X[:,0] c2 - X[:,1] s2 conj(e2); Y[:,1] = X[:,0] s2 e2 + X[:,1] c2
+                    double y00r = c2 * x00r - s2 * (x01r * e2r + x01i * e2i);
+                    double y00i = c2 * x00i - s2 * (x01i * e2r - x01r * e2i);
+                    double y10r = c2 * x10r - s2 * (x11r * e2r + x11i * e2i);
+                    double y10i = c2 * x10i - s2 * (x11i * e2r - x11r * e2i);
+                    double y01r = s2 * (x00r * e2r - x00i * e2i) + c2 * x01r;
+                    double y01i = s2 * (x00r * e2i + x00i * e2r) + c2 * x01i;
+                    double y11r = s2 * (x10r * e2r - x10i * e2i) + c2 * x11r;
+                    double y11i = s2 * (x10r * e2i + x10i * e2r) + c2 * x11i;
+                    if (al == be) {
+                        y01r = y01i = y10r = y10i = 0.0;
+                        y00i = y11i = 0.0;
+                    }
+                    Ar[p][u] = y00r; Ai[p][u] = y00i;
+                    Ar[p][w] = y01r; Ai[p][w] = y01i;
+                    Ar[q][u] = y10r; Ai[q][u] = y10i;
+                    Ar[q][w] = y11r; Ai[q][w] = y11i;
+                } else {
+                    // V <- V J
+                    const int idx = it - half * half;
+                    const int i = idx / half, be = idx % half;
+                    const int u = rp[be], w = rq[be];
+                    const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
+                    const double v0r = Vr[i][u], v0i = Vi[i][u], v1r = Vr[i][w], v1i = Vi[i][w];
+                    Vr[i][u] = c2 * v0r - s2 * (v1r * e2r + v1i * e2i);
+                    Vi[i][u] = c2 * v0i - s2 * (v1i * e2r - v1r * e2i);
+                    Vr[i][w] = s2 * (v0r * e2r - v0i * e2i) + c2 * v1r;
+                    Vi[i][w] = s2 * (v0r * e2i + v0i * e2r) + c2 * v1i;
                 }
-                Ar[p][u] = y00r; Ai[p][u] = y00i;
-                Ar[p][w] = y01r; Ai[p][w] = y01i;
-                Ar[q][u] = y10r; Ai[q][u] = y10i;
-                Ar[q][w] = y11r; Ai[q][w] = y11i;
-            }
-            // V <- V J
-            for (int idx = tid; idx < ne * half; idx += 256) {
-                const int i = idx / half, be = idx % half;
-                const int u = rp[be], w = rq[be];
-                const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
-                const double v0r = Vr[i][u], v0i = Vi[i][u], v1r = Vr[i][w], v1i = Vi[i][w];
-                Vr[i][u] = c2 * v0r - s2 * (v1r * e2r + v1i * e2i);
-                Vi[i][u] = c2 * v0i - s2 * (v1i * e2r - v1r * e2i);
-                Vr[i][w] = s2 * (v0r * e2r - v0i * e2i) + c2 * v1r;
-                Vi[i][w] = s2 * (v0r * e2i + v0i * e2r) + c2 * v1i;
             }
             __syncthreads();
         }
@@ -583,14 +589,14 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
     }
     __syncthreads();
     // nuclear norm summed in rank order for determinism
+    if (tid < n) by_rank[rank_of[tid]] = tid;
+    __syncthreads();
     if (tid == 0) {
         double nuc = 0.0;
-        for (int k = 0; k < n; ++k)
-            for (int j = 0; j < n; ++j)
-                if (rank_of[j] == k) {
-                    const double sg = sig[j];
-                    nuc += phi[j] * sg;
-                }
+        for (int k = 0; k < n; ++k) {
+            const int j = by_rank[k];
+            nuc += phi[j] * sig[j];
+        }
         a.stat[4] = nuc;
         a.stat[5] = tau;
         a.stat[6] = (double)sweeps;
@@ -598,7 +604,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
     (void)nuc_part;
     // W = V diag(phi) V^H and its real-expanded MFMA operand
     const int K2 = 2 * NTP;
-    for (int idx = tid; idx < NTP * NTP; idx += 256) {
+    for (int idx = tid; idx < NTP * NTP; idx += kEigThreads) {
         const int t = idx / NTP, j = idx % NTP;
         double wr = 0.0, wi = 0.0;
         if (t < n && j < n) {
@@ -619,7 +625,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
         a.Wop[(NTP + j) * K2 + t] = fi;       // Wr[t][NTP+j]     =  Im W
         a.Wop[(NTP + j) * K2 + NTP + t] = fr; // Wr[NTP+t][NTP+j] =  Re W
     }
-    for (int idx = tid; idx < n * n; idx += 256) {
+    for (int idx = tid; idx < n * n; idx += kEigThreads) {
         const int i = idx / n, j = idx % n;
         a.V[2 * idx] = Vr[i][j];
         a.V[2 * idx + 1] = Vi[i][j];
@@ -627,7 +633,7 @@ __global__ void __launch_bounds__(256) pls_eig_kernel(EigArgs a) {
 }
 
 void launch_eig(const EigArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(pls_eig_kernel, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pls_eig_kernel, dim3(1), dim3(kEigThreads), 0, s, a);
 }
 
 }  // namespace pls

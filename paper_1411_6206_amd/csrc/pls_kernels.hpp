@@ -19,7 +19,8 @@ struct DcArgs {
     const float2* S;       // NULL means S = 0
     const float2* Lold;    // previous iterate, read only by the statistics variant
     const float2* Sold;
-    float2* C;             // out: C = M - S = L - E^H(E Y - d)
+    float2* C;             // out: C = M - S = L - E^H(E Y - d); also holds Y between coils,
+                           // so it must not alias L or S
     const float2* sens;    // NULL: single unit coil
     const float2* dh;
     const int* dh_off;
