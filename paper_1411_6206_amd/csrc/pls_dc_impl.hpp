@@ -88,7 +88,6 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
     // so whatever the stand-in holds cannot leak in).
     const bool has_y = (a.L != nullptr);
     const bool has_s = has_y && (a.S != nullptr);
-    const bool has_sens = (a.sens != nullptr);
     const float2* Lp = has_y ? a.L : a.C;
     const float2* Sp = has_s ? a.S : Lp;
     const D0 d0(tid);
@@ -159,7 +158,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
         }
         if constexpr (G::NPZ == 0) __syncthreads();   // no block barrier inside the transform
         if (c + 1 < a.nc) stage_load(c + 1, dnext);
-        const float2* sc = has_sens ? a.sens + (c * a.nx + x0) * P : Lp;
+        const float2* sc = a.sens + (c * a.nx + x0) * P;
 #pragma unroll
         for (int i = 0; i < D0::NB; ++i) {
             const int pbc = min(e0.pb[i], nvalid - 1);
@@ -185,8 +184,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
                         yv = a.C[gi];
                     }
                 }
-                float2 sv = sc[o + r * D0::STEP];
-                if (!has_sens) sv = make_float2(1.f, 0.f);
+                const float2 sv = sc[o + r * D0::STEP];
                 v[q] = cmul(sv, yv);
             }
         }
@@ -233,8 +231,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int q = i * R0 + r;
-                float2 sv = sc[o + r * D0::STEP];
-                if (!has_sens) sv = make_float2(1.f, 0.f);
+                const float2 sv = sc[o + r * D0::STEP];
                 acc[q] = cadd(acc[q], cmulc(v[q], sv));
             }
         }

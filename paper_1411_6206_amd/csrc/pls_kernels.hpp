@@ -21,7 +21,7 @@ struct DcArgs {
     const float2* Sold;
     float2* C;             // out: C = M - S = L - E^H(E Y - d); also holds Y between coils,
                            // so it must not alias L or S
-    const float2* sens;    // NULL: single unit coil
+    const float2* sens;    // [nc][nx][nz][ny]; a single unit coil is an array of ones
     const float2* dh;
     const int* dh_off;
     const int* ns;

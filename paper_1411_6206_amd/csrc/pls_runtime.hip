@@ -127,7 +127,7 @@ Sizes sizes_of(const prior_ls_dims& d) {
     s.spb = sparse_blocks(d);
     uint64_t b = 0;
     b += 5 * s.I * 8;                                   // C, L[2], S[2]
-    if (d.nc > 1) b += (uint64_t)d.nc * s.N * 8;        // sensitivities
+    b += (uint64_t)d.nc * s.N * 8;                      // sensitivities (ones when nc == 1)
     b += 2 * s.I;                                       // weights, support of T(S)
     b += (uint64_t)2 * d.nt * s.P + 64 * 8;             // masks (two copies), sigma of L
     b += (uint64_t)d.nt * s.P * (2 + 4) + 3 * (d.nt + 1) * 4;  // sidx, plist, ns, offsets
@@ -158,6 +158,7 @@ struct prior_ls_handle {
     float2* L[2] = {nullptr, nullptr};
     float2* S[2] = {nullptr, nullptr};
     float2* sens = nullptr;
+    float2* ones = nullptr;          // the unit coil of a single-coil problem (nc == 1)
     uint8_t* w = nullptr;
     bool has_w = false, has_sens = false;
     float2* dh = nullptr;
@@ -323,7 +324,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     da.Lold = h->L[p];
     da.Sold = h->S[p];
     da.C = h->C;
-    da.sens = h->has_sens ? h->sens : nullptr;
+    da.sens = h->has_sens ? h->sens : h->ones;
     da.dh = h->dh;
     da.dh_off = h->dh_off;
     da.ns = h->ns;
@@ -472,7 +473,7 @@ DcArgs dc_args(prior_ls_handle* h, const float2* L, const float2* S, float2* C) 
     da.L = L;
     da.S = S;
     da.C = C;
-    da.sens = h->has_sens ? h->sens : nullptr;
+    da.sens = h->has_sens ? h->sens : h->ones;
     da.dh = h->dh;
     da.dh_off = h->dh_off;
     da.ns = h->ns;
@@ -842,6 +843,12 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
             h->S[k] = h->alloc<float2>(sz.I * sizeof(float2));
         }
         if (d.nc > 1) h->sens = h->alloc<float2>((size_t)d.nc * sz.N * sizeof(float2));
+        if (d.nc == 1) {
+            h->ones = h->alloc<float2>(sz.N * sizeof(float2));
+            const std::vector<float2> one(sz.N, make_float2(1.f, 0.f));
+            PLS_HIP(hipMemcpyAsync(h->ones, one.data(), sz.N * sizeof(float2), hipMemcpyHostToDevice, h->stream));
+            PLS_HIP(hipStreamSynchronize(h->stream));
+        }
         h->w = h->alloc<uint8_t>(sz.I);
         h->supp = h->alloc<uint8_t>(sz.I);
         h->mask_d = h->alloc<uint8_t>((size_t)d.nt * sz.P);
