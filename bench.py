@@ -243,6 +243,7 @@ def main():
     ap.add_argument("--no-gram-modes", action="store_true",
                     help="skip the per-Gram-mode comparison (short profiling runs)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes, no autotuning")
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -277,7 +278,15 @@ def main():
     cal = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
     torch.neg(cal.fill_(1.0), out=torch.empty_like(cal))
     del cal
-    solve(0)                                    # load: compact k-space, coils, weights, X_0
+    if args.no_tune:
+        solve(0)                                # load: compact k-space, coils, weights, X_0
+        tuning = None
+    else:
+        # the library's autotuner: times the sparse fork point, the Gram split and the
+        # back-projection grid on this problem and keeps the fastest; leaves X_0 loaded
+        tuning = h.tune(t["kspace"], t["mask"], t["sens"], t["prior_w"], check_every=10,
+                        **solve_kw)
+        print(f"[bench] tuned: {tuning}", file=sys.stderr, flush=True)
     h.step(args.warmup) if args.warmup > 0 else None
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -360,6 +369,7 @@ def main():
         "kernels": kernels,
         "resid_norm": st["resid_norm"],
         "eig_sweeps_last": st["eig_sweeps"],
+        "tuning": tuning,
         "input_gen_s": gen_s,
     }
     h.close()

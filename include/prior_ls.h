@@ -177,6 +177,37 @@ int prior_ls_append(prior_ls_handle *h, const void *kspace_frame, const uint8_t 
                     const prior_ls_params *params, const prior_ls_outputs *out,
                     prior_ls_stats *stats);
 
+/* Launch shapes and schedule of the iteration, chosen by measurement (prior_ls_tune) or
+ * set by the caller (for instance from a cache of earlier tunings).  Every choice computes
+ * the same iteration; only the Gram split changes its summation order (results agree to
+ * rounding; each choice is deterministic). */
+typedef struct {
+    size_t  struct_size;        /* = sizeof(prior_ls_tuning) */
+    int32_t gram_blocks;        /* the Casorati Gram is split over about this many workgroups
+                                   of voxels: 0 (default 512) or 64..2048 */
+    int32_t bp_grid;            /* back-projection workgroups at most: 0 (default 2048) or
+                                   64..65536 */
+    int32_t sparse_fork;        /* 0: the sparse update runs beside the reduction / eigensolve
+                                   / back-projection (forked after the Gram pass); 1: beside
+                                   the whole chain (forked before the Gram pass) */
+    int32_t reserved;           /* must be 0 */
+    double  ms_per_iteration;   /* prior_ls_tune: measured time per iteration of the choice */
+} prior_ls_tuning;
+
+/* Autotuner.  Loads the problem as prior_ls_solve does, then times params->check_every
+ * iterations (replayed as a hipGraph chunk, after one untimed chunk) for candidate launch
+ * shapes and schedules: the sparse fork point, the Gram split (256 ... 2048 blocks) and the
+ * back-projection grid (1024 ... 8192), one knob at a time starting from the current
+ * choice.  It reloads the problem before each trial and at the end, so the handle is left
+ * exactly as prior_ls_solve(max_iter = 0) leaves it, with the fastest choice applied;
+ * *best (may be NULL) receives it.  Errors as for prior_ls_solve. */
+int prior_ls_tune(prior_ls_handle *h, const prior_ls_inputs *in, const prior_ls_params *params,
+                  prior_ls_tuning *best);
+
+/* Apply a tuning (EINVAL when out of range) / read the one in use. */
+int prior_ls_set_tuning(prior_ls_handle *h, const prior_ls_tuning *t);
+int prior_ls_get_tuning(const prior_ls_handle *h, prior_ls_tuning *t);
+
 /* Release every resource of the handle.  NULL is a no-op. */
 void prior_ls_destroy(prior_ls_handle *h);
 

@@ -30,7 +30,8 @@ EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destr
            "prior_ls_strerror", "prior_ls_last_error", "prior_ls_plan_bytes",
            "prior_ls_op_dc", "prior_ls_op_svt", "prior_ls_op_sparse", "prior_ls_step_timed",
            "prior_ls_append", "prior_ls_server_create", "prior_ls_server_submit",
-           "prior_ls_server_wait", "prior_ls_server_info", "prior_ls_server_destroy")
+           "prior_ls_server_wait", "prior_ls_server_info", "prior_ls_server_destroy",
+           "prior_ls_tune", "prior_ls_set_tuning", "prior_ls_get_tuning")
 NKERNELS = 7
 KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats")
 
@@ -82,6 +83,16 @@ class Stats(C.Structure):
              if k not in ("sigma", "struct_size", "reserved")}
         d["sigma"] = list(self.sigma)[: self.sigma_count]
         return d
+
+
+class Tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("gram_blocks", C.c_int32), ("bp_grid", C.c_int32),
+                ("sparse_fork", C.c_int32), ("reserved", C.c_int32),
+                ("ms_per_iteration", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_
+                if k not in ("struct_size", "reserved")}
 
 
 class ServerConfig(C.Structure):
@@ -151,6 +162,12 @@ def lib():
     L.prior_ls_append.argtypes = [H, C.c_void_p, C.c_void_p, C.POINTER(Params),
                                   C.POINTER(Outputs), C.POINTER(Stats)]
     L.prior_ls_append.restype = C.c_int
+    L.prior_ls_tune.argtypes = [H, C.POINTER(Inputs), C.POINTER(Params), C.POINTER(Tuning)]
+    L.prior_ls_tune.restype = C.c_int
+    L.prior_ls_set_tuning.argtypes = [H, C.POINTER(Tuning)]
+    L.prior_ls_set_tuning.restype = C.c_int
+    L.prior_ls_get_tuning.argtypes = [H, C.POINTER(Tuning)]
+    L.prior_ls_get_tuning.restype = C.c_int
     S = C.c_void_p
     L.prior_ls_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(S)]
     L.prior_ls_server_create.restype = C.c_int
@@ -258,6 +275,60 @@ class PriorLS:
         torch.cuda.current_stream().synchronize()
         self._check(rc, "prior_ls_append")
         return outs, st.as_dict()
+
+    def tune(self, kspace, mask, sens=None, prior_w=None, sigma_prev=None, lambda_L=0.01,
+             lambda_S=0.01, lambda_p=0.0, lambda_L_relative=True, check_every=10, cache=None):
+        """prior_ls_tune: time candidate launch shapes on this problem and keep the fastest;
+        leaves the problem loaded (as solve with max_iter = 0).  cache: a JSON file (default
+        $PRIOR_LS_TUNE_CACHE) of earlier choices keyed by device, geometry and chunk length;
+        a hit is applied without measuring (the problem is then loaded by a 0-iteration
+        solve).  Returns the choice as a dict."""
+        import json
+        import torch
+        cache = cache or os.environ.get("PRIOR_LS_TUNE_CACHE")
+        d = self.dims
+        key = (f"{torch.cuda.get_device_name()}|{d.nx}x{d.ny}x{d.nz}x{d.nt}x{d.nc}|J{d.wavelet_levels}"
+               f"|gram{d.gram_mode}|chunk{check_every}")
+        book = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                book = json.load(fh)
+        if key in book:
+            t = Tuning(C.sizeof(Tuning), int(book[key]["gram_blocks"]), int(book[key]["bp_grid"]),
+                       int(book[key]["sparse_fork"]), 0, float(book[key]["ms_per_iteration"]))
+            self._check(lib().prior_ls_set_tuning(self._h, C.byref(t)), "prior_ls_set_tuning")
+            self.solve(kspace, mask, sens, prior_w, sigma_prev, lambda_L=lambda_L,
+                       lambda_S=lambda_S, lambda_p=lambda_p, lambda_L_relative=lambda_L_relative,
+                       max_iter=0, check_every=check_every, outputs=())
+            return dict(t.as_dict(), cached=True)
+        sp = None
+        if sigma_prev is not None:
+            vals = [float(v) for v in sigma_prev]
+            sp = (C.c_double * len(vals))(*vals)
+        ins = Inputs(_ptr(kspace), _ptr(mask), _ptr(sens), _ptr(prior_w),
+                     C.cast(sp, C.POINTER(C.c_double)) if sp is not None else None, None, None)
+        prm = Params(C.sizeof(Params), float(lambda_L), float(lambda_S), float(lambda_p), 0.0,
+                     1 if lambda_L_relative else 0, 0, int(check_every), 1)
+        t = Tuning()
+        t.struct_size = C.sizeof(Tuning)
+        rc = lib().prior_ls_tune(self._h, C.byref(ins), C.byref(prm), C.byref(t))
+        torch.cuda.current_stream().synchronize()
+        self._check(rc, "prior_ls_tune")
+        if cache:
+            book[key] = t.as_dict()
+            with open(cache, "w") as fh:
+                json.dump(book, fh, indent=1)
+        return dict(t.as_dict(), cached=False)
+
+    def set_tuning(self, gram_blocks=0, bp_grid=0, sparse_fork=0):
+        t = Tuning(C.sizeof(Tuning), int(gram_blocks), int(bp_grid), int(sparse_fork), 0, 0.0)
+        self._check(lib().prior_ls_set_tuning(self._h, C.byref(t)), "prior_ls_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        t.struct_size = C.sizeof(Tuning)
+        self._check(lib().prior_ls_get_tuning(self._h, C.byref(t)), "prior_ls_get_tuning")
+        return t.as_dict()
 
     def step(self, n_iter, outputs=("L", "S", "X", "M")):
         """prior_ls_step: continue the resident iteration."""

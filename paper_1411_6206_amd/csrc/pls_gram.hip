@@ -23,9 +23,15 @@ constexpr int npair() { return (2 * NB) * (2 * NB + 1) / 2; }
 
 int gram_tiles(int nt) { return nt <= 16 ? npair<1>() : npair<2>(); }
 
-int gram_blocks(int N) {
-    int vpb = (N + kGramBlocks - 1) / kGramBlocks;
-    vpb = (vpb + 127) / 128 * 128;
+// Voxels per block for a target block count (0 = the default), a multiple of 128.
+int gram_vpb(int N, int target) {
+    const int t = target > 0 ? target : kGramBlocks;
+    int vpb = (N + t - 1) / t;
+    return (vpb + 127) / 128 * 128;
+}
+
+int gram_blocks(int N, int target) {
+    const int vpb = gram_vpb(N, target);
     return (N + vpb - 1) / vpb;
 }
 
@@ -277,8 +283,7 @@ __global__ void __launch_bounds__(256) pls_gram_bf16x3_kernel(GramArgs a) {
 
 int launch_gram(int mode, const GramArgs& a0, hipStream_t s) {
     GramArgs a = a0;
-    int vpb = (a.N + kGramBlocks - 1) / kGramBlocks;
-    vpb = (vpb + 127) / 128 * 128;
+    const int vpb = gram_vpb(a.N, a.target_blocks);
     a.vox_per_block = vpb;
     const int grid = (a.N + vpb - 1) / vpb;
     const bool one = a.nt <= 16;

@@ -72,10 +72,11 @@ struct GramArgs {
     const float2* C;       // [nt][N]
     double* part;          // [blocks][NTILE * 256]
     int N, nt, vox_per_block;
+    int target_blocks;     // split of the voxels into about this many blocks (0 = default)
 };
 // returns number of blocks
 int launch_gram(int mode, const GramArgs& a, hipStream_t s);
-int gram_blocks(int N);
+int gram_blocks(int N, int target = 0);
 int gram_tiles(int nt);
 void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s);
 
@@ -99,6 +100,7 @@ struct BpArgs {
     float2* L;
     const float* Wop;
     int N, nt;
+    int max_grid;          // workgroups at most (0 = default)
 };
 void launch_bp(const BpArgs& a, hipStream_t s);
 

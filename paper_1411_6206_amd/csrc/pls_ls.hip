@@ -76,7 +76,8 @@ __global__ void __launch_bounds__(256) pls_bp_kernel(BpArgs a) {
 
 void launch_bp(const BpArgs& a, hipStream_t s) {
     const int tiles = (a.N + 63) / 64;
-    const int grid = tiles < 2048 ? tiles : 2048;
+    const int cap = a.max_grid > 0 ? a.max_grid : 2048;
+    const int grid = tiles < cap ? tiles : cap;
     if (a.nt <= 16)
         hipLaunchKernelGGL(pls_bp_kernel<1>, dim3(grid), dim3(256), 0, s, a);
     else

@@ -33,6 +33,7 @@ namespace {
 
 constexpr int kStatRec = 64;          // doubles per iteration record
 constexpr int kMaxChunk = 1024;
+constexpr int kMaxGramBlocks = 2048;  // largest Gram split the tuner tries
 
 struct HipError {
     hipError_t e;
@@ -121,7 +122,7 @@ Sizes sizes_of(const prior_ls_dims& d) {
     s.P = (size_t)d.ny * d.nz;
     s.N = s.P * d.nx;
     s.I = s.N * d.nt;
-    s.gblocks = pls::gram_blocks((int)s.N);
+    s.gblocks = pls::gram_blocks((int)s.N, kMaxGramBlocks);   // the largest split tuning tries
     s.gentries = pls::gram_tiles(d.nt) * 256;
     s.dcb = pls::dc_blocks(d.ny, d.nz, d.nx, d.nt);
     s.spb = sparse_blocks(d);
@@ -191,6 +192,7 @@ struct prior_ls_handle {
     int iters = 0;
     bool loaded = false;
     prior_ls_params params{};
+    prior_ls_tuning tuning{sizeof(prior_ls_tuning), 0, 0, 0, 0, 0.0};
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
     std::string err;
@@ -266,16 +268,24 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     auto mark = [&](int k, hipStream_t st) {
         if (ev) PLS_HIP(hipEventRecord(ev[k], st));
     };
+    // The sparse update forks off after the Gram pass (it then fills the GPU beside the
+    // one-block eigensolve instead of competing with the Gram for bandwidth), or, with
+    // tuning.sparse_fork = 1, at the start of the iteration.
+    const bool fork_first = h->tuning.sparse_fork == 1;
+    if (fork_first) {
+        PLS_HIP(hipEventRecord(h->ev_fork, s));
+        PLS_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
+    }
     // steps (1)-(2): Gram, eigensolve, W, L_k = C W   [main stream]
     mark(0, s);
-    pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0};
+    pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0, h->tuning.gram_blocks};
     const int gb = pls::launch_gram(d.gram_mode, ga, s);
     mark(1, s);
-    PLS_HIP(hipEventRecord(h->ev_fork, s));
-    PLS_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
-    // step (3), forked after the Gram pass so that it fills the GPU beside the one-block
-    // eigensolve rather than competing with the Gram for bandwidth:
-    // S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)   [side stream]
+    if (!fork_first) {
+        PLS_HIP(hipEventRecord(h->ev_fork, s));
+        PLS_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
+    }
+    // step (3): S_k = T^-1 soft(T(M_{k-1} - L_{k-1}))   (M = C + S)   [side stream]
     pls::SparseArgs sa{};
     sa.C = h->C;
     sa.S = h->S[p];
@@ -312,7 +322,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     mark(4, s);
     pls::launch_eig(ea, s);
     mark(5, s);
-    pls::BpArgs ba{h->C, h->L[q], h->Wop, (int)sz.N, d.nt};
+    pls::BpArgs ba{h->C, h->L[q], h->Wop, (int)sz.N, d.nt, h->tuning.bp_grid};
     mark(8, s);
     pls::launch_bp(ba, s);
     mark(9, s);
@@ -717,6 +727,47 @@ int shift_window(prior_ls_handle* h, const void* kspace_frame, const uint8_t* ma
     return PRIOR_LS_OK;
 }
 
+int check_inputs(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* params) {
+    if (!in) return fail(h, PRIOR_LS_EINVAL, "inputs is NULL");
+    const int rc = check_params(h, params);
+    if (rc) return rc;
+    if (!in->kspace || !in->mask) return fail(h, PRIOR_LS_EINVAL, "kspace and mask are required");
+    if (h->d.nc > 1 && !in->sens) return fail(h, PRIOR_LS_EINVAL, "sens is required when nc > 1");
+    if ((in->L0 == nullptr) != (in->S0 == nullptr)) return fail(h, PRIOR_LS_EINVAL, "L0 and S0: both or neither");
+    if (params->lambda_p > 0 && !in->sigma_prev) return fail(h, PRIOR_LS_EINVAL, "sigma_prev is required when lambda_p > 0");
+    const void* dev[] = {in->kspace, in->mask, in->sens, in->prior_w, in->L0, in->S0};
+    for (const void* p : dev)
+        if (p && !is_device_ptr(p)) return fail(h, PRIOR_LS_EINVAL, "input array is not device memory");
+    return PRIOR_LS_OK;
+}
+
+int check_tuning(prior_ls_handle* h, const prior_ls_tuning* t) {
+    if (!t || t->struct_size != sizeof(prior_ls_tuning)) return fail(h, PRIOR_LS_EINVAL, "tuning.struct_size mismatch");
+    if (t->gram_blocks != 0 && (t->gram_blocks < 64 || t->gram_blocks > kMaxGramBlocks))
+        return fail(h, PRIOR_LS_EINVAL, "gram_blocks must be 0 or in [64, 2048]");
+    if (t->bp_grid != 0 && (t->bp_grid < 64 || t->bp_grid > 65536))
+        return fail(h, PRIOR_LS_EINVAL, "bp_grid must be 0 or in [64, 65536]");
+    if (t->sparse_fork != 0 && t->sparse_fork != 1) return fail(h, PRIOR_LS_EINVAL, "sparse_fork must be 0 or 1");
+    if (t->reserved != 0) return fail(h, PRIOR_LS_EINVAL, "tuning.reserved must be 0");
+    return PRIOR_LS_OK;
+}
+
+// Milliseconds per iteration of one chunk of the current choice: the chunk is captured and
+// run once untimed, then replayed between two events.
+double time_choice(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* p,
+                   hipEvent_t e0, hipEvent_t e1) {
+    if (load_problem(h, in, p) != PRIOR_LS_OK) return -1.0;
+    const int n = std::max(1, std::min(p->check_every, kMaxChunk));
+    run_chunk(h, n);
+    PLS_HIP(hipEventRecord(e0, h->stream));
+    run_chunk(h, n);
+    PLS_HIP(hipEventRecord(e1, h->stream));
+    PLS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    PLS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms / n;
+}
+
 }  // namespace
 
 namespace pls {
@@ -910,18 +961,10 @@ int prior_ls_solve(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls
     if (!h) return PRIOR_LS_EINVAL;
     h->err.clear();
     const auto t0 = std::chrono::steady_clock::now();
-    if (!in) return fail(h, PRIOR_LS_EINVAL, "inputs is NULL");
-    int rc = check_params(h, params);
+    int rc = check_inputs(h, in, params);
     if (rc) return rc;
     if (stats && stats->struct_size != sizeof(prior_ls_stats))
         return fail(h, PRIOR_LS_EINVAL, "stats.struct_size mismatch");
-    if (!in->kspace || !in->mask) return fail(h, PRIOR_LS_EINVAL, "kspace and mask are required");
-    if (h->d.nc > 1 && !in->sens) return fail(h, PRIOR_LS_EINVAL, "sens is required when nc > 1");
-    if ((in->L0 == nullptr) != (in->S0 == nullptr)) return fail(h, PRIOR_LS_EINVAL, "L0 and S0: both or neither");
-    if (params->lambda_p > 0 && !in->sigma_prev) return fail(h, PRIOR_LS_EINVAL, "sigma_prev is required when lambda_p > 0");
-    const void* dev[] = {in->kspace, in->mask, in->sens, in->prior_w, in->L0, in->S0};
-    for (const void* p : dev)
-        if (p && !is_device_ptr(p)) return fail(h, PRIOR_LS_EINVAL, "input array is not device memory");
     if (out) {
         const void* o[] = {out->L, out->S, out->X, out->M};
         for (const void* p : o)
@@ -940,6 +983,84 @@ int prior_ls_solve(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls
         fill_stats(h, stats, conv, ms);
         return r;
     });
+}
+
+int prior_ls_set_tuning(prior_ls_handle* h, const prior_ls_tuning* t) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    const int rc = check_tuning(h, t);
+    if (rc) return rc;
+    h->tuning = *t;
+    h->clear_graphs();
+    return PRIOR_LS_OK;
+}
+
+int prior_ls_get_tuning(const prior_ls_handle* h, prior_ls_tuning* t) {
+    if (!h || !t || t->struct_size != sizeof(prior_ls_tuning)) return PRIOR_LS_EINVAL;
+    *t = h->tuning;
+    return PRIOR_LS_OK;
+}
+
+int prior_ls_tune(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* params,
+                  prior_ls_tuning* best) {
+    if (!h) return PRIOR_LS_EINVAL;
+    h->err.clear();
+    int rc = check_inputs(h, in, params);
+    if (rc) return rc;
+    if (best && best->struct_size != sizeof(prior_ls_tuning))
+        return fail(h, PRIOR_LS_EINVAL, "tuning.struct_size mismatch");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = guarded(h, [&]() -> int {
+        PLS_HIP(hipEventCreate(&e0));
+        PLS_HIP(hipEventCreate(&e1));
+        enter(h);
+        prior_ls_params p = *params;
+        p.use_graph = 1;
+        prior_ls_tuning cur = h->tuning;
+        h->tuning = cur;
+        double best_ms = time_choice(h, in, &p, e0, e1);
+        if (best_ms < 0) return fail(h, PRIOR_LS_EINVAL, "cannot load the problem");
+        // one knob at a time, each from the best choice so far
+        const int forks[] = {0, 1};
+        const int grams[] = {256, 512, 1024, 2048};
+        const int grids[] = {1024, 2048, 4096, 8192};
+        auto trial = [&](prior_ls_tuning t) {
+            h->tuning = t;
+            h->clear_graphs();
+            const double ms = time_choice(h, in, &p, e0, e1);
+            if (ms >= 0 && ms < best_ms) {
+                best_ms = ms;
+                cur = t;
+            }
+        };
+        for (int v : forks) {
+            prior_ls_tuning t = cur;
+            t.sparse_fork = v;
+            if (v != cur.sparse_fork) trial(t);
+        }
+        for (int v : grams) {
+            prior_ls_tuning t = cur;
+            t.gram_blocks = v;
+            if (v != cur.gram_blocks) trial(t);
+        }
+        for (int v : grids) {
+            prior_ls_tuning t = cur;
+            t.bp_grid = v;
+            if (v != cur.bp_grid) trial(t);
+        }
+        cur.ms_per_iteration = best_ms;
+        h->tuning = cur;
+        h->clear_graphs();
+        h->params = *params;
+        const int r = load_problem(h, in, params);
+        leave(h);
+        PLS_HIP(hipStreamSynchronize(h->stream));
+        if (best) *best = cur;
+        return r;
+    });
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int prior_ls_step(prior_ls_handle* h, int32_t n_iter, const prior_ls_outputs* out, prior_ls_stats* stats) {
@@ -1085,7 +1206,7 @@ int prior_ls_op_svt(prior_ls_handle* h, const void* C, void* L, double* sigma) {
         enter(h);
         hipStream_t s = h->stream;
         pls::launch_pack((const float2*)C, nullptr, h->T1, d.nt, d.nx, d.ny, d.nz, s);
-        pls::GramArgs ga{h->T1, h->gpart, (int)h->sz.N, d.nt, 0};
+        pls::GramArgs ga{h->T1, h->gpart, (int)h->sz.N, d.nt, 0, h->tuning.gram_blocks};
         const int gb = pls::launch_gram(d.gram_mode, ga, s);
         pls::launch_gram_reduce(h->gpart, gb, h->sz.gentries, h->gred, s);
         set_identity_V(h, h->Vop);
@@ -1103,7 +1224,7 @@ int prior_ls_op_svt(prior_ls_handle* h, const void* C, void* L, double* sigma) {
         ea.lambda_p = h->params.lambda_p;
         ea.relative = h->params.lambda_L_relative;
         pls::launch_eig(ea, s);
-        pls::BpArgs ba{h->T1, h->T2, h->Wopop, (int)h->sz.N, d.nt};
+        pls::BpArgs ba{h->T1, h->T2, h->Wopop, (int)h->sz.N, d.nt, h->tuning.bp_grid};
         pls::launch_bp(ba, s);
         pls::launch_unpack(h->T2, nullptr, (float2*)L, d.nt, d.nx, d.ny, d.nz, s);
         PLS_HIP(hipGetLastError());

@@ -36,8 +36,9 @@ bool dc_supported(int ny, int nz) { return ny >= 16 && ny <= 256 && nz >= 1 && n
 bool xifft_supported(int nx) { return nx >= 16 && nx <= 256; }
 int dc_blocks(int ny, int nz, int nx, int nt) { return nx * nt; }
 int gram_tiles(int nt) { return nt <= 16 ? 3 : 10; }
-int gram_blocks(int N) {
-    int vpb = (N + 511) / 512;
+int gram_blocks(int N, int target) {
+    const int t = target > 0 ? target : 512;
+    int vpb = (N + t - 1) / t;
     vpb = (vpb + 127) / 128 * 128;
     return (N + vpb - 1) / vpb;
 }
@@ -135,7 +136,7 @@ void launch_add(const float2* a, const float2* b, float2* out, size_t n, hipStre
 }
 int launch_gram(int mode, const GramArgs& a, hipStream_t s) {
     GramArgs c = a;
-    const int gb = gram_blocks(c.N);
+    const int gb = gram_blocks(c.N, c.target_blocks);
     fh_stream(s)->push([c, gb] {
         look(c.C, (size_t)c.N * c.nt);
         touch(c.part, (size_t)gb * gram_tiles(c.nt) * 256);

@@ -46,7 +46,7 @@ def test_struct_layouts_match_a_c_compiler(tmp_path):
                "prior_ls_inputs": pls.Inputs, "prior_ls_outputs": pls.Outputs,
                "prior_ls_stats": pls.Stats, "prior_ls_server_config": pls.ServerConfig,
                "prior_ls_request": pls.Request, "prior_ls_result": pls.Result,
-               "prior_ls_server_stats": pls.ServerStats}
+               "prior_ls_server_stats": pls.ServerStats, "prior_ls_tuning": pls.Tuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "prior_ls.h"', 'int main(void) {']
     for cname, py in structs.items():
         last = py._fields_[-1][0]
