@@ -244,6 +244,8 @@ def main():
                     help="skip the per-Gram-mode comparison (short profiling runs)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes, no autotuning")
+    ap.add_argument("--no-transforms", action="store_true",
+                    help="skip the temporal-Fourier transform measurement")
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -405,6 +407,25 @@ def main():
     out["gram_modes"] = modes or None
     out["gram_modes_sample"] = (f"{iters} iterations, {len(fx['idx'])} sampled voxels of the "
                                 f"committed FP64-oracle fixture") if fx is not None and modes else None
+    # the temporal-Fourier sparsifying transform on the same problem (no prior weights:
+    # the workload's weights are Haar-domain): throughput and its sparse-update kernel
+    if not args.no_transforms:
+        with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, gram_mode=args.gram_mode,
+                         transform="tfft") as ht:
+            ht.solve(t["kspace"], t["mask"], t["sens"], None, max_iter=args.warmup, outputs=(),
+                     **solve_kw)
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            kmt, _ = ht.step_timed(args.steps)
+            torch.cuda.synchronize()
+            per = kmt["sparse"] / args.steps
+            b = 4 * p.nx * p.ny * p.nz * p.nt * 8 + p.nx * p.ny * p.nz * p.nt
+            out["transforms"] = {"tfft": {
+                "iterations_per_s": args.steps / (time.perf_counter() - a0),
+                "sparse_ms": per, "sparse_GB_s": b / (per * 1e-3) / 1e9,
+                "sparse_hbm_frac": b / (per * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "note": "unitary DFT along frames on FP32 MFMA, forward and inverse fused "
+                        "with the shrink in one kernel"}}
     del t
     torch.cuda.empty_cache()
     if not args.no_serving:

@@ -66,6 +66,12 @@ extern "C" {
 #define PRIOR_LS_GRAM_BF16X3 2  /* Gram on BF16 MFMA with hi+lo split (3 products), FP32
                                    accumulate, FP64 across blocks */
 
+#define PRIOR_LS_T_HAAR      0  /* orthonormal Haar, J = wavelet_levels levels over space */
+#define PRIOR_LS_T_TFFT      1  /* unitary DFT along the frames of every voxel (coefficient
+                                   f of voxel v is its temporal frequency f); prior weights
+                                   are then [nt (frequency)][nz][ny][nx] and wavelet_levels
+                                   is not used */
+
 #define PRIOR_LS_MAX_NT 32
 
 typedef struct prior_ls_handle prior_ls_handle;   /* opaque; owns all device state */
@@ -73,14 +79,15 @@ typedef struct prior_ls_handle prior_ls_handle;   /* opaque; owns all device sta
 /* Problem geometry, fixed for the life of a handle.
  * Supported: ny in {16,24,32,48,64,96,128,192,256}, nz in {1,4,8,16,32} (nz = 1 is the 2D
  * case), nx in {16,24,32,48,64,96,128,192,256}, 1 <= nt <= 32, 1 <= nc <= 64,
- * wavelet_levels J in [0,3] with every spatial axis of size > 1 divisible by 2^J
- * (J = 0 means T is the identity).  Anything else returns PRIOR_LS_ESHAPE. */
+ * wavelet_levels J in [0,3] with, for the Haar transform, every spatial axis of size > 1
+ * divisible by 2^J (J = 0 means T is the identity).  Anything else returns PRIOR_LS_ESHAPE. */
 typedef struct {
     size_t   struct_size;       /* = sizeof(prior_ls_dims) */
     int32_t  nx, ny, nz, nt, nc;
     int32_t  wavelet_levels;    /* J */
     int32_t  gram_mode;         /* PRIOR_LS_GRAM_* */
-    int32_t  reserved;          /* must be 0 */
+    int32_t  transform;         /* sparsifying transform T: PRIOR_LS_T_HAAR (0) or
+                                   PRIOR_LS_T_TFFT (1) */
     uint64_t hbm_budget;        /* bytes of device memory the handle may own; 0 = unlimited */
 } prior_ls_dims;
 

@@ -126,6 +126,30 @@ def haar_inv(c, levels):
 
 
 # --------------------------------------------------------------------------------------
+# A second sparsifying transform (Section 2 leaves T generic; the L+S method the paper builds
+# on uses the temporal Fourier transform for cardiac series): the unitary DFT along the
+# frames of every voxel.  Coefficient (f, z, y, x) is temporal frequency f of voxel (z,y,x).
+# --------------------------------------------------------------------------------------
+def tfft_fwd(x):
+    return np.fft.fft(np.asarray(x, np.complex128), axis=0, norm="ortho")
+
+
+def tfft_inv(c):
+    return np.fft.ifft(np.asarray(c, np.complex128), axis=0, norm="ortho")
+
+
+TRANSFORMS = ("haar", "tfft")
+
+
+def T_fwd(x, levels, transform="haar"):
+    return haar_fwd(x, levels) if transform == "haar" else tfft_fwd(x)
+
+
+def T_inv(c, levels, transform="haar"):
+    return haar_inv(c, levels) if transform == "haar" else tfft_inv(c)
+
+
+# --------------------------------------------------------------------------------------
 # Casorati matrix.  Reading: rows = voxels of one volume, columns = the nt time frames
 # (the L+S convention the paper builds on), so cas(X) is N x nt.
 # --------------------------------------------------------------------------------------
@@ -197,12 +221,12 @@ def svt_gram(C, lambda_L, relative=True, lambda_p=0.0, sigma_prev=None):
 # the literal T(S_{it-1}) would never see the data), and the support indicator is
 # generalised to a weight w in [0, 1] giving the threshold lambda_S (1 - w).
 # --------------------------------------------------------------------------------------
-def sparse_step(M_prev, L_prev, prior_w, lambda_S, levels):
-    Z = haar_fwd(M_prev - L_prev, levels)
+def sparse_step(M_prev, L_prev, prior_w, lambda_S, levels, transform="haar"):
+    Z = T_fwd(M_prev - L_prev, levels, transform)
     w = 0.0 if prior_w is None else prior_w.astype(np.float64) / 255.0
     tau = lambda_S * (1.0 - w)
     Zs = soft(Z, tau)
-    return haar_inv(Zs, levels), Zs
+    return T_inv(Zs, levels, transform), Zs
 
 
 # --------------------------------------------------------------------------------------
@@ -215,7 +239,7 @@ def dc_step(Y, d, mask, sens):
 
 def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=None,
           levels=2, iters=50, tol=0.0, L0=None, S0=None, lambda_L_relative=True,
-          svt_fn=None):
+          svt_fn=None, transform="haar"):
     """Algorithm 1 (Priori L+S), step by step, for `iters` iterations or until the
     relative change of the solution drops below tol (Section 3, stopping rule).
 
@@ -251,7 +275,7 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
                                          lambda_p, sigma_prev)
         L_new = uncas(Lc, shape)
         # step (3)
-        S_new, Zs = sparse_step(M, L, prior_w, lambda_S, levels)
+        S_new, Zs = sparse_step(M, L, prior_w, lambda_S, levels, transform)
         L, S = L_new, S_new
         supp = np.where(Zs != 0, 255, 0).astype(np.uint8)
         sigma_L = sig_t
@@ -296,18 +320,24 @@ def shift_window(a, new):
 
 
 def append_frame(prev, d, mask, sens, d_new, mask_new, lambda_L, lambda_S, lambda_p=0.0,
-                 levels=2, iters=20, tol=0.0, lambda_L_relative=True):
+                 levels=2, iters=20, tol=0.0, lambda_L_relative=True, transform="haar"):
     """One step of the sequence: prev is the result of solve() (or append_frame) for the
     window (d, mask); d_new [nc][nz][ny][nx] and mask_new [nz][ny] are the new frame.
-    Returns (result of the new window, its data, its mask)."""
+    Returns (result of the new window, its data, its mask).
+    Reading: with the temporal Fourier transform a coefficient is a temporal frequency of
+    the whole window, not a frame, and sliding the window by one frame changes the phase of
+    the spectrum, not its magnitude; its support prior is taken over unshifted."""
     d_next = np.concatenate([np.asarray(d)[:, 1:], np.asarray(d_new)[:, None]], axis=1)
     mask_next = shift_window(mask, mask_new)
     L0 = shift_window(prev["L"], prev["L"][-1])
     S0 = shift_window(prev["S"], prev["S"][-1])
-    w = shift_window(prev["supp"], prev["supp"][-1])
+    if transform == "haar":
+        w = shift_window(prev["supp"], prev["supp"][-1])
+    else:
+        w = np.array(prev["supp"], copy=True)
     r = solve(d_next, mask_next, sens, w, lambda_L, lambda_S, lambda_p=lambda_p,
               sigma_prev=prev["sigma_L"], levels=levels, iters=iters, tol=tol, L0=L0, S0=S0,
-              lambda_L_relative=lambda_L_relative)
+              lambda_L_relative=lambda_L_relative, transform=transform)
     return r, d_next, mask_next
 
 

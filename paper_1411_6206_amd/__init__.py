@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libprior_ls.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 GRAM_MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+TRANSFORMS = {"haar": 0, "tfft": 1}
 MAX_NT = 32
 
 # every symbol include/prior_ls.h declares
@@ -50,7 +51,7 @@ class Dims(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("nz", C.c_int32), ("nt", C.c_int32), ("nc", C.c_int32),
                 ("wavelet_levels", C.c_int32), ("gram_mode", C.c_int32),
-                ("reserved", C.c_int32), ("hbm_budget", C.c_uint64)]
+                ("transform", C.c_int32), ("hbm_budget", C.c_uint64)]
 
 
 class Params(C.Structure):
@@ -183,13 +184,15 @@ def lib():
     return L
 
 
-def make_dims(nx, ny, nz, nt, nc, wavelet_levels=2, gram_mode="fp64", hbm_budget=0):
+def make_dims(nx, ny, nz, nt, nc, wavelet_levels=2, gram_mode="fp64", hbm_budget=0,
+              transform="haar"):
     gm = GRAM_MODES[gram_mode] if isinstance(gram_mode, str) else int(gram_mode)
-    return Dims(C.sizeof(Dims), nx, ny, nz, nt, nc, wavelet_levels, gm, 0, hbm_budget)
+    tf = TRANSFORMS[transform] if isinstance(transform, str) else int(transform)
+    return Dims(C.sizeof(Dims), nx, ny, nz, nt, nc, wavelet_levels, gm, tf, hbm_budget)
 
 
-def plan_bytes(nx, ny, nz, nt, nc, wavelet_levels=2, gram_mode="fp64"):
-    d = make_dims(nx, ny, nz, nt, nc, wavelet_levels, gram_mode)
+def plan_bytes(nx, ny, nz, nt, nc, wavelet_levels=2, gram_mode="fp64", transform="haar"):
+    d = make_dims(nx, ny, nz, nt, nc, wavelet_levels, gram_mode, transform=transform)
     return int(lib().prior_ls_plan_bytes(C.byref(d)))
 
 
@@ -214,10 +217,11 @@ class PriorLS:
     """One problem geometry (prior_ls_create); owns the device state until close()."""
 
     def __init__(self, nx, ny, nz, nt, nc, wavelet_levels=2, gram_mode="fp64",
-                 hbm_budget=0, stream=None):
+                 hbm_budget=0, stream=None, transform="haar"):
         L = lib()
         self._h = C.c_void_p()
-        self.dims = make_dims(nx, ny, nz, nt, nc, wavelet_levels, gram_mode, hbm_budget)
+        self.dims = make_dims(nx, ny, nz, nt, nc, wavelet_levels, gram_mode, hbm_budget,
+                              transform)
         self.shape = (nt, nz, ny, nx)
         st = _current_stream() if stream is None else C.c_void_p(stream)
         rc = L.prior_ls_create(C.byref(self.dims), st, C.byref(self._h))
@@ -288,7 +292,7 @@ class PriorLS:
         cache = cache or os.environ.get("PRIOR_LS_TUNE_CACHE")
         d = self.dims
         key = (f"{torch.cuda.get_device_name()}|{d.nx}x{d.ny}x{d.nz}x{d.nt}x{d.nc}|J{d.wavelet_levels}"
-               f"|gram{d.gram_mode}|chunk{check_every}")
+               f"|T{d.transform}|gram{d.gram_mode}|chunk{check_every}")
         book = {}
         if cache and os.path.exists(cache):
             with open(cache) as fh:

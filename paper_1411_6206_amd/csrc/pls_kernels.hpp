@@ -115,9 +115,13 @@ struct SparseArgs {
     double* part;          // per block: weighted l1 of the shrunk coefficients
     int nx, ny, nz, nt;
     float lambda_S;
+    const float* Wf;       // temporal transform only: MFMA operands of the forward DFT and
+    const float* Wi;       // of the inverse (its columns in the forward's output order)
 };
 // returns number of blocks
 int launch_sparse(int levels, const SparseArgs& a, hipStream_t s);
+int launch_sparse_tfft(const SparseArgs& a, hipStream_t s);
+int sparse_tfft_blocks(int N);
 
 struct StatsArgs {
     const double* dc_part;

@@ -222,6 +222,145 @@ int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
     return 0;
 }
 
+// ---------------------------------------------------------------- sparse update, temporal T
+// Step (3) with T the unitary DFT along the frames of each voxel: per tile of 16 voxels a
+// wave forms U = X - L_prev (all frames), Z = F U on FP32 MFMA (real-expanded, like the
+// back-projection), soft-thresholds Z in the accumulator registers, and forms S = F^H Z_s
+// with a second MFMA product.  The accumulator of the first product holds row
+// 16 mb + 4 g + r in register (mb, r) of lane group g, which is the B operand that the
+// second product's instruction 4 mb + r takes from lane group g once the inverse operator's
+// columns are listed in that order (done on the host): no data moves between the two.
+int sparse_tfft_blocks(int N) {
+    const int tiles = (N + 63) / 64;
+    return tiles < 2048 ? tiles : 2048;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) pls_tfft_sparse_kernel(SparseArgs a) {
+    constexpr int NTP = 16 * NB, K2 = 2 * NTP, MB = K2 / 16, KS = K2 / 4, KH = NTP / 4;
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, g = lane >> 4;
+    float Af[MB][KS], Ai[MB][KS];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            Af[mb][ks] = a.Wf[(16 * mb + i16) * K2 + 4 * ks + g];
+            Ai[mb][ks] = a.Wi[(16 * mb + i16) * K2 + 4 * ks + g];
+        }
+    const int N = a.nx * a.ny * a.nz;
+    const int nt = a.nt;
+    const int stride = gridDim.x * 4 * 16;
+    const bool has_s = a.S != nullptr, has_w = a.w != nullptr;
+    const float2* Sp = has_s ? a.S : a.C;
+    const uint8_t* wp = has_w ? a.w : reinterpret_cast<const uint8_t*>(a.C);
+    // frames clamped into range and voxels into the volume: every load is valid
+    auto load_tile = [&](int v0, float2 (&cb)[KH]) __attribute__((always_inline)) {
+        const int v = v0 + i16;
+        const int vc = v < N ? v : N - 1;
+        float2 c[KH], sv[KH], l[KH];
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) {
+            const int f = 4 * kk + g;
+            const int idx = (f < nt ? f : nt - 1) * N + vc;
+            c[kk] = a.C[idx];
+            sv[kk] = Sp[idx];
+            l[kk] = a.Lp[idx];
+        }
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) {
+            const float2 u = has_s ? cadd(c[kk], sv[kk]) : c[kk];
+            cb[kk] = (4 * kk + g < nt && v < N) ? csub(u, l[kk]) : make_float2(0.f, 0.f);
+        }
+    };
+    float l1 = 0.f;
+    int v0 = (blockIdx.x * 4 + wave) * 16;
+    float2 cb[KH];
+    if (v0 < N) load_tile(v0, cb);
+    for (; v0 < N; v0 += stride) {
+        float2 nb[KH];
+        const int vn = v0 + stride;
+        load_tile(vn < N ? vn : v0, nb);
+        const int v = v0 + i16;
+        const int vc = v < N ? v : N - 1;
+        // Z = F U
+        f4 z[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) z[mb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const float b = ks < KH ? cb[ks].x : cb[ks - KH].y;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                z[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[mb][ks], b, z[mb], 0, 0, 0);
+        }
+        // soft threshold of frequency f = 16 mb + 4 g + r (real part in z[mb], imaginary
+        // part in z[mb + MB/2])
+        uint8_t wq[MB / 2][4];
+#pragma unroll
+        for (int mb = 0; mb < MB / 2; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = 16 * mb + 4 * g + r;
+                wq[mb][r] = wp[(f < nt ? f : nt - 1) * N + vc];
+            }
+#pragma unroll
+        for (int mb = 0; mb < MB / 2; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = 16 * mb + 4 * g + r;
+                const bool valid = f < nt && v < N;
+                const float wk = has_w ? (float)wq[mb][r] * (1.0f / 255.0f) : 0.0f;
+                const float tau = a.lambda_S * (1.0f - wk);
+                const float zr = z[mb][r], zi = z[mb + MB / 2][r];
+                const float m2 = fmaf(zr, zr, zi * zi);
+                const bool keep = valid && m2 > tau * tau;
+                const float rm = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
+                const float sc = keep ? fmaf(-tau, rm, 1.0f) : 0.0f;
+                z[mb][r] = zr * sc;
+                z[mb + MB / 2][r] = zi * sc;
+                l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
+                if (a.supp && valid) a.supp[f * N + v] = keep ? 255 : 0;
+            }
+        // S = F^H Z_s: instruction 4 mb + r takes register (mb, r) as its B operand
+        f4 o[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) o[mb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float b = z[mb][r];
+#pragma unroll
+                for (int mo = 0; mo < MB; ++mo)
+                    o[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ai[mo][4 * mb + r], b, o[mo], 0, 0, 0);
+            }
+        if (v < N) {
+#pragma unroll
+            for (int mb = 0; mb < MB / 2; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int f = 16 * mb + 4 * g + r;
+                    if (f < nt) a.Sout[f * N + v] = make_float2(o[mb][r], o[mb + MB / 2][r]);
+                }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk) cb[kk] = nb[kk];
+    }
+    const double s = block_sum<256>((double)l1, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
+    const int grid = sparse_tfft_blocks(a.nx * a.ny * a.nz);
+    if (a.nt <= 16)
+        hipLaunchKernelGGL(pls_tfft_sparse_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(pls_tfft_sparse_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+    return grid;
+}
+
 // ---------------------------------------------------------------- statistics
 // stat record (doubles): [0] ||r||^2, [1] ||Y - Yold||^2, [2] ||Yold||^2, [3] weighted l1,
 // [4] nuclear norm, [5] tau_L, [6] Jacobi sweeps, [7] non-finite flag, [16..48) sigma

@@ -57,8 +57,8 @@ int check_dims(const prior_ls_dims* d, std::string& msg) {
         msg = "dims.struct_size mismatch";
         return PRIOR_LS_EINVAL;
     }
-    if (d->reserved != 0) {
-        msg = "dims.reserved must be 0";
+    if (d->transform != PRIOR_LS_T_HAAR && d->transform != PRIOR_LS_T_TFFT) {
+        msg = "unknown transform";
         return PRIOR_LS_EINVAL;
     }
     if (d->gram_mode < PRIOR_LS_GRAM_FP64 || d->gram_mode > PRIOR_LS_GRAM_BF16X3) {
@@ -90,6 +90,7 @@ int check_dims(const prior_ls_dims* d, std::string& msg) {
         msg = "wavelet_levels must be in [0, 3]";
         return PRIOR_LS_ESHAPE;
     }
+    if (d->transform == PRIOR_LS_T_TFFT) return PRIOR_LS_OK;   // J is not used
     if (!is_pow2_div(d->nx, J) || !is_pow2_div(d->ny, J) || !is_pow2_div(d->nz, J)) {
         msg = "every spatial axis of size > 1 must be divisible by 2^wavelet_levels";
         return PRIOR_LS_ESHAPE;
@@ -109,6 +110,7 @@ struct Sizes {
 };
 
 int sparse_blocks(const prior_ls_dims& d) {
+    if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz);
     const int J = d.wavelet_levels;
     const int B = 1 << J;
     const int ZW = d.nz > 1 ? B : 1;
@@ -135,6 +137,7 @@ Sizes sizes_of(const prior_ls_dims& d) {
     b += (uint64_t)(d.nx + d.ny + d.nz) * 8;            // twiddles
     b += (uint64_t)s.gblocks * s.gentries * 8 + s.gentries * 8;
     b += 64 * 64 * 4 + 2 * 32 * 32 * 16 + 64 * 8;
+    if (d.transform == PRIOR_LS_T_TFFT) b += 2 * 64 * 64 * 4;
     b += (uint64_t)s.dcb * 32 + (uint64_t)s.spb * 8 + (uint64_t)kMaxChunk * kStatRec * 8;
     s.base_bytes = b;
     return s;
@@ -160,6 +163,7 @@ struct prior_ls_handle {
     float2* S[2] = {nullptr, nullptr};
     float2* sens = nullptr;
     float2* ones = nullptr;          // the unit coil of a single-coil problem (nc == 1)
+    float *Wtf = nullptr, *Wti = nullptr;   // temporal transform: forward / inverse operands
     uint8_t* w = nullptr;
     bool has_w = false, has_sens = false;
     float2* dh = nullptr;
@@ -253,6 +257,50 @@ bool is_device_ptr(const void* p) {
     return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
 }
 
+// Step (3) with the handle's sparsifying transform.
+int launch_sparse_any(const prior_ls_handle* h, const pls::SparseArgs& sa, hipStream_t s) {
+    if (h->d.transform == PRIOR_LS_T_TFFT) return pls::launch_sparse_tfft(sa, s);
+    return pls::launch_sparse(h->d.wavelet_levels, sa, s);
+}
+
+// MFMA operands of the unitary temporal DFT (64 x 64 FP32, real-expanded, as the
+// back-projection's): forward F[f][t] = exp(-2 pi i f t / nt) / sqrt(nt) with rows (Re f,
+// Im f) and columns (Re t, Im t); inverse F^H with rows (Re t, Im t) and its columns in the
+// order in which the forward product leaves its rows in the accumulator registers.
+void upload_tfft_operands(prior_ls_handle* h) {
+    const int nt = h->d.nt;
+    const int NTP = nt <= 16 ? 16 : 32, K2 = 2 * NTP;
+    std::vector<float> wf(64 * 64, 0.f), wi(64 * 64, 0.f);
+    const double sc = 1.0 / std::sqrt((double)nt);
+    auto expand = [&](std::vector<double>& m, double sign) {
+        // m[o][k], o = (component, output index), k = (component, input index)
+        for (int a = 0; a < nt; ++a)
+            for (int b = 0; b < nt; ++b) {
+                const double ang = sign * 2.0 * M_PI * (double)((long)a * b % nt) / nt;
+                const double re = std::cos(ang) * sc, im = std::sin(ang) * sc;
+                m[a * K2 + b] = re;
+                m[a * K2 + NTP + b] = -im;
+                m[(NTP + a) * K2 + b] = im;
+                m[(NTP + a) * K2 + NTP + b] = re;
+            }
+    };
+    std::vector<double> F(K2 * K2, 0.0), G(K2 * K2, 0.0);
+    expand(F, -1.0);
+    expand(G, +1.0);
+    for (int o = 0; o < K2; ++o)
+        for (int k = 0; k < K2; ++k) {
+            wf[o * K2 + k] = (float)F[o * K2 + k];
+            // column k = 4 ks + g of the inverse's operand takes forward output row
+            // 16 (ks / 4) + 4 g + ks % 4
+            const int ks = k / 4, g = k % 4;
+            const int row = 16 * (ks / 4) + 4 * g + ks % 4;
+            wi[o * K2 + k] = (float)G[o * K2 + row];
+        }
+    PLS_HIP(hipMemcpyAsync(h->Wtf, wf.data(), wf.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    PLS_HIP(hipMemcpyAsync(h->Wti, wi.data(), wi.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    PLS_HIP(hipStreamSynchronize(h->stream));
+}
+
 // one iteration of Algorithm 1 on the resident state (see the schedule in the header)
 // One iteration of Algorithm 1 on the resident state.  Steps (1)-(2) (Gram, eigensolve,
 // back-projection) run on the main stream while step (3) (sparse update) runs on the side
@@ -300,7 +348,9 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     sa.nt = d.nt;
     sa.lambda_S = (float)h->params.lambda_S;
     mark(6, s2);
-    const int spb = pls::launch_sparse(d.wavelet_levels, sa, s2);
+    sa.Wf = h->Wtf;
+    sa.Wi = h->Wti;
+    const int spb = launch_sparse_any(h, sa, s2);
     mark(7, s2);
     PLS_HIP(hipEventRecord(h->ev_join, s2));
     mark(2, s);
@@ -564,7 +614,9 @@ int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_p
         pls::launch_pack((const float2*)in->sens, nullptr, h->sens, d.nc, d.nx, d.ny, d.nz, s);
     }
     h->has_w = in->prior_w != nullptr;
-    if (h->has_w) pls::launch_pack_weights(in->prior_w, h->w, d.nt, d.nx, d.ny, d.nz, d.wavelet_levels, s);
+    if (h->has_w)
+        pls::launch_pack_weights(in->prior_w, h->w, d.nt, d.nx, d.ny, d.nz,
+                                 d.transform == PRIOR_LS_T_TFFT ? 0 : d.wavelet_levels, s);
     std::vector<double> sp(d.nt, 0.0);
     if (p->lambda_p > 0 && in->sigma_prev) {
         for (int i = 0; i < d.nt; ++i) sp[i] = in->sigma_prev[i];
@@ -711,8 +763,13 @@ int shift_window(prior_ls_handle* h, const void* kspace_frame, const uint8_t* ma
     }
     h->cur = q;
     // a-priori knowledge: support of T(S) shifted the same way, singular values of L
-    if (nt > 1) PLS_HIP(hipMemcpyAsync(h->w, h->supp + N, (nt - 1) * N, hipMemcpyDeviceToDevice, s));
-    PLS_HIP(hipMemcpyAsync(h->w + (nt - 1) * N, h->supp + (nt - 1) * N, N, hipMemcpyDeviceToDevice, s));
+    if (d.transform == PRIOR_LS_T_TFFT) {
+        // a coefficient is a temporal frequency of the window: the support carries over
+        PLS_HIP(hipMemcpyAsync(h->w, h->supp, (size_t)nt * N, hipMemcpyDeviceToDevice, s));
+    } else {
+        if (nt > 1) PLS_HIP(hipMemcpyAsync(h->w, h->supp + N, (nt - 1) * N, hipMemcpyDeviceToDevice, s));
+        PLS_HIP(hipMemcpyAsync(h->w + (nt - 1) * N, h->supp + (nt - 1) * N, N, hipMemcpyDeviceToDevice, s));
+    }
     PLS_HIP(hipMemcpyAsync(h->sigma_prev, h->sigL, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (!h->has_w || !same_captured_params(h->params, *params)) h->clear_graphs();
     h->has_w = true;
@@ -922,10 +979,15 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
         h->dc_part = h->alloc<double>((size_t)sz.dcb * 4 * sizeof(double));
         h->sp_part = h->alloc<double>((size_t)std::max(sz.spb, 1) * sizeof(double));
         h->stats_d = h->alloc<double>((size_t)kMaxChunk * kStatRec * sizeof(double));
+        if (d.transform == PRIOR_LS_T_TFFT) {
+            h->Wtf = h->alloc<float>(64 * 64 * sizeof(float));
+            h->Wti = h->alloc<float>(64 * 64 * sizeof(float));
+        }
         PLS_HIP(hipHostMalloc((void**)&h->stats_h, kStatRec * sizeof(double), hipHostMallocDefault));
         upload_twiddles(h->twx, d.nx, h->stream);
         upload_twiddles(h->twy, d.ny, h->stream);
         upload_twiddles(h->twz, d.nz, h->stream);
+        if (d.transform == PRIOR_LS_T_TFFT) upload_tfft_operands(h);
         PLS_HIP(hipMemsetAsync(h->stats_d, 0, (size_t)kMaxChunk * kStatRec * sizeof(double), h->stream));
         PLS_HIP(hipStreamSynchronize(h->stream));
         return PRIOR_LS_OK;
@@ -1263,7 +1325,9 @@ int prior_ls_op_sparse(prior_ls_handle* h, const void* Xm, const void* Lp, void*
         sa.nz = d.nz;
         sa.nt = d.nt;
         sa.lambda_S = (float)h->params.lambda_S;
-        pls::launch_sparse(d.wavelet_levels, sa, s);
+        sa.Wf = h->Wtf;
+        sa.Wi = h->Wti;
+        launch_sparse_any(h, sa, s);
         pls::launch_unpack(h->T1, nullptr, (float2*)S, d.nt, d.nx, d.ny, d.nz, s);
         PLS_HIP(hipGetLastError());
         leave(h);

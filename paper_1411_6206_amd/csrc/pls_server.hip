@@ -48,7 +48,8 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 bool same_dims(const prior_ls_dims& a, const prior_ls_dims& b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.nt == b.nt && a.nc == b.nc &&
-           a.wavelet_levels == b.wavelet_levels && a.gram_mode == b.gram_mode;
+           a.wavelet_levels == b.wavelet_levels && a.gram_mode == b.gram_mode &&
+           a.transform == b.transform;
 }
 
 bool on_device(const void* p) {

@@ -186,6 +186,29 @@ int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
     });
     return blocks;
 }
+int sparse_tfft_blocks(int N) {
+    const int tiles = (N + 63) / 64;
+    return tiles < 2048 ? tiles : 2048;
+}
+int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
+    SparseArgs c = a;
+    const int blocks = sparse_tfft_blocks(c.nx * c.ny * c.nz);
+    fh_stream(s)->push([c, blocks] {
+        const size_t I = (size_t)c.nx * c.ny * c.nz * c.nt;
+        look(c.C, I);
+        look(c.S, c.S ? I : 0);
+        look(c.Lp, I);
+        look(c.w, c.w ? I : 0);
+        look(c.Wf, 64 * 64);
+        look(c.Wi, 64 * 64);
+        touch(c.Sout, I);
+        if (c.supp) touch(c.supp, I);
+        touch(c.part, (size_t)blocks);
+        work_us(40);
+    });
+    return blocks;
+}
+
 void launch_stats(const StatsArgs& a, hipStream_t s) {
     StatsArgs c = a;
     fh_stream(s)->push([c] {

@@ -135,7 +135,7 @@ def test_create_rejects_null_and_size_mismatch():
     d.struct_size = 12
     assert L.prior_ls_create(C.byref(d), None, C.byref(h)) == pls.EINVAL
     d = pls.make_dims(64, 64, 1, 16, 1)
-    d.reserved = 1
+    d.transform = 7                                   # unknown transform
     assert L.prior_ls_create(C.byref(d), None, C.byref(h)) == pls.EINVAL
     assert L.prior_ls_create(C.byref(pls.make_dims(64, 64, 1, 16, 1)), None, None) == pls.EINVAL
 
@@ -145,6 +145,12 @@ def test_budget_below_plan_is_enomem():
     assert need > 5 * 64 * 64 * 16 * 8
     rc, h, msg = _create(hbm_budget=need // 2)
     assert rc == pls.ENOMEM, msg
+
+
+def test_temporal_transform_ignores_the_haar_divisibility():
+    # nz = 4 with J = 3 is invalid for Haar, valid for the temporal transform
+    assert pls.plan_bytes(16, 16, 4, 6, 2, wavelet_levels=3) == 0
+    assert pls.plan_bytes(16, 16, 4, 6, 2, wavelet_levels=3, transform="tfft") > 0
 
 
 def test_plan_bytes_zero_for_invalid():

@@ -374,3 +374,39 @@ def test_recovery_improves_on_zero_filled():
     r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, 0.01, 0.01, levels=2, iters=30)
     zf = oracle.EH(p.kspace, p.mask, p.sens)
     assert oracle.psnr(r["X"], p.X_true) > oracle.psnr(zf, p.X_true) + 1.0
+
+
+# ---- the temporal Fourier sparsifying transform (tfft) ------------------------------------
+def test_tfft_is_the_unitary_dft_along_frames():
+    # against the DFT matrix written out from its definition, and unitarity
+    rng = np.random.default_rng(41)
+    nt = 5
+    x = rng.standard_normal((nt, 2, 3, 4)) + 1j * rng.standard_normal((nt, 2, 3, 4))
+    f = np.arange(nt)
+    Fm = np.exp(-2j * np.pi * np.outer(f, f) / nt) / np.sqrt(nt)
+    want = np.einsum("ft,tzyx->fzyx", Fm, x)
+    np.testing.assert_allclose(oracle.tfft_fwd(x), want, atol=1e-13)
+    np.testing.assert_allclose(oracle.tfft_inv(want), x, atol=1e-13)
+    assert np.linalg.norm(oracle.tfft_fwd(x)) == pytest.approx(np.linalg.norm(x), rel=1e-13)
+
+
+def test_tfft_sparse_step_keeps_a_single_temporal_frequency():
+    # a voxel series that is one complex exponential has one nonzero coefficient, of
+    # magnitude sqrt(nt) |a|; the soft threshold shrinks it by tau and leaves the frequency
+    nt = 8
+    t = np.arange(nt)[:, None, None, None]
+    a, k = 0.7 - 0.2j, 3
+    X = a * np.exp(2j * np.pi * k * t / nt) * np.ones((1, 1, 2, 2))
+    S, Zs = oracle.sparse_step(X, np.zeros_like(X), None, 0.1, 0, transform="tfft")
+    mag = np.sqrt(nt) * abs(a)
+    assert np.count_nonzero(np.abs(Zs) > 1e-12) == 4
+    np.testing.assert_allclose(np.abs(Zs[k]), mag - 0.1, atol=1e-12)
+    np.testing.assert_allclose(S, X * (mag - 0.1) / mag, atol=1e-12)
+
+
+def test_tfft_full_weight_prior_passes_everything():
+    rng = np.random.default_rng(42)
+    X = rng.standard_normal((6, 1, 4, 4)) + 1j * rng.standard_normal((6, 1, 4, 4))
+    w = np.full(X.shape, 255, np.uint8)
+    S, _ = oracle.sparse_step(X, 0 * X, w, 5.0, 0, transform="tfft")
+    np.testing.assert_allclose(S, X, atol=1e-12)
