@@ -77,8 +77,9 @@ extern "C" {
 typedef struct prior_ls_handle prior_ls_handle;   /* opaque; owns all device state */
 
 /* Problem geometry, fixed for the life of a handle.
- * Supported: ny in {16,24,32,48,64,96,128,192,256}, nz in {1,4,8,16,32} (nz = 1 is the 2D
- * case), nx in {16,24,32,48,64,96,128,192,256}, 1 <= nt <= 32, 1 <= nc <= 64,
+ * Supported: ny in {16,24,32,48,64,96,128,192,256} with nz in {1,4,8,16,32} (nz = 1 is the
+ * 2D case), or nz = 14 with ny in {16,32,64,128,256} (radix 7 along z);
+ * nx in {16,24,32,48,64,96,128,192,256}, 1 <= nt <= 32, 1 <= nc <= 64,
  * wavelet_levels J in [0,3] with, for the Haar transform, every spatial axis of size > 1
  * divisible by 2^J (J = 0 means T is the identity).  Anything else returns PRIOR_LS_ESHAPE. */
 typedef struct {

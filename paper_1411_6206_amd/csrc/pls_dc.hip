@@ -12,7 +12,12 @@ static bool in_list(int v, const int* l, int n) {
     return false;
 }
 
-bool dc_supported(int ny, int nz) { return in_list(ny, kNY, 9) && in_list(nz, kNZ, 5); }
+static const int kNY14[] = {16, 32, 64, 128, 256};   // nz = 14 needs 7 | Q: powers of two in y
+
+bool dc_supported(int ny, int nz) {
+    if (nz == 14) return in_list(ny, kNY14, 5);
+    return in_list(ny, kNY, 9) && in_list(nz, kNZ, 5);
+}
 
 bool xifft_supported(int nx) { return in_list(nx, kNY, 9); }
 
@@ -32,11 +37,23 @@ static int grid_for(int ny, int nx, int nt) {
     return 0;
 }
 
+static int grid_for14(int ny, int nx, int nt) {
+    switch (ny) {
+        case 16: return dc_grid<16, 14>(nx, nt);
+        case 32: return dc_grid<32, 14>(nx, nt);
+        case 64: return dc_grid<64, 14>(nx, nt);
+        case 128: return dc_grid<128, 14>(nx, nt);
+        case 256: return dc_grid<256, 14>(nx, nt);
+    }
+    return 0;
+}
+
 int dc_blocks(int ny, int nz, int nx, int nt) {
     switch (nz) {
         case 1: return grid_for<1>(ny, nx, nt);
         case 4: return grid_for<4>(ny, nx, nt);
         case 8: return grid_for<8>(ny, nx, nt);
+        case 14: return grid_for14(ny, nx, nt);
         case 16: return grid_for<16>(ny, nx, nt);
         case 32: return grid_for<32>(ny, nx, nt);
     }
@@ -49,6 +66,7 @@ int launch_dc(int ny, int nz, bool stats, const DcArgs& a, hipStream_t s) {
         case 1: r = dc_launch_nz1(ny, stats, a, s); break;
         case 4: r = dc_launch_nz4(ny, stats, a, s); break;
         case 8: r = dc_launch_nz8(ny, stats, a, s); break;
+        case 14: r = dc_launch_nz14(ny, stats, a, s); break;
         case 16: r = dc_launch_nz16(ny, stats, a, s); break;
         case 32: r = dc_launch_nz32(ny, stats, a, s); break;
     }

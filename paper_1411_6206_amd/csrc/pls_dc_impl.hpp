@@ -17,13 +17,15 @@ template <int NY, int NZ>
 struct DcCfg {
     static constexpr int P = NY * NZ;
     static constexpr bool kHas3 = (NY % 3 == 0);
-    static constexpr int Q0 = kHas3 ? 12 : 16;
+    static constexpr bool kHas7 = (NZ % 7 == 0);      // nz = 14: radix 14 = 2 x 7 along z
+    static constexpr int Q0 = kHas7 ? 28 : (kHas3 ? 12 : 16);
     static constexpr int Q = (P / Q0 > 512) ? P / 512 : Q0;
     static constexpr int PB = (P / Q >= 64) ? 1 : (64 * Q) / P;
     static constexpr int T = PB * P / Q;
     // large blocks reload Y = L + S per coil (L2 hits) and cap registers at 128 so two
     // blocks share a CU; small blocks keep Y in registers
-    using G = Geom<NY, NZ, PB, Q, 0, 32, (T >= 256 ? 4 : 2), (T < 256)>;
+    // (28 points per thread for nz = 14 leave no room for Y in registers)
+    using G = Geom<NY, NZ, PB, Q, 0, 32, (T >= 256 ? 4 : 2), (T < 256) && !kHas7>;
 };
 
 // Register distribution of a first pass of radix R along axis AX: element (i, r) of a
@@ -354,6 +356,7 @@ inline void xifft_launch_t(const XiArgs& a, hipStream_t s) {
 int dc_launch_nz1(int ny, bool stats, const DcArgs& a, hipStream_t s);
 int dc_launch_nz4(int ny, bool stats, const DcArgs& a, hipStream_t s);
 int dc_launch_nz8(int ny, bool stats, const DcArgs& a, hipStream_t s);
+int dc_launch_nz14(int ny, bool stats, const DcArgs& a, hipStream_t s);
 int dc_launch_nz16(int ny, bool stats, const DcArgs& a, hipStream_t s);
 int dc_launch_nz32(int ny, bool stats, const DcArgs& a, hipStream_t s);
 bool xifft_launch_any(int nx, const XiArgs& a, hipStream_t s);

@@ -45,9 +45,41 @@ __device__ __forceinline__ void dft(float2* x) {
         x[2] = csub(a, c);
         x[1] = cadd(b, e);
         x[3] = csub(b, e);
+    } else if constexpr (R == 5 || R == 7) {
+        // odd prime: the inputs j and R - j share their cosine terms and have opposite sine
+        // terms, X[k] = x0 + sum_j cos(2 pi jk/R) (x_j + x_{R-j}) -+ i sin(2 pi jk/R)
+        // (x_j - x_{R-j}), and X[R - k] takes the other sign
+        constexpr int H = (R - 1) / 2;
+        float2 t[H + 1], u[H + 1];
+        float2 sum = x[0];
+        sfor<H>([&](auto jI) __attribute__((always_inline)) {
+            constexpr int j = decltype(jI)::value + 1;
+            t[j] = cadd(x[j], x[R - j]);
+            u[j] = csub(x[j], x[R - j]);
+            sum = cadd(sum, t[j]);
+        });
+        float2 out[R];
+        out[0] = sum;
+        sfor<H>([&](auto kI) __attribute__((always_inline)) {
+            constexpr int k = decltype(kI)::value + 1;
+            float2 a = x[0], b = make_float2(0.f, 0.f);
+            sfor<H>([&](auto jI) __attribute__((always_inline)) {
+                constexpr int j = decltype(jI)::value + 1;
+                constexpr double ang = 2.0 * kPi * ((j * k) % R) / R;
+                constexpr float c = (float)cx_cos(ang), sn = (float)cx_sin(ang);
+                a = make_float2(fmaf(c, t[j].x, a.x), fmaf(c, t[j].y, a.y));
+                b = make_float2(fmaf(sn, u[j].x, b.x), fmaf(sn, u[j].y, b.y));
+            });
+            // forward: X[k] = a - i b, X[R - k] = a + i b; the inverse swaps them
+            const float2 mib = make_float2(a.x + b.y, a.y - b.x);
+            const float2 pib = make_float2(a.x - b.y, a.y + b.x);
+            out[k] = INV ? pib : mib;
+            out[R - k] = INV ? mib : pib;
+        });
+        sfor<R>([&](auto iI) __attribute__((always_inline)) { x[decltype(iI)::value] = out[decltype(iI)::value]; });
     } else {
         // R = A B:  X[c + A d] = sum_b w_B^{bd} w_R^{bc} sum_a x[B a + b] w_A^{ac}
-        constexpr int A = (R % 4 == 0) ? 4 : ((R % 2 == 0) ? 2 : 3);
+        constexpr int A = (R % 4 == 0) ? 4 : ((R % 2 == 0) ? 2 : ((R % 3 == 0) ? 3 : ((R % 5 == 0) ? 5 : 7)));
         constexpr int B = R / A;
         float2 t[R];
         sfor<B>([&](auto bI) __attribute__((always_inline)) {

@@ -26,6 +26,10 @@ CASES = [
     ("3d_32x48x8_nt12_nc3", dict(nx=32, ny=48, nz=8, nt=12, nc=3, accel=4, rank=3, nblobs=4, seed=13), 2),
     ("2d_32x32_nt8_nc1", dict(nx=32, ny=32, nz=1, nt=8, nc=1, accel=3, rank=2, nblobs=3, seed=14), 2),
     ("3d_48x96x16_nt17_nc2", dict(nx=48, ny=96, nz=16, nt=17, nc=2, accel=6, rank=3, nblobs=6, seed=15), 3),
+    # nz = 14 (the cardiac geometry's slice count): radix 14 = 2 x 7 along z
+    ("3d_16x32x14_nt6_nc2", dict(nx=16, ny=32, nz=14, nt=6, nc=2, accel=3, rank=2, nblobs=3, seed=16), 1),
+    ("3d_32x16x14_nt5_nc1", dict(nx=32, ny=16, nz=14, nt=5, nc=1, accel=2, rank=2, nblobs=2, seed=17), 1),
+    ("3d_16x256x14_nt4_nc1", dict(nx=16, ny=256, nz=14, nt=4, nc=1, accel=4, rank=2, nblobs=3, seed=18), 1),
 ]
 
 
