@@ -18,14 +18,18 @@ struct DcCfg {
     static constexpr int P = NY * NZ;
     static constexpr bool kHas3 = (NY % 3 == 0);
     static constexpr bool kHas7 = (NZ % 7 == 0);      // nz = 14: radix 14 = 2 x 7 along z
-    static constexpr int Q0 = kHas7 ? 28 : (kHas3 ? 12 : 16);
+    // planes of 6144+ points with a factor 3 take 24 points per thread: two passes per axis
+    // (e.g. 192 = 8 x 24, 32 = 4 x 8) instead of three, at 256 registers and 2 waves/SIMD
+    static constexpr bool kWide = kHas3 && !kHas7 && P >= 24 * 256;
+    static constexpr int Q0 = kHas7 ? 28 : (kWide ? 24 : (kHas3 ? 12 : 16));
     static constexpr int Q = (P / Q0 > 512) ? P / 512 : Q0;
     static constexpr int PB = (P / Q >= 64) ? 1 : (64 * Q) / P;
     static constexpr int T = PB * P / Q;
     // large blocks reload Y = L + S per coil (L2 hits) and cap registers at 128 so two
     // blocks share a CU; small blocks keep Y in registers
-    // (28 points per thread for nz = 14 leave no room for Y in registers)
-    using G = Geom<NY, NZ, PB, Q, 0, 32, (T >= 256 ? 4 : 2), (T < 256) && !kHas7>;
+    // (24 or 28 points per thread leave no room for Y in registers)
+    static constexpr int MINW = (Q0 >= 24) ? 2 : (T >= 256 ? 4 : 2);
+    using G = Geom<NY, NZ, PB, Q, 0, 32, MINW, (T < 256) && Q0 < 24>;
 };
 
 // Register distribution of a first pass of radix R along axis AX: element (i, r) of a
@@ -60,20 +64,20 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
     constexpr int R0 = radix_in<G>();
     constexpr int RL = radix_out<G>();
     constexpr int AXL = G::NPZ > 0 ? 1 : 0;
-    // staged compact data of one coil (all planes of the batch), double-buffered
+    // staged compact data of one coil (all planes of the batch); one buffer suffices when
+    // the transform has block barriers (see the coil loop), else two alternate
     constexpr int NST = (PB * P < 1024) ? PB * P : 1024;
     constexpr int NSTT = (NST + T - 1) / T;   // staged entries per thread
+    constexpr int NBUF = (G::NPZ > 0) ? 1 : 2;
     using D0 = Dist<G, 0, R0>;
     using DL = Dist<G, AXL, RL>;
     __shared__ float2 lds[G::LDS_ELEMS];
-    __shared__ float2 twy[NY];
-    __shared__ float2 twz[NZ];
+    __shared__ float2 twt[G::TW_ELEMS];      // per-pass twiddle tables
     __shared__ int16_t smap[P];               // sample index of (kz, ky) in this frame, or -1
-    __shared__ float2 dhs[2][NST];
+    __shared__ float2 dhs[NBUF][NST];
     __shared__ double red[T / kWave];
     const int tid = threadIdx.x;
-    for (int m = tid; m < NY; m += T) twy[m] = a.twy[m];
-    for (int m = tid; m < NZ; m += T) twz[m] = a.twz[m];
+    tw_fill<G>(twt, a.twy, a.twz, tid);
 
     // Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD works on a
     // contiguous range of (x, t) planes and the coil maps of an x plane stay in its L2.
@@ -150,9 +154,12 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
         const int tidc = opaque(tid);
         const D0 e0(tidc);
         const DL el(tidc);
-        const int buf = c & 1;
-        // stage coil c's compact data (loaded one coil ahead) and fetch coil c + 1's; the
-        // buffer being written was last read two coils ago, before this coil's barriers
+        const int buf = (NBUF == 2) ? (c & 1) : 0;
+        // stage coil c's compact data (loaded one coil ahead) and fetch coil c + 1's.  With
+        // one buffer, its last reads (the previous coil's residual) precede the block barrier
+        // inside the previous coil's inverse transform, which every wave has passed here;
+        // with two, the buffer being written was last read two coils ago, before this
+        // coil's barriers
 #pragma unroll
         for (int k = 0; k < NSTT; ++k) {
             const int e = tidc + k * T;
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
         // rows of this wave were last read by this wave (previous inverse); the column
         // phases of the previous coil ended at the barrier inside fft2_inv, which also
         // orders the staging writes above before the reads below
-        fft2_fwd<G>(v, lds, twy, twz, tidc);
+        fft2_fwd<G>(v, lds, twt, tidc);
         // residual on the sampled entries; the compact data come from LDS when staged, else
         // from global memory (two copies of the loop under a block-uniform branch, so each
         // uses plain LDS or global loads rather than generic ones)
@@ -225,7 +232,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
         };
         if (staged) residual(std::true_type{});
         else residual(std::false_type{});
-        fft2_inv<G>(v, lds, twy, twz, tidc);
+        fft2_inv<G>(v, lds, twt, tidc);
 #pragma unroll
         for (int i = 0; i < D0::NB; ++i) {
             const int pbc = min(e0.pb[i], nvalid - 1);

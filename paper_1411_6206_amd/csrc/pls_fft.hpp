@@ -145,6 +145,49 @@ constexpr int plan_prod(const RadixPlan& p, int upto) {
     return s;
 }
 
+// Stage length of the inverse pass of radix p.r[idx]: the inverse runs the radices in
+// reverse order, so its stage length is the product of the radices after idx.
+constexpr int plan_prod_after(const RadixPlan& p, int idx) {
+    int s = 1;
+    for (int u = p.n - 1; u > idx; --u) s *= p.r[u];
+    return s;
+}
+
+// Per-pass twiddle tables.  A pass of radix R and stage length LS multiplies point r of
+// butterfly k (k < LS) by exp(-+2 pi i k r / (LS R)); the table of that (R, LS) holds these
+// factors (forward sign) at off + (r - 1) LS + k, so lanes that take consecutive butterflies
+// read consecutive entries instead of a stride-r gather from the axis table.  One table
+// serves every forward or inverse pass, on either axis, with the same (R, LS).
+struct TwPlan {
+    int n;
+    int R[32], LS[32], off[32];
+    int total;
+};
+
+constexpr TwPlan tw_add(TwPlan t, int R, int LS) {
+    if (LS <= 1) return t;
+    for (int i = 0; i < t.n; ++i)
+        if (t.R[i] == R && t.LS[i] == LS) return t;
+    t.R[t.n] = R;
+    t.LS[t.n] = LS;
+    t.off[t.n] = t.total;
+    t.total += (R - 1) * LS;
+    ++t.n;
+    return t;
+}
+
+constexpr TwPlan tw_axis(TwPlan t, const RadixPlan& p) {
+    for (int q = 1; q < p.n; ++q) t = tw_add(t, p.r[q], plan_prod(p, q));
+    for (int idx = 0; idx + 1 < p.n; ++idx) t = tw_add(t, p.r[idx], plan_prod_after(p, idx));
+    return t;
+}
+
+constexpr int tw_find(const TwPlan& t, int R, int LS) {
+    for (int i = 0; i < t.n; ++i)
+        if (t.R[i] == R && t.LS[i] == LS) return t.off[i];
+    return -1;
+}
+
 // ---------------------------------------------------------------- plane geometry
 template <int NY_, int NZ_, int PB_, int Q_, int PADY_, int RMAX_ = 32, int MINW_ = 1,
           bool KEEPY_ = true, bool PREF_ = false>
@@ -164,6 +207,8 @@ struct Geom {
     static constexpr RadixPlan PZ = plan_axis(NZ, Q, RMAX_);
     static constexpr int NPY = PY.n;
     static constexpr int NPZ = PZ.n;
+    static constexpr TwPlan TW = tw_axis(tw_axis(TwPlan{0, {}, {}, {}, 0}, PY), PZ);
+    static constexpr int TW_ELEMS = TW.total > 0 ? TW.total : 1;
     static_assert(PB * P % Q == 0, "Q must divide the block's points");
     static_assert(T % 64 == 0 && T <= 1024, "threads must be whole waves");
     static_assert(NPY >= 1 && NPZ >= 0, "axis not factorable with this Q");
@@ -238,10 +283,12 @@ __device__ __forceinline__ void pass_pos(int tid, int i, int r, int& pb, int& z,
     PassMap<G, AX, R>::pos(tid, i, r, pb, z, y);
 }
 
-// One Stockham pass.  tw = exp(-2 pi i m / N), m in [0, N), for this axis' length N.
-// Reads follow a block barrier or a wave-local sync of the previous pass; writes are
-// followed by a wave-local sync (callers add the block barrier at a change of axis).
-template <class G, int AX, int R, int LS, bool INV, bool IN_REG, bool OUT_REG>
+// One Stockham pass.  With TWOFF < 0, tw = exp(-2 pi i m / N), m in [0, N), for this axis'
+// length N; otherwise tw is a block of per-pass tables (TwPlan) and this pass' factors sit at
+// TWOFF + (r - 1) LS + k.  Reads follow a block barrier or a wave-local sync of the previous
+// pass; writes are followed by a wave-local sync (callers add the block barrier at a change
+// of axis).
+template <class G, int AX, int R, int LS, bool INV, bool IN_REG, bool OUT_REG, int TWOFF = -1>
 __device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const float2* tw,
                                          int tid) {
     using M = PassMap<G, AX, R>;
@@ -269,7 +316,7 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const f
             constexpr int step = N / (LS * R);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[k * r * step];
+                float2 w = (TWOFF >= 0) ? tw[TWOFF + (r - 1) * LS + k] : tw[k * r * step];
                 if (INV) w.y = -w.y;
                 v[i * R + r] = cmul(v[i * R + r], w);
             }
@@ -289,13 +336,31 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const f
     }
 }
 
+// Fills the per-pass twiddle tables (G::TW_ELEMS entries of LDS) from the axis tables
+// twy = exp(-2 pi i m / NY) and twz = exp(-2 pi i m / NZ).  The caller adds the barrier.
+template <class G>
+__device__ __forceinline__ void tw_fill(float2* twt, const float2* twy, const float2* twz,
+                                        int tid) {
+    sfor<G::TW.n>([&](auto iI) __attribute__((always_inline)) {
+        constexpr int i = decltype(iI)::value;
+        constexpr int R = G::TW.R[i], LS = G::TW.LS[i], off = G::TW.off[i];
+        constexpr int M = R * LS;
+        static_assert(G::NY % M == 0 || G::NZ % M == 0, "stage length outside both axes");
+        for (int e = tid; e < (R - 1) * LS; e += G::T) {
+            const int m = (e % LS) * (e / LS + 1);            // k r < M
+            twt[off + e] = (G::NY % M == 0) ? twy[m * (G::NY / M)] : twz[m * (G::NZ / M)];
+        }
+    });
+}
+
 // Forward 2D transform: y passes (ascending radices) then z passes (ascending).
 // Input: registers in the distribution of the first y pass; output: registers in the
 // distribution of a first pass of radix (last z radix) along z (or y when NZ == 1).
-// The caller guarantees that no other wave still reads this block's rows (LDS).
+// twt holds the per-pass tables tw_fill wrote.  The caller guarantees that no other wave
+// still reads this block's rows (LDS).
 template <class G>
-__device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const float2* twy,
-                                         const float2* twz, int tid) {
+__device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const float2* twt,
+                                         int tid) {
     constexpr int NPY = G::NPY, NPZ = G::NPZ, NP = NPY + NPZ;
     sfor<NP>([&](auto pI) __attribute__((always_inline)) {
         constexpr int p = decltype(pI)::value;
@@ -304,13 +369,13 @@ __device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const f
         if constexpr (p < NPY) {
             constexpr int R = G::PY.r[p];
             constexpr int LS = plan_prod(G::PY, p);
-            fft_pass<G, 0, R, LS, false, IN_REG, OUT_REG>(v, lds, twy, tid);
+            fft_pass<G, 0, R, LS, false, IN_REG, OUT_REG, tw_find(G::TW, R, LS)>(v, lds, twt, tid);
         } else {
             constexpr int q = p - NPY;
             constexpr int R = G::PZ.r[q];
             constexpr int LS = plan_prod(G::PZ, q);
             if constexpr (q == 0) __syncthreads();   // rows -> columns
-            fft_pass<G, 1, R, LS, false, IN_REG, OUT_REG>(v, lds, twz, tid);
+            fft_pass<G, 1, R, LS, false, IN_REG, OUT_REG, tw_find(G::TW, R, LS)>(v, lds, twt, tid);
         }
     });
 }
@@ -319,8 +384,8 @@ __device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const f
 // in descending order.  Reads the registers fft2_fwd left and returns them in the
 // distribution fft2_fwd read.
 template <class G>
-__device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const float2* twy,
-                                         const float2* twz, int tid) {
+__device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const float2* twt,
+                                         int tid) {
     constexpr int NPY = G::NPY, NPZ = G::NPZ, NP = NPY + NPZ;
     sfor<NP>([&](auto pI) __attribute__((always_inline)) {
         constexpr int p = decltype(pI)::value;
@@ -329,23 +394,15 @@ __device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const f
         if constexpr (p < NPZ) {
             constexpr int idx = NPZ - 1 - p;          // radices reversed
             constexpr int R = G::PZ.r[idx];
-            constexpr int LS = [] {
-                int s = 1;
-                for (int u = NPZ - 1; u > idx; --u) s *= G::PZ.r[u];
-                return s;
-            }();
-            fft_pass<G, 1, R, LS, true, IN_REG, OUT_REG>(v, lds, twz, tid);
+            constexpr int LS = plan_prod_after(G::PZ, idx);
+            fft_pass<G, 1, R, LS, true, IN_REG, OUT_REG, tw_find(G::TW, R, LS)>(v, lds, twt, tid);
         } else {
             constexpr int q = p - NPZ;
             constexpr int idx = NPY - 1 - q;
             constexpr int R = G::PY.r[idx];
-            constexpr int LS = [] {
-                int s = 1;
-                for (int u = NPY - 1; u > idx; --u) s *= G::PY.r[u];
-                return s;
-            }();
+            constexpr int LS = plan_prod_after(G::PY, idx);
             if constexpr (q == 0 && NPZ > 0) __syncthreads();   // columns -> rows
-            fft_pass<G, 0, R, LS, true, IN_REG, OUT_REG>(v, lds, twy, tid);
+            fft_pass<G, 0, R, LS, true, IN_REG, OUT_REG, tw_find(G::TW, R, LS)>(v, lds, twt, tid);
         }
     });
 }
