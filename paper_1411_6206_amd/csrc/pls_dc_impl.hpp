@@ -29,7 +29,9 @@ struct DcCfg {
     // blocks share a CU; small blocks keep Y in registers
     // (24 or 28 points per thread leave no room for Y in registers)
     static constexpr int MINW = (Q0 >= 24) ? 2 : (T >= 256 ? 4 : 2);
-    using G = Geom<NY, NZ, PB, Q, 0, 32, MINW, (T < 256) && Q0 < 24>;
+    // with 24 points per thread the frame's sample indices of the thread's points stay in
+    // registers (two per register) instead of being looked up in LDS for every coil
+    using G = Geom<NY, NZ, PB, Q, 0, 32, MINW, (T < 256) && Q0 < 24, kWide>;
 };
 
 // Register distribution of a first pass of radix R along axis AX: element (i, r) of a
@@ -73,7 +75,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
     using DL = Dist<G, AXL, RL>;
     __shared__ float2 lds[G::LDS_ELEMS];
     __shared__ float2 twt[G::TW_ELEMS];      // per-pass twiddle tables
-    __shared__ int16_t smap[P];               // sample index of (kz, ky) in this frame, or -1
+    __shared__ int16_t smap[G::SIDREG ? 1 : P];  // sample index of (kz, ky) in this frame, or -1
     __shared__ float2 dhs[NBUF][NST];
     __shared__ double red[T / kWave];
     const int tid = threadIdx.x;
@@ -100,7 +102,27 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
     const int nst = a.ns[t];
     const float2* dh_t = a.dh + a.dh_off[t];
     const int16_t* sid_t = a.sidx + t * P;
-    for (int m = tid; m < P; m += T) smap[m] = sid_t[m];
+    if constexpr (!G::SIDREG)
+        for (int m = tid; m < P; m += T) smap[m] = sid_t[m];
+    // sample index (or -1) of each point of the thread in the distribution the forward
+    // transform leaves, packed two per register; -1 also marks points of absent planes
+    uint32_t sidp[G::SIDREG ? Q / 2 : 1];
+    if constexpr (G::SIDREG) {
+        static_assert(Q % 2 == 0, "sample indices are packed in pairs");
+        const DL dl(tid);
+#pragma unroll
+        for (int i = 0; i < DL::NB; ++i) {
+            const bool ok = dl.pb[i] < nvalid;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int q = i * RL + r;
+                const int sv = ok ? (int)sid_t[dl.rel[i] + r * DL::STEP] : -1;
+                const uint32_t h = (uint32_t)sv & 0xffffu;
+                if (q % 2 == 0) sidp[q / 2] = h;
+                else sidp[q / 2] |= h << 16;
+            }
+        }
+    }
     // the compact data of coil c for the batch: entry pb * nst + s, contiguous in memory when
     // PB == 1 (index (x * nc + c) * nst + s)
     const bool staged = pbv * nst <= NST;
@@ -121,6 +143,22 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
 
     float2 Y[G::KEEPY ? Q : 1], acc[Q], v[Q];
     double dy2 = 0.0, y2 = 0.0;
+    // Y = L + S at element gi; the statistics variant also accumulates |Y - Yold|^2 and
+    // |Yold|^2 over the elements the block owns (Yold = Lold + Sold)
+    auto form_y = [&](int gi, bool ok) __attribute__((always_inline)) {
+        const float2 l = Lp[gi], sv = Sp[gi];
+        float2 yv = has_s ? cadd(l, sv) : l;
+        if (!has_y) yv = make_float2(0.f, 0.f);
+        if constexpr (STATS) {
+            const float2 lo = a.Lold[gi], so = a.Sold[gi];
+            const float2 yo = cadd(lo, so);
+            const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
+            const double w = ok ? 1.0 : 0.0;
+            dy2 += w * (dx * dx + dyy * dyy);
+            y2 += w * ((double)yo.x * yo.x + (double)yo.y * yo.y);
+        }
+        return yv;
+    };
 #pragma unroll
     for (int i = 0; i < D0::NB; ++i) {
         const int pbc = min(d0.pb[i], nvalid - 1);
@@ -129,21 +167,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int q = i * R0 + r;
-            const int gi = o + r * D0::STEP;
-            if constexpr (G::KEEPY || STATS) {
-                const float2 l = Lp[gi], sv = Sp[gi];
-                float2 yv = has_s ? cadd(l, sv) : l;
-                if (!has_y) yv = make_float2(0.f, 0.f);
-                if constexpr (STATS) {
-                    const float2 lo = a.Lold[gi], so = a.Sold[gi];
-                    const float2 yo = cadd(lo, so);
-                    const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
-                    const double w = ok ? 1.0 : 0.0;
-                    dy2 += w * (dx * dx + dyy * dyy);
-                    y2 += w * ((double)yo.x * yo.x + (double)yo.y * yo.y);
-                }
-                if constexpr (G::KEEPY) Y[q] = yv;
-            }
+            if constexpr (G::KEEPY) Y[q] = form_y(o + r * D0::STEP, ok);
             acc[q] = make_float2(0.f, 0.f);
         }
     }
@@ -185,9 +209,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
                     // read one array instead of two
                     const int gi = plane0 + o + r * D0::STEP;
                     if (c == 0) {
-                        const float2 l = Lp[gi], sv = Sp[gi];
-                        yv = has_s ? cadd(l, sv) : l;
-                        if (!has_y) yv = make_float2(0.f, 0.f);
+                        yv = form_y(gi, own);
                         if (own) a.C[gi] = yv;
                     } else {
                         yv = a.C[gi];
@@ -215,8 +237,13 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
 #pragma unroll
                 for (int r = 0; r < RL; ++r) {
                     const int q = i * RL + r;
-                    int s = smap[el.rel[i] + r * DL::STEP];
-                    s = ok ? s : -1;
+                    int s;
+                    if constexpr (G::SIDREG) {
+                        s = (int)(int16_t)(sidp[q / 2] >> (16 * (q % 2)));
+                    } else {
+                        s = smap[el.rel[i] + r * DL::STEP];
+                        s = ok ? s : -1;
+                    }
                     const int sc0 = s < 0 ? 0 : s;
                     float2 d;
                     if constexpr (kStaged) d = dhs[buf][pbc * nst + sc0];
