@@ -257,6 +257,47 @@ int prior_ls_op_svt(prior_ls_handle *h, const void *C, void *L, double *sigma);
 /* Step (3): S = T^{-1} soft(T(Xm - Lp), lambda_S (1 - w)) with the handle's weights. */
 int prior_ls_op_sparse(prior_ls_handle *h, const void *Xm, const void *Lp, void *S);
 
+/* ---- Batches: several problems of one geometry advanced together (one launch per kernel
+ * of an iteration for all of them), the amortised form of the iteration for problems too
+ * small to fill the GPU alone. ----
+ *
+ * A batch groups `count` existing handles (1 ... 4096) that share nx, ny, nz, nt, nc,
+ * wavelet_levels, gram_mode, transform and device.  It does not own them: they stay usable
+ * on their own, and must outlive the batch.  Each kernel of an iteration of Algorithm 1 is
+ * launched once with the problems along the grid's z axis; a problem's workgroups read its
+ * own arrays, so its masks, coil maps, prior weights, parameters and data are its own.  The
+ * launch shapes (Gram split, back-projection grid, sparse fork point) are those of the
+ * first handle's tuning when the batch is created.  Every problem computes exactly what it
+ * computes alone with that tuning: the same kernels in the same order on its data, and it
+ * stops where it would alone (after params.max_iter iterations, or at convergence tested
+ * after every check_every of its own iterations).  Stopped problems' workgroups return at
+ * once.  Calls on a batch and on its handles must not overlap (one thread at a time).
+ * Errors: EINVAL (NULL, count out of range, a handle twice, mixed geometry or device) with
+ * the message in prior_ls_last_error(NULL) on this thread; ENOMEM, EHIP. */
+typedef struct prior_ls_batch prior_ls_batch;
+int prior_ls_batch_create(prior_ls_handle *const *handles, int32_t count, prior_ls_batch **out);
+
+/* prior_ls_solve of every problem of the batch: in[i], params[i] (their own max_iter, tol,
+ * check_every; use_graph of params[0] applies to all), out[i] (out may be NULL), stats[i]
+ * (may be NULL; stats[i].ms is the wall time of the whole call).  Each handle's work is
+ * ordered after its own stream, like prior_ls_solve.  Returns the first error; a problem
+ * that reaches a non-finite iterate stops (stats[i].nonfinite) while the others go on. */
+int prior_ls_batch_solve(prior_ls_batch *b, const prior_ls_inputs *in,
+                         const prior_ls_params *params, const prior_ls_outputs *out,
+                         prior_ls_stats *stats);
+
+/* prior_ls_step of every problem (all loaded, each having done iterations of the same
+ * parity, e.g. all freshly solved): n_iter more iterations under each problem's own
+ * parameters of its last solve. */
+int prior_ls_batch_step(prior_ls_batch *b, int32_t n_iter, const prior_ls_outputs *out,
+                        prior_ls_stats *stats);
+
+/* Message of the batch's last error ("" if none). */
+const char *prior_ls_batch_last_error(const prior_ls_batch *b);
+
+/* Release the batch (not its handles).  NULL is a no-op. */
+void prior_ls_batch_destroy(prior_ls_batch *b);
+
 /* ---- Serving: continuous batching of recursive reconstructions (the priori L+S scheme of
  * Section 3 / Fig. 2 applied to many sequences at once).
  *

@@ -32,7 +32,9 @@ EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destr
            "prior_ls_op_dc", "prior_ls_op_svt", "prior_ls_op_sparse", "prior_ls_step_timed",
            "prior_ls_append", "prior_ls_server_create", "prior_ls_server_submit",
            "prior_ls_server_wait", "prior_ls_server_info", "prior_ls_server_destroy",
-           "prior_ls_tune", "prior_ls_set_tuning", "prior_ls_get_tuning")
+           "prior_ls_tune", "prior_ls_set_tuning", "prior_ls_get_tuning",
+           "prior_ls_batch_create", "prior_ls_batch_solve", "prior_ls_batch_step",
+           "prior_ls_batch_last_error", "prior_ls_batch_destroy")
 NKERNELS = 7
 KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats")
 
@@ -169,6 +171,18 @@ def lib():
     L.prior_ls_set_tuning.restype = C.c_int
     L.prior_ls_get_tuning.argtypes = [H, C.POINTER(Tuning)]
     L.prior_ls_get_tuning.restype = C.c_int
+    B = C.c_void_p
+    L.prior_ls_batch_create.argtypes = [C.POINTER(H), C.c_int32, C.POINTER(B)]
+    L.prior_ls_batch_create.restype = C.c_int
+    L.prior_ls_batch_solve.argtypes = [B, C.POINTER(Inputs), C.POINTER(Params), C.POINTER(Outputs),
+                                       C.POINTER(Stats)]
+    L.prior_ls_batch_solve.restype = C.c_int
+    L.prior_ls_batch_step.argtypes = [B, C.c_int32, C.POINTER(Outputs), C.POINTER(Stats)]
+    L.prior_ls_batch_step.restype = C.c_int
+    L.prior_ls_batch_last_error.argtypes = [B]
+    L.prior_ls_batch_last_error.restype = C.c_char_p
+    L.prior_ls_batch_destroy.argtypes = [B]
+    L.prior_ls_batch_destroy.restype = None
     S = C.c_void_p
     L.prior_ls_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(S)]
     L.prior_ls_server_create.restype = C.c_int
@@ -382,6 +396,94 @@ class PriorLS:
         if getattr(self, "_h", None) and self._h.value:
             lib().prior_ls_destroy(self._h)
             self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """prior_ls_batch_*: several PriorLS handles of one geometry advanced together, one
+    launch per kernel of an iteration for all of them.  The handles stay owned by the
+    caller and must outlive the batch."""
+
+    def __init__(self, solvers: Sequence["PriorLS"]):
+        L = lib()
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        arr = (C.c_void_p * n)(*[s._h.value for s in self.solvers])
+        self._b = C.c_void_p()
+        rc = L.prior_ls_batch_create(arr, n, C.byref(self._b))
+        if rc != OK:
+            raise PriorLSError(rc, f"prior_ls_batch_create: {L.prior_ls_last_error(None).decode()}")
+
+    def _check(self, rc, what):
+        if rc != OK:
+            raise PriorLSError(rc, f"{what}: {lib().prior_ls_batch_last_error(self._b).decode()}")
+
+    def _outputs(self, want):
+        outs, os_ = [], []
+        for s in self.solvers:
+            o, oc = s._outputs(want)
+            outs.append(o)
+            os_.append(oc)
+        return outs, (Outputs * len(os_))(*os_)
+
+    def solve(self, problems, params, outputs=("L", "S", "X", "M")):
+        """problems: per problem a dict of device tensors (kspace, mask, sens, prior_w and
+        optionally sigma_prev, L0, S0); params: one Params for all or one per problem.
+        Returns (outputs, stats) lists."""
+        import torch
+        n = len(self.solvers)
+        if len(problems) != n:
+            raise ValueError("one problem per handle")
+        prms = list(params) if isinstance(params, (list, tuple)) else [params] * n
+        keep, ins = [], []
+        for p in problems:
+            sp = None
+            if p.get("sigma_prev") is not None:
+                vals = [float(v) for v in p["sigma_prev"]]
+                sp = (C.c_double * len(vals))(*vals)
+                keep.append(sp)
+            ins.append(Inputs(_ptr(p["kspace"]), _ptr(p["mask"]), _ptr(p.get("sens")),
+                              _ptr(p.get("prior_w")),
+                              C.cast(sp, C.POINTER(C.c_double)) if sp is not None else None,
+                              _ptr(p.get("L0")), _ptr(p.get("S0"))))
+        in_arr = (Inputs * n)(*ins)
+        prm_arr = (Params * n)(*prms)
+        outs, o_arr = self._outputs(outputs)
+        st = (Stats * n)()
+        for k in range(n):
+            st[k].struct_size = C.sizeof(Stats)
+        rc = lib().prior_ls_batch_solve(self._b, in_arr, prm_arr, o_arr, st)
+        torch.cuda.current_stream().synchronize()
+        self._check(rc, "prior_ls_batch_solve")
+        return outs, [st[k].as_dict() for k in range(n)]
+
+    def step(self, n_iter, outputs=("L", "S", "X", "M")):
+        import torch
+        n = len(self.solvers)
+        outs, o_arr = self._outputs(outputs)
+        st = (Stats * n)()
+        for k in range(n):
+            st[k].struct_size = C.sizeof(Stats)
+        rc = lib().prior_ls_batch_step(self._b, int(n_iter), o_arr, st)
+        torch.cuda.current_stream().synchronize()
+        self._check(rc, "prior_ls_batch_step")
+        return outs, [st[k].as_dict() for k in range(n)]
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            lib().prior_ls_batch_destroy(self._b)
+            self._b = C.c_void_p()
 
     def __enter__(self):
         return self

@@ -60,8 +60,10 @@ struct Dist {
     }
 };
 
-template <class G, bool STATS>
-__global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(DcArgs a) {
+template <class G, bool STATS, class SRC>
+__global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
+    if (src.skip()) return;
+    const DcArgs a = src.get();
     constexpr int Q = G::Q, P = G::P, NY = G::NY, NZ = G::NZ, PB = G::PB, T = G::T;
     constexpr int R0 = radix_in<G>();
     constexpr int RL = radix_out<G>();
@@ -367,14 +369,15 @@ inline int dc_grid(int nx, int nt) {
     return ((nx + C::PB - 1) / C::PB) * nt;
 }
 
+// bt NULL: one problem with argument block a; else the batch *bt (a: problem 0's block)
 template <int NY, int NZ>
-inline int dc_launch_t(bool stats, const DcArgs& a, hipStream_t s) {
+inline int dc_launch_t(bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s) {
     using G = typename DcCfg<NY, NZ>::G;
     const int grid = dc_grid<NY, NZ>(a.nx, a.nt);
     if (stats)
-        hipLaunchKernelGGL((pls_dc_kernel<G, true>), dim3(grid), dim3(G::T), 0, s, a);
+        PLS_LAUNCH(dim3(grid), dim3(G::T), s, a, bt, pls_dc_kernel, G, true);
     else
-        hipLaunchKernelGGL((pls_dc_kernel<G, false>), dim3(grid), dim3(G::T), 0, s, a);
+        PLS_LAUNCH(dim3(grid), dim3(G::T), s, a, bt, pls_dc_kernel, G, false);
     return grid;
 }
 
@@ -387,12 +390,12 @@ inline void xifft_launch_t(const XiArgs& a, hipStream_t s) {
 
 // Per-nz translation units (pls_dc_nz*.hip) instantiate the kernels; these return -1 when
 // the shape is not theirs.
-int dc_launch_nz1(int ny, bool stats, const DcArgs& a, hipStream_t s);
-int dc_launch_nz4(int ny, bool stats, const DcArgs& a, hipStream_t s);
-int dc_launch_nz8(int ny, bool stats, const DcArgs& a, hipStream_t s);
-int dc_launch_nz14(int ny, bool stats, const DcArgs& a, hipStream_t s);
-int dc_launch_nz16(int ny, bool stats, const DcArgs& a, hipStream_t s);
-int dc_launch_nz32(int ny, bool stats, const DcArgs& a, hipStream_t s);
+int dc_launch_nz1(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz4(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz8(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz14(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz16(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz32(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
 bool xifft_launch_any(int nx, const XiArgs& a, hipStream_t s);
 
 }  // namespace pls

@@ -85,8 +85,10 @@ __device__ __forceinline__ void gram_block_store(const f4 (&acc)[NP], double (*r
 // Lane (i, g) = (lane % 16, lane / 16).  A wave takes chunks of 16 voxels; lane group g
 // covers voxels 4g..4g+3 of the chunk, one per K step of v_mfma_f64_16x16x4.  The lane
 // loads frames i and 16 + i of those voxels (32 contiguous bytes per frame).
-template <int NB>
-__global__ void __launch_bounds__(256) pls_gram_f64_kernel(GramArgs a) {
+template <int NB, class SRC>
+__global__ void __launch_bounds__(256) pls_gram_f64_kernel(SRC src) {
+    if (src.skip()) return;
+    GramArgs a = src.get();
     constexpr int NT4 = 2 * NB;
     constexpr int NP = npair<NB>();
     __shared__ double red[2][NP * 256];
@@ -172,8 +174,10 @@ __global__ void __launch_bounds__(256) pls_gram_f64_kernel(GramArgs a) {
 // ---------------------------------------------------------------- FP32 MFMA Gram
 // Same lane mapping as the FP64 kernel with v_mfma_f32_16x16x4f32; FP32 accumulation within
 // a wave (a few hundred voxels per entry), FP64 across waves and blocks.
-template <int NB>
-__global__ void __launch_bounds__(256) pls_gram_f32_kernel(GramArgs a) {
+template <int NB, class SRC>
+__global__ void __launch_bounds__(256) pls_gram_f32_kernel(SRC src) {
+    if (src.skip()) return;
+    GramArgs a = src.get();
     constexpr int NT4 = 2 * NB;
     constexpr int NP = npair<NB>();
     __shared__ double red[2][NP * 256];
@@ -226,8 +230,10 @@ __global__ void __launch_bounds__(256) pls_gram_f32_kernel(GramArgs a) {
 // v_mfma_f32_16x16x32_bf16 (the lo^T lo term, ~2^-16 relative, is dropped).  Lane (i, g)
 // holds 8 consecutive voxels 8g..8g+7 of a 32-voxel chunk for frames i and 16 + i; A and B
 // use the same (lane, element) -> voxel mapping, which is all a Gram needs.
-template <int NB>
-__global__ void __launch_bounds__(256) pls_gram_bf16x3_kernel(GramArgs a) {
+template <int NB, class SRC>
+__global__ void __launch_bounds__(256) pls_gram_bf16x3_kernel(SRC src) {
+    if (src.skip()) return;
+    GramArgs a = src.get();
     constexpr int NT4 = 2 * NB;
     constexpr int NP = npair<NB>();
     __shared__ double red[2][NP * 256];
@@ -281,31 +287,43 @@ __global__ void __launch_bounds__(256) pls_gram_bf16x3_kernel(GramArgs a) {
     gram_block_store<NP, false>(acc, red, a.part, lane, wave);
 }
 
-int launch_gram(int mode, const GramArgs& a0, hipStream_t s) {
+// Batched: every argument block must already hold vox_per_block = gram_vpb(N, target_blocks)
+// (the kernel reads it from there); a0 is problem 0's block, for the launch shape.
+int launch_gram_batched(int mode, const GramArgs& a0, const Batched<GramArgs>* bt, hipStream_t s) {
     GramArgs a = a0;
     const int vpb = gram_vpb(a.N, a.target_blocks);
     a.vox_per_block = vpb;
     const int grid = (a.N + vpb - 1) / vpb;
     const bool one = a.nt <= 16;
     if (mode == PRIOR_LS_GRAM_FP32) {
-        if (one) hipLaunchKernelGGL(pls_gram_f32_kernel<1>, dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(pls_gram_f32_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+        if (one) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f32_kernel, 1);
+        else PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f32_kernel, 2);
     } else if (mode == PRIOR_LS_GRAM_BF16X3) {
-        if (one) hipLaunchKernelGGL(pls_gram_bf16x3_kernel<1>, dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(pls_gram_bf16x3_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+        if (one) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_bf16x3_kernel, 1);
+        else PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_bf16x3_kernel, 2);
     } else {
-        if (one) hipLaunchKernelGGL(pls_gram_f64_kernel<1>, dim3(grid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(pls_gram_f64_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+        if (one) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f64_kernel, 1);
+        else PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f64_kernel, 2);
     }
     return grid;
+}
+
+int launch_gram(int mode, const GramArgs& a, hipStream_t s) {
+    return launch_gram_batched(mode, a, nullptr, s);
 }
 
 // out[e] = sum over the per-block partials in a fixed order: a block covers 16 entries
 // (one 128-byte row segment per partial) with 16 row groups; group g sums the partials
 // b = g + 16 m into eight accumulators (m mod 8, so eight loads are in flight), adds them in
 // index order, and the 16 group sums are added in group order.
-__global__ void __launch_bounds__(256) pls_gram_reduce_kernel(const double* part, int blocks,
-                                                              int entries, double* out) {
+template <int NTH, class SRC>
+__global__ void __launch_bounds__(NTH) pls_gram_reduce_kernel(SRC src) {
+    static_assert(NTH == 256, "16 row groups of 16 entries");
+    if (src.skip()) return;
+    const ReduceArgs ra = src.get();
+    const double* part = ra.part;
+    double* out = ra.out;
+    const int blocks = ra.blocks, entries = ra.entries;
     __shared__ double red[16][16];
     // on the critical path while the sparse update shares the CUs: issue before its waves
     __builtin_amdgcn_s_setprio(3);
@@ -336,9 +354,12 @@ __global__ void __launch_bounds__(256) pls_gram_reduce_kernel(const double* part
     }
 }
 
+void launch_gram_reduce_batched(const ReduceArgs& a, const Batched<ReduceArgs>* bt, hipStream_t s) {
+    PLS_LAUNCH(dim3((a.entries + 15) / 16), dim3(256), s, a, bt, pls_gram_reduce_kernel, 256);
+}
+
 void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(pls_gram_reduce_kernel, dim3((entries + 15) / 16), dim3(256), 0, s, part,
-                       blocks, entries, out);
+    launch_gram_reduce_batched(ReduceArgs{part, out, blocks, entries}, nullptr, s);
 }
 
 // ---------------------------------------------------------------- Hermitian eigensolver
@@ -360,14 +381,15 @@ __device__ __forceinline__ double gram_real(const double* red, int NB, int c1, i
     return red[p * 256 + i * 16 + j];
 }
 
+// Pair k of round r in the round-robin ordering of n (even) indices; r, k < n - 1.
 __device__ __forceinline__ void rr_pair(int n, int r, int k, int& p, int& q) {
-    if (k == 0) {
-        p = n - 1;
-        q = r;
-    } else {
-        p = (r + k) % (n - 1);
-        q = (r - k + n - 1) % (n - 1);
-    }
+    const int m = n - 1;
+    int pp = r + k;                 // < 2m
+    pp = pp >= m ? pp - m : pp;
+    int qq = r - k + m;             // in (0, 2m)
+    qq = qq >= m ? qq - m : qq;
+    p = k == 0 ? m : pp;
+    q = k == 0 ? r : qq;
 }
 
 // FP64 reciprocal and reciprocal square root: hardware approximations refined by two
@@ -415,26 +437,37 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double cr, do
     }
 }
 
-__global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
-    __shared__ double Ar[kNMax][kNMax + 1], Ai[kNMax][kNMax + 1];
+// One block of NT threads.  The rotated matrix is double-buffered (a round reads one copy
+// and writes the other) and every wave derives the round's rotations for itself, so a
+// round needs a single block barrier.
+template <int NT, class SRC>
+__global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
+    if (src.skip()) return;
+    const EigArgs a = src.get();
+    constexpr int NW = NT / 64;
+    // Ab[0] / Ab[1]: the two copies of A (real, imaginary); Ab[1] holds T in the set-up
+    __shared__ double Ab[2][2][kNMax][kNMax + 1];
     __shared__ double Vr[kNMax][kNMax + 1], Vi[kNMax][kNMax + 1];
-    __shared__ double Tr[kNMax][kNMax + 1], Ti[kNMax][kNMax + 1];
-    __shared__ double rc[kNMax / 2], rs[kNMax / 2], rer[kNMax / 2], rei[kNMax / 2];
-    __shared__ int rp[kNMax / 2], rq[kNMax / 2];
-    __shared__ double red[kEigThreads / 64];
+    __shared__ double rc[NW][kNMax / 2], rs[NW][kNMax / 2], rer[NW][kNMax / 2], rei[NW][kNMax / 2];
+    __shared__ double red[NW];
     __shared__ double sig[kNMax], phi[kNMax];
     __shared__ int rank_of[kNMax], by_rank[kNMax];
+    double (*Ar)[kNMax + 1] = Ab[0][0];
+    double (*Ai)[kNMax + 1] = Ab[0][1];
+    double (*Tr)[kNMax + 1] = Ab[1][0];
+    double (*Ti)[kNMax + 1] = Ab[1][1];
     // one block on the critical path while the sparse update fills the other CUs (and
     // possibly this one): its waves issue first
     __builtin_amdgcn_s_setprio(3);
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const int n = a.nt;
     const int ne = n + (n & 1);
     const int NB = n <= 16 ? 1 : 2;
     const int NTP = 16 * NB;
 
     // G (complex Hermitian, n x n; padded index decoupled)
-    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
+    for (int idx = tid; idx < ne * ne; idx += NT) {
         const int i = idx / ne, j = idx % ne;
         double gr = 0.0, gi = 0.0;
         if (i < n && j < n) {
@@ -453,7 +486,7 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
     }
     __syncthreads();
     // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
-    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
+    for (int idx = tid; idx < ne * ne; idx += NT) {
         const int i = idx / ne, j = idx % ne;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < ne; ++k) {
@@ -464,7 +497,7 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
         Ai[i][j] = si;
     }
     __syncthreads();
-    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
+    for (int idx = tid; idx < ne * ne; idx += NT) {
         const int i = idx / ne, j = idx % ne;
         double sr = 0.0, si = 0.0;
         for (int k = 0; k < ne; ++k) {
@@ -476,7 +509,7 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
         Ti[i][j] = si;
     }
     __syncthreads();
-    for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
+    for (int idx = tid; idx < ne * ne; idx += NT) {
         const int i = idx / ne, j = idx % ne;
         // symmetrise: A = (T + T^H) / 2
         Ar[i][j] = 0.5 * (Tr[i][j] + Tr[j][i]);
@@ -485,44 +518,55 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
     __syncthreads();
 
     const int half = ne / 2;
-    int sweeps = 0;
+    int sweeps = 0, cur = 0;
     for (; sweeps < kMaxSweeps && ne > 1; ++sweeps) {
+        double (*Cr)[kNMax + 1] = Ab[cur][0];
+        double (*Ci)[kNMax + 1] = Ab[cur][1];
         double off = 0.0, dg = 0.0;
-        for (int idx = tid; idx < ne * ne; idx += kEigThreads) {
+        for (int idx = tid; idx < ne * ne; idx += NT) {
             const int i = idx / ne, j = idx % ne;
-            if (i == j) dg += Ar[i][i] * Ar[i][i];
-            else off += Ar[i][j] * Ar[i][j] + Ai[i][j] * Ai[i][j];
+            if (i == j) dg += Cr[i][i] * Cr[i][i];
+            else off += Cr[i][j] * Cr[i][j] + Ci[i][j] * Ci[i][j];
         }
-        off = block_sum<kEigThreads>(off, red);
-        dg = block_sum<kEigThreads>(dg, red);
+        off = block_sum<NT>(off, red);
+        dg = block_sum<NT>(dg, red);
         // relative off-diagonal norm below 1e-8: eigenvector errors of that order (times
         // the inverse gap) are far below the FP32 resolution of W
         if (!(off > 1e-16 * dg)) break;   // also stops on NaN
         for (int r = 0; r < ne - 1; ++r) {
-            if (tid < half) {
+            double (*Sr)[kNMax + 1] = Ab[cur][0];
+            double (*Si)[kNMax + 1] = Ab[cur][1];
+            double (*Dr)[kNMax + 1] = Ab[cur ^ 1][0];
+            double (*Di)[kNMax + 1] = Ab[cur ^ 1][1];
+            // this wave's copy of the round's rotations (every wave computes the same ones)
+            if (lane < half) {
                 int p, q;
-                rr_pair(ne, r, tid, p, q);
+                rr_pair(ne, r, lane, p, q);
                 double cs, sn, er, ei;
-                jacobi_rot(Ar[p][p], Ar[q][q], Ar[p][q], Ai[p][q], cs, sn, er, ei);
-                rc[tid] = cs;
-                rs[tid] = sn;
-                rer[tid] = er;
-                rei[tid] = ei;
-                rp[tid] = p;
-                rq[tid] = q;
+                jacobi_rot(Sr[p][p], Sr[q][q], Sr[p][q], Si[p][q], cs, sn, er, ei);
+                rc[wv][lane] = cs;
+                rs[wv][lane] = sn;
+                rer[wv][lane] = er;
+                rei[wv][lane] = ei;
             }
-            __syncthreads();
-            // A <- J^H A J on every 2x2 block; J = [[cs, sn e], [-sn conj(e), cs]]
+            // the LDS executes a wave's accesses in issue order: keep the compiler from
+            // moving the reads below above the writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // D = J^H S J on every 2x2 block; J = [[cs, sn e], [-sn conj(e), cs]]
             // one pass: items [0, half^2) update A, items [half^2, half^2 + ne half) update V
-            for (int it = tid; it < half * half + ne * half; it += kEigThreads) {
+            for (int it = tid; it < half * half + ne * half; it += NT) {
                 if (it < half * half) {
                     const int idx = it;
                     const int al = idx / half, be = idx % half;
-                    const int p = rp[al], q = rq[al], u = rp[be], w = rq[be];
-                    const double c1 = rc[al], s1 = rs[al], e1r = rer[al], e1i = rei[al];
-                    const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
-                    const double b00r = Ar[p][u], b00i = Ai[p][u], b01r = Ar[p][w], b01i = Ai[p][w];
-                    const double b10r = Ar[q][u], b10i = Ai[q][u], b11r = Ar[q][w], b11i = Ai[q][w];
+                    int p, q, u, w;
+                    rr_pair(ne, r, al, p, q);
+                    rr_pair(ne, r, be, u, w);
+                    const double c1 = rc[wv][al], s1 = rs[wv][al], e1r = rer[wv][al], e1i = rei[wv][al];
+                    const double c2 = rc[wv][be], s2 = rs[wv][be], e2r = rer[wv][be], e2i = rei[wv][be];
+                    const double b00r = Sr[p][u], b00i = Si[p][u], b01r = Sr[p][w], b01i = Si[p][w];
+                    const double b10r = Sr[q][u], b10i = Si[q][u], b11r = Sr[q][w], b11i = Si[q][w];
                     // X = J1^H B, J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
                     const double x00r = c1 * b00r - s1 * (e1r * b10r - e1i * b10i);
                     const double x00i = c1 * b00i - s1 * (e1r * b10i + e1i * b10r);
@@ -545,16 +589,17 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
                         y01r = y01i = y10r = y10i = 0.0;
                         y00i = y11i = 0.0;
                     }
-                    Ar[p][u] = y00r; Ai[p][u] = y00i;
-                    Ar[p][w] = y01r; Ai[p][w] = y01i;
-                    Ar[q][u] = y10r; Ai[q][u] = y10i;
-                    Ar[q][w] = y11r; Ai[q][w] = y11i;
+                    Dr[p][u] = y00r; Di[p][u] = y00i;
+                    Dr[p][w] = y01r; Di[p][w] = y01i;
+                    Dr[q][u] = y10r; Di[q][u] = y10i;
+                    Dr[q][w] = y11r; Di[q][w] = y11i;
                 } else {
                     // V <- V J
                     const int idx = it - half * half;
                     const int i = idx / half, be = idx % half;
-                    const int u = rp[be], w = rq[be];
-                    const double c2 = rc[be], s2 = rs[be], e2r = rer[be], e2i = rei[be];
+                    int u, w;
+                    rr_pair(ne, r, be, u, w);
+                    const double c2 = rc[wv][be], s2 = rs[wv][be], e2r = rer[wv][be], e2i = rei[wv][be];
                     const double v0r = Vr[i][u], v0i = Vi[i][u], v1r = Vr[i][w], v1i = Vi[i][w];
                     Vr[i][u] = c2 * v0r - s2 * (v1r * e2r + v1i * e2i);
                     Vi[i][u] = c2 * v0i - s2 * (v1i * e2r - v1r * e2i);
@@ -562,10 +607,13 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
                     Vi[i][w] = s2 * (v0r * e2i + v0i * e2r) + c2 * v1i;
                 }
             }
+            // every entry of D was written (the pairs partition the indices); the next round
+            // reads D and overwrites S, whose last readers are behind this barrier
             __syncthreads();
+            cur ^= 1;
         }
     }
-    double (*Acur)[kNMax + 1] = Ar;
+    double (*Acur)[kNMax + 1] = Ab[cur][0];
 
     // spectrum, descending ranks (ties broken by index), thresholds
     if (tid < n) sig[tid] = sqrt(fmax(Acur[tid][tid], 0.0));
@@ -609,7 +657,7 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
     (void)nuc_part;
     // W = V diag(phi) V^H and its real-expanded MFMA operand
     const int K2 = 2 * NTP;
-    for (int idx = tid; idx < NTP * NTP; idx += kEigThreads) {
+    for (int idx = tid; idx < NTP * NTP; idx += NT) {
         const int t = idx / NTP, j = idx % NTP;
         double wr = 0.0, wi = 0.0;
         if (t < n && j < n) {
@@ -630,15 +678,19 @@ __global__ void __launch_bounds__(kEigThreads) pls_eig_kernel(EigArgs a) {
         a.Wop[(NTP + j) * K2 + t] = fi;       // Wr[t][NTP+j]     =  Im W
         a.Wop[(NTP + j) * K2 + NTP + t] = fr; // Wr[NTP+t][NTP+j] =  Re W
     }
-    for (int idx = tid; idx < n * n; idx += kEigThreads) {
+    for (int idx = tid; idx < n * n; idx += NT) {
         const int i = idx / n, j = idx % n;
         a.V[2 * idx] = Vr[i][j];
         a.V[2 * idx + 1] = Vi[i][j];
     }
 }
 
+void launch_eig_batched(const EigArgs& a, const Batched<EigArgs>* bt, hipStream_t s) {
+    PLS_LAUNCH(dim3(1), dim3(kEigThreads), s, a, bt, pls_eig_kernel, kEigThreads);
+}
+
 void launch_eig(const EigArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(pls_eig_kernel, dim3(1), dim3(kEigThreads), 0, s, a);
+    launch_eig_batched(a, nullptr, s);
 }
 
 }  // namespace pls

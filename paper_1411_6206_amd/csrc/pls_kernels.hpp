@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pls {
 
 struct DcArgs {
@@ -77,6 +79,7 @@ struct GramArgs {
 // returns number of blocks
 int launch_gram(int mode, const GramArgs& a, hipStream_t s);
 int gram_blocks(int N, int target = 0);
+int gram_vpb(int N, int target);   // voxels per Gram block
 int gram_tiles(int nt);
 void launch_gram_reduce(const double* part, int blocks, int entries, double* out, hipStream_t s);
 
@@ -133,5 +136,82 @@ struct StatsArgs {
     double lambda_S;
 };
 void launch_stats(const StatsArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- batched launches
+// A kernel reads its argument block through a source.  ArgOne carries the block by value
+// (one problem per launch).  ArgBatch serves several problems of one geometry in one
+// launch: the blocks with blockIdx.z == b work on problem b, read args[b] from device
+// memory, return at once while active[b] is 0, and add rec_off to the statistics-record
+// pointer (eigensolver and statistics kernels: the iteration's slot in the chunk).
+template <class A>
+__device__ __forceinline__ void offset_record(A&, long) {}
+__device__ __forceinline__ void offset_record(EigArgs& a, long off) { a.stat += off; }
+__device__ __forceinline__ void offset_record(StatsArgs& a, long off) { a.stat += off; }
+
+template <class A>
+struct ArgOne {
+    A a;
+    __device__ __forceinline__ bool skip() const { return false; }
+    __device__ __forceinline__ A get() const { return a; }
+};
+
+template <class A>
+struct ArgBatch {
+    const A* args;         // [count] (device)
+    const int* active;     // [count] (device), or NULL: all active
+    long rec_off;
+    __device__ __forceinline__ bool skip() const { return active && active[blockIdx.z] == 0; }
+    __device__ __forceinline__ A get() const {
+        A a = args[blockIdx.z];
+        offset_record(a, rec_off);
+        return a;
+    }
+};
+
+// A batched launch: `count` problems (grid z), their device argument blocks, the per-problem
+// activity flags (device, or NULL) and the record offset.
+template <class A>
+struct Batched {
+    int count;
+    const A* args;
+    const int* active;
+    long rec_off;
+    ArgBatch<A> src() const { return ArgBatch<A>{args, active, rec_off}; }
+};
+
+// Launches kernel template KERN (its last template parameter is the argument source) with
+// the remaining template arguments given after the fixed ones: for one problem (BT NULL)
+// with argument block A by value, else for the batch *BT with the grid's z extent set to
+// the problem count.
+#define PLS_LAUNCH(GRID, BLOCK, STREAM, A, BT, KERN, ...)                                   \
+    do {                                                                                    \
+        using PlsA_ = std::decay_t<decltype(A)>;                                            \
+        if (BT) {                                                                           \
+            dim3 g_ = (GRID);                                                               \
+            g_.z = (unsigned)(BT)->count;                                                   \
+            hipLaunchKernelGGL((KERN<__VA_ARGS__, ::pls::ArgBatch<PlsA_>>), g_, (BLOCK), 0,  \
+                               (STREAM), (BT)->src());                                      \
+        } else {                                                                            \
+            hipLaunchKernelGGL((KERN<__VA_ARGS__, ::pls::ArgOne<PlsA_>>), (GRID), (BLOCK),  \
+                               0, (STREAM), ::pls::ArgOne<PlsA_>{(A)});                      \
+        }                                                                                   \
+    } while (0)
+
+struct ReduceArgs {
+    const double* part;    // [blocks][entries]
+    double* out;           // [entries]
+    int blocks, entries;
+};
+
+int launch_gram_batched(int mode, const GramArgs& a0, const Batched<GramArgs>* bt, hipStream_t s);
+void launch_gram_reduce_batched(const ReduceArgs& a0, const Batched<ReduceArgs>* bt, hipStream_t s);
+void launch_eig_batched(const EigArgs& a0, const Batched<EigArgs>* bt, hipStream_t s);
+void launch_bp_batched(const BpArgs& a0, const Batched<BpArgs>* bt, hipStream_t s);
+int launch_sparse_batched(int levels, const SparseArgs& a0, const Batched<SparseArgs>* bt,
+                          hipStream_t s);
+int launch_sparse_tfft_batched(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s);
+void launch_stats_batched(const StatsArgs& a0, const Batched<StatsArgs>* bt, hipStream_t s);
+int launch_dc_batched(int ny, int nz, bool stats, const DcArgs& a0, const Batched<DcArgs>* bt,
+                      hipStream_t s);
 
 }  // namespace pls

@@ -15,8 +15,10 @@ namespace pls {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- back-projection
-template <int NB>
-__global__ void __launch_bounds__(256) pls_bp_kernel(BpArgs a) {
+template <int NB, class SRC>
+__global__ void __launch_bounds__(256) pls_bp_kernel(SRC src) {
+    if (src.skip()) return;
+    const BpArgs a = src.get();
     constexpr int NTP = 16 * NB, K2 = 2 * NTP, MB = K2 / 16, KS = K2 / 4, KH = NTP / 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
@@ -74,15 +76,17 @@ __global__ void __launch_bounds__(256) pls_bp_kernel(BpArgs a) {
     }
 }
 
-void launch_bp(const BpArgs& a, hipStream_t s) {
+void launch_bp_batched(const BpArgs& a, const Batched<BpArgs>* bt, hipStream_t s) {
     const int tiles = (a.N + 63) / 64;
     const int cap = a.max_grid > 0 ? a.max_grid : 2048;
     const int grid = tiles < cap ? tiles : cap;
     if (a.nt <= 16)
-        hipLaunchKernelGGL(pls_bp_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+        PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_bp_kernel, 1);
     else
-        hipLaunchKernelGGL(pls_bp_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+        PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_bp_kernel, 2);
 }
+
+void launch_bp(const BpArgs& a, hipStream_t s) { launch_bp_batched(a, nullptr, s); }
 
 // ---------------------------------------------------------------- sparse update
 __device__ __forceinline__ float2 shfl_xor2(float2 v, int m) {
@@ -132,8 +136,10 @@ __device__ __forceinline__ void haar_level(float2 (&v)[1 << J], int l, int yl, i
     (void)lane;
 }
 
-template <int J, bool ZA>
-__global__ void __launch_bounds__(256) pls_sparse_kernel(SparseArgs a) {
+template <int J, bool ZA, class SRC>
+__global__ void __launch_bounds__(256) pls_sparse_kernel(SRC src) {
+    if (src.skip()) return;
+    const SparseArgs a = src.get();
     constexpr int B = 1 << J;
     constexpr int ZW = ZA ? B : 1;
     constexpr int YW = 64 / ZW;
@@ -201,25 +207,30 @@ __global__ void __launch_bounds__(256) pls_sparse_kernel(SparseArgs a) {
 }
 
 template <int J, bool ZA>
-static int sparse_launch_t(const SparseArgs& a, hipStream_t s) {
+static int sparse_launch_t(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
     constexpr int B = 1 << J;
     constexpr int ZW = ZA ? B : 1;
     constexpr int YW = 64 / ZW;
     const int nyt = (a.ny + 4 * YW - 1) / (4 * YW);
     const int tiles = nyt * (a.nz / ZW) * (a.nx / B);
-    hipLaunchKernelGGL((pls_sparse_kernel<J, ZA>), dim3(tiles, a.nt), dim3(256), 0, s, a);
+    PLS_LAUNCH(dim3(tiles, a.nt), dim3(256), s, a, bt, pls_sparse_kernel, J, ZA);
     return tiles * a.nt;
 }
 
-int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
+int launch_sparse_batched(int levels, const SparseArgs& a, const Batched<SparseArgs>* bt,
+                          hipStream_t s) {
     const bool za = a.nz > 1;
     switch (levels) {
-        case 0: return za ? sparse_launch_t<0, true>(a, s) : sparse_launch_t<0, false>(a, s);
-        case 1: return za ? sparse_launch_t<1, true>(a, s) : sparse_launch_t<1, false>(a, s);
-        case 2: return za ? sparse_launch_t<2, true>(a, s) : sparse_launch_t<2, false>(a, s);
-        case 3: return za ? sparse_launch_t<3, true>(a, s) : sparse_launch_t<3, false>(a, s);
+        case 0: return za ? sparse_launch_t<0, true>(a, bt, s) : sparse_launch_t<0, false>(a, bt, s);
+        case 1: return za ? sparse_launch_t<1, true>(a, bt, s) : sparse_launch_t<1, false>(a, bt, s);
+        case 2: return za ? sparse_launch_t<2, true>(a, bt, s) : sparse_launch_t<2, false>(a, bt, s);
+        case 3: return za ? sparse_launch_t<3, true>(a, bt, s) : sparse_launch_t<3, false>(a, bt, s);
     }
     return 0;
+}
+
+int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
+    return launch_sparse_batched(levels, a, nullptr, s);
 }
 
 // ---------------------------------------------------------------- sparse update, temporal T
@@ -235,8 +246,10 @@ int sparse_tfft_blocks(int N) {
     return tiles < 2048 ? tiles : 2048;
 }
 
-template <int NB>
-__global__ void __launch_bounds__(256) pls_tfft_sparse_kernel(SparseArgs a) {
+template <int NB, class SRC>
+__global__ void __launch_bounds__(256) pls_tfft_sparse_kernel(SRC src) {
+    if (src.skip()) return;
+    const SparseArgs a = src.get();
     constexpr int NTP = 16 * NB, K2 = 2 * NTP, MB = K2 / 16, KS = K2 / 4, KH = NTP / 4;
     __shared__ double red[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -352,19 +365,27 @@ __global__ void __launch_bounds__(256) pls_tfft_sparse_kernel(SparseArgs a) {
     if (threadIdx.x == 0) a.part[blockIdx.x] = s;
 }
 
-int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
+int launch_sparse_tfft_batched(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
     const int grid = sparse_tfft_blocks(a.nx * a.ny * a.nz);
     if (a.nt <= 16)
-        hipLaunchKernelGGL(pls_tfft_sparse_kernel<1>, dim3(grid), dim3(256), 0, s, a);
+        PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_tfft_sparse_kernel, 1);
     else
-        hipLaunchKernelGGL(pls_tfft_sparse_kernel<2>, dim3(grid), dim3(256), 0, s, a);
+        PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_tfft_sparse_kernel, 2);
     return grid;
+}
+
+int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
+    return launch_sparse_tfft_batched(a, nullptr, s);
 }
 
 // ---------------------------------------------------------------- statistics
 // stat record (doubles): [0] ||r||^2, [1] ||Y - Yold||^2, [2] ||Yold||^2, [3] weighted l1,
 // [4] nuclear norm, [5] tau_L, [6] Jacobi sweeps, [7] non-finite flag, [16..48) sigma
-__global__ void __launch_bounds__(256) pls_stats_kernel(StatsArgs a) {
+template <int NTH, class SRC>
+__global__ void __launch_bounds__(NTH) pls_stats_kernel(SRC src) {
+    static_assert(NTH == 256, "one block of 256 threads");
+    if (src.skip()) return;
+    const StatsArgs a = src.get();
     __shared__ double red[4];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int b = threadIdx.x; b < a.dc_blocks; b += 256) {
@@ -388,8 +409,10 @@ __global__ void __launch_bounds__(256) pls_stats_kernel(StatsArgs a) {
     }
 }
 
-void launch_stats(const StatsArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(pls_stats_kernel, dim3(1), dim3(256), 0, s, a);
+void launch_stats_batched(const StatsArgs& a, const Batched<StatsArgs>* bt, hipStream_t s) {
+    PLS_LAUNCH(dim3(1), dim3(256), s, a, bt, pls_stats_kernel, 256);
 }
+
+void launch_stats(const StatsArgs& a, hipStream_t s) { launch_stats_batched(a, nullptr, s); }
 
 }  // namespace pls

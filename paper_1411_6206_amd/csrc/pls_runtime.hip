@@ -1337,3 +1337,451 @@ int prior_ls_op_sparse(prior_ls_handle* h, const void* Xm, const void* Lp, void*
 }
 
 }  // extern "C"
+
+// ================================================================ batches
+// A batch advances several loaded handles of one geometry together: every kernel of an
+// iteration is launched once for all of them (grid z = problem), each problem's blocks
+// reading its argument block from device memory.  Problems stop on their own terms (their
+// iteration count, or convergence checked at their own chunk boundaries, as when run
+// alone); the blocks of a stopped problem return at once.
+
+struct prior_ls_batch {
+    std::vector<prior_ls_handle*> hs;
+    int device = 0;
+    prior_ls_dims d{};
+    Sizes sz{};
+    prior_ls_tuning tuning{};
+    hipStream_t stream = nullptr, side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr, ev_h = nullptr;
+    char* dev = nullptr;       // argument arrays [kernel][parity][problem] and activity flags
+    char* host = nullptr;      // pinned staging of the same layout
+    size_t bytes = 0;
+    size_t off[8] = {0};       // gram, reduce, eig, bp, sparse, dc, stats, active
+    int gram_vpb = 0;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_objs;
+    std::string err;
+    void clear_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto g : graph_objs) (void)hipGraphDestroy(g);
+        graphs.clear();
+        graph_objs.clear();
+    }
+};
+
+namespace {
+
+constexpr int kMaxBatch = 4096;
+
+int bfail(prior_ls_batch* b, int code, const std::string& m) {
+    if (b) b->err = m;
+    return code;
+}
+
+bool same_geometry(const prior_ls_dims& a, const prior_ls_dims& b) {
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.nt == b.nt && a.nc == b.nc &&
+           a.wavelet_levels == b.wavelet_levels && a.gram_mode == b.gram_mode &&
+           a.transform == b.transform;
+}
+
+template <class T>
+T* barr(prior_ls_batch* b, char* base, int k, int parity) {
+    return reinterpret_cast<T*>(base + b->off[k]) + (size_t)parity * b->hs.size();
+}
+
+// Argument blocks of every problem for both parities of the state (p = index of the
+// current iterate), written to the pinned staging area and copied to the device.
+void batch_upload_args(prior_ls_batch* b) {
+    const int n = (int)b->hs.size();
+    const prior_ls_dims& d = b->d;
+    const Sizes& sz = b->sz;
+    for (int p = 0; p < 2; ++p) {
+        const int q = 1 - p;
+        for (int i = 0; i < n; ++i) {
+            prior_ls_handle* h = b->hs[i];
+            barr<pls::GramArgs>(b, b->host, 0, p)[i] =
+                pls::GramArgs{h->C, h->gpart, (int)sz.N, d.nt, b->gram_vpb, b->tuning.gram_blocks};
+            barr<pls::ReduceArgs>(b, b->host, 1, p)[i] =
+                pls::ReduceArgs{h->gpart, h->gred, pls::gram_blocks((int)sz.N, b->tuning.gram_blocks),
+                                sz.gentries};
+            pls::EigArgs ea{};
+            ea.gram = h->gred;
+            ea.V = h->V;
+            ea.warm = 1;
+            ea.Wop = h->Wop;
+            ea.Wd = h->Wd;
+            ea.sigma_prev = h->sigma_prev;
+            ea.stat = h->stats_d;            // + slot * kStatRec at launch
+            ea.sigL = h->sigL;
+            ea.nt = d.nt;
+            ea.lambda_L = h->params.lambda_L;
+            ea.lambda_p = h->params.lambda_p;
+            ea.relative = h->params.lambda_L_relative;
+            barr<pls::EigArgs>(b, b->host, 2, p)[i] = ea;
+            barr<pls::BpArgs>(b, b->host, 3, p)[i] =
+                pls::BpArgs{h->C, h->L[q], h->Wop, (int)sz.N, d.nt, b->tuning.bp_grid};
+            pls::SparseArgs sa{};
+            sa.C = h->C;
+            sa.S = h->S[p];
+            sa.Lp = h->L[p];
+            sa.w = h->has_w ? h->w : nullptr;
+            sa.Sout = h->S[q];
+            sa.supp = h->supp;
+            sa.part = h->sp_part;
+            sa.nx = d.nx;
+            sa.ny = d.ny;
+            sa.nz = d.nz;
+            sa.nt = d.nt;
+            sa.lambda_S = (float)h->params.lambda_S;
+            sa.Wf = h->Wtf;
+            sa.Wi = h->Wti;
+            barr<pls::SparseArgs>(b, b->host, 4, p)[i] = sa;
+            DcArgs da = dc_args(h, h->L[q], h->S[q], h->C);
+            da.Lold = h->L[p];
+            da.Sold = h->S[p];
+            barr<DcArgs>(b, b->host, 5, p)[i] = da;
+            barr<pls::StatsArgs>(b, b->host, 6, p)[i] =
+                pls::StatsArgs{h->dc_part, sz.dcb, h->sp_part, sz.spb, h->stats_d, (double)sz.P,
+                               h->params.lambda_S};
+        }
+    }
+    PLS_HIP(hipMemcpyAsync(b->dev, b->host, b->off[7], hipMemcpyHostToDevice, b->stream));
+    PLS_HIP(hipStreamSynchronize(b->stream));
+}
+
+// One iteration of every active problem (the schedule of enqueue_iteration, batched).
+void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
+    const prior_ls_dims& d = b->d;
+    const int n = (int)b->hs.size();
+    hipStream_t s = b->stream, s2 = b->side;
+    const int* act = reinterpret_cast<const int*>(b->dev + b->off[7]);
+    const long rec = (long)slot * kStatRec;
+    const bool fork_first = b->tuning.sparse_fork == 1;
+    if (fork_first) {
+        PLS_HIP(hipEventRecord(b->ev_fork, s));
+        PLS_HIP(hipStreamWaitEvent(s2, b->ev_fork, 0));
+    }
+    const pls::Batched<pls::GramArgs> bg{n, barr<pls::GramArgs>(b, b->dev, 0, p), act, 0};
+    pls::launch_gram_batched(d.gram_mode, barr<pls::GramArgs>(b, b->host, 0, p)[0], &bg, s);
+    if (!fork_first) {
+        PLS_HIP(hipEventRecord(b->ev_fork, s));
+        PLS_HIP(hipStreamWaitEvent(s2, b->ev_fork, 0));
+    }
+    const pls::Batched<pls::SparseArgs> bs{n, barr<pls::SparseArgs>(b, b->dev, 4, p), act, 0};
+    const pls::SparseArgs& sa0 = barr<pls::SparseArgs>(b, b->host, 4, p)[0];
+    if (d.transform == PRIOR_LS_T_TFFT) pls::launch_sparse_tfft_batched(sa0, &bs, s2);
+    else pls::launch_sparse_batched(d.wavelet_levels, sa0, &bs, s2);
+    PLS_HIP(hipEventRecord(b->ev_join, s2));
+    const pls::Batched<pls::ReduceArgs> br{n, barr<pls::ReduceArgs>(b, b->dev, 1, p), act, 0};
+    pls::launch_gram_reduce_batched(barr<pls::ReduceArgs>(b, b->host, 1, p)[0], &br, s);
+    const pls::Batched<pls::EigArgs> be{n, barr<pls::EigArgs>(b, b->dev, 2, p), act, rec};
+    pls::launch_eig_batched(barr<pls::EigArgs>(b, b->host, 2, p)[0], &be, s);
+    const pls::Batched<pls::BpArgs> bb{n, barr<pls::BpArgs>(b, b->dev, 3, p), act, 0};
+    pls::launch_bp_batched(barr<pls::BpArgs>(b, b->host, 3, p)[0], &bb, s);
+    PLS_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
+    const pls::Batched<DcArgs> bd{n, barr<DcArgs>(b, b->dev, 5, p), act, 0};
+    pls::launch_dc_batched(d.ny, d.nz, stats, barr<DcArgs>(b, b->host, 5, p)[0], &bd, s);
+    if (stats) {
+        const pls::Batched<pls::StatsArgs> bt{n, barr<pls::StatsArgs>(b, b->dev, 6, p), act, rec};
+        pls::launch_stats_batched(barr<pls::StatsArgs>(b, b->host, 6, p)[0], &bt, s);
+    }
+}
+
+// m iterations from parity p, captured into a graph per (m, p) when use_graph.
+void run_batch_chunk(prior_ls_batch* b, int m, int p, bool graph) {
+    if (!graph) {
+        for (int j = 0; j < m; ++j) enqueue_batch_iteration(b, j, j == m - 1, (p + j) & 1);
+        PLS_HIP(hipGetLastError());
+        return;
+    }
+    const auto key = std::make_pair(m, p);
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        hipGraph_t g = nullptr;
+        PLS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < m; ++j) enqueue_batch_iteration(b, j, j == m - 1, (p + j) & 1);
+        hipError_t le = hipGetLastError();
+        PLS_HIP(hipStreamEndCapture(b->stream, &g));
+        PLS_HIP(le);
+        hipGraphExec_t ex = nullptr;
+        PLS_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        b->graph_objs.push_back(g);
+        it = b->graphs.emplace(key, ex).first;
+    }
+    PLS_HIP(hipGraphLaunch(it->second, b->stream));
+}
+
+// Advances problem i by up to target[i] iterations, stopping it early on convergence (tested
+// where it would be alone: after every check_every iterations of its own and after its last)
+// or on a non-finite iterate.  The handles' streams must have reached the batch (their work
+// before this call is ordered by the caller).  conv[i], status[i] out.
+void batch_iterate(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& conv,
+                   std::vector<int>& status) {
+    const int n = (int)b->hs.size();
+    std::vector<int> done(n, 0);
+    int* act = reinterpret_cast<int*>(b->host + b->off[7]);
+    int* act_d = reinterpret_cast<int*>(b->dev + b->off[7]);
+    conv.assign(n, 0);
+    status.assign(n, PRIOR_LS_OK);
+    for (int i = 0; i < n; ++i) act[i] = target[i] > 0 ? 1 : 0;
+    const bool graph = b->hs[0]->params.use_graph != 0;
+    for (;;) {
+        int m = kMaxChunk, p = -1;
+        for (int i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            const prior_ls_handle* h = b->hs[i];
+            const int ce = std::max(1, std::min(h->params.check_every, kMaxChunk));
+            m = std::min(m, std::min(ce - done[i] % ce, target[i] - done[i]));
+            p = h->cur;        // every active problem has done the same number of iterations
+        }
+        if (p < 0) break;
+        PLS_HIP(hipMemcpyAsync(act_d, act, n * sizeof(int), hipMemcpyHostToDevice, b->stream));
+        run_batch_chunk(b, m, p, graph);
+        for (int i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            prior_ls_handle* h = b->hs[i];
+            PLS_HIP(hipMemcpyAsync(h->stats_h, h->stats_d + (size_t)(m - 1) * kStatRec,
+                                   kStatRec * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        }
+        PLS_HIP(hipEventRecord(b->ev_done, b->stream));
+        PLS_HIP(hipEventSynchronize(b->ev_done));
+        for (int i = 0; i < n; ++i) {
+            if (!act[i]) continue;
+            prior_ls_handle* h = b->hs[i];
+            const int ce = std::max(1, std::min(h->params.check_every, kMaxChunk));
+            done[i] += m;
+            h->iters += m;
+            if (m % 2) h->cur = 1 - h->cur;
+            std::memcpy(h->last, h->stats_h, sizeof(h->last));
+            if (h->last[7] != 0.0) {
+                status[i] = fail(h, PRIOR_LS_ENONFINITE, "non-finite value in the iterate");
+                act[i] = 0;
+                continue;
+            }
+            if (done[i] % ce == 0 || done[i] == target[i]) {
+                const double rel = h->last[2] > 0 ? std::sqrt(h->last[1] / h->last[2]) : INFINITY;
+                if (h->params.tol > 0 && rel < h->params.tol) {
+                    conv[i] = 1;
+                    act[i] = 0;
+                }
+            }
+            if (done[i] >= target[i]) act[i] = 0;
+        }
+    }
+}
+
+// The batch stream waits for the work queued so far on every handle's stream.
+void batch_join_handles(prior_ls_batch* b) {
+    for (prior_ls_handle* h : b->hs) {
+        PLS_HIP(hipEventRecord(b->ev_h, h->stream));
+        PLS_HIP(hipStreamWaitEvent(b->stream, b->ev_h, 0));
+    }
+}
+
+// Outputs and statistics of every problem on its own stream after the batch's work.
+void batch_finish(prior_ls_batch* b, const prior_ls_outputs* out, prior_ls_stats* stats,
+                  const std::vector<char>& conv, double ms) {
+    PLS_HIP(hipEventRecord(b->ev_done, b->stream));
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        prior_ls_handle* h = b->hs[i];
+        PLS_HIP(hipStreamWaitEvent(h->stream, b->ev_done, 0));
+        write_outputs(h, out ? &out[i] : nullptr);
+        leave(h);
+    }
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        prior_ls_handle* h = b->hs[i];
+        PLS_HIP(hipStreamSynchronize(h->stream));
+        fill_stats(h, stats ? &stats[i] : nullptr, conv[i] != 0, ms);
+    }
+}
+
+template <class F>
+int bguarded(prior_ls_batch* b, F&& f) {
+    try {
+        return f();
+    } catch (const HipError& e) {
+        return bfail(b, PRIOR_LS_EHIP, e.where + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return bfail(b, PRIOR_LS_ENOMEM, "host or device allocation failed");
+    }
+}
+
+int batch_check_io(prior_ls_batch* b, const prior_ls_outputs* out, prior_ls_stats* stats) {
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        if (stats && stats[i].struct_size != sizeof(prior_ls_stats))
+            return bfail(b, PRIOR_LS_EINVAL, "stats[" + std::to_string(i) + "].struct_size mismatch");
+        if (out) {
+            const void* o[] = {out[i].L, out[i].S, out[i].X, out[i].M};
+            for (const void* q : o)
+                if (q && !is_device_ptr(q))
+                    return bfail(b, PRIOR_LS_EINVAL, "outputs[" + std::to_string(i) + "] is not device memory");
+        }
+    }
+    return PRIOR_LS_OK;
+}
+
+int first_status(const std::vector<int>& st) {
+    for (int s : st)
+        if (s) return s;
+    return PRIOR_LS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int prior_ls_batch_create(prior_ls_handle* const* handles, int32_t count, prior_ls_batch** out) {
+    if (!out) return PRIOR_LS_EINVAL;
+    *out = nullptr;
+    if (!handles || count < 1 || count > kMaxBatch) {
+        pls::set_thread_error("handles is NULL or count outside [1, 4096]");
+        return PRIOR_LS_EINVAL;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (!handles[i]) {
+            pls::set_thread_error("handles[" + std::to_string(i) + "] is NULL");
+            return PRIOR_LS_EINVAL;
+        }
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == handles[i]) {
+                pls::set_thread_error("a handle appears twice in the batch");
+                return PRIOR_LS_EINVAL;
+            }
+        if (!same_geometry(handles[i]->d, handles[0]->d) || handles[i]->device != handles[0]->device) {
+            pls::set_thread_error("the handles of a batch need one geometry, Gram mode, transform and device");
+            return PRIOR_LS_EINVAL;
+        }
+    }
+    auto* b = new (std::nothrow) prior_ls_batch();
+    if (!b) return PRIOR_LS_ENOMEM;
+    b->hs.assign(handles, handles + count);
+    b->d = handles[0]->d;
+    b->sz = handles[0]->sz;
+    b->device = handles[0]->device;
+    b->tuning = handles[0]->tuning;
+    const int rc = bguarded(b, [&]() -> int {
+        PLS_HIP(hipSetDevice(b->device));
+        PLS_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        PLS_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+        PLS_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&b->ev_h, hipEventDisableTiming));
+        const size_t sizes[7] = {sizeof(pls::GramArgs), sizeof(pls::ReduceArgs), sizeof(pls::EigArgs),
+                                 sizeof(pls::BpArgs), sizeof(pls::SparseArgs), sizeof(DcArgs),
+                                 sizeof(pls::StatsArgs)};
+        size_t o = 0;
+        for (int k = 0; k < 7; ++k) {
+            b->off[k] = o;
+            o += (2 * (size_t)count * sizes[k] + 255) / 256 * 256;
+        }
+        b->off[7] = o;
+        b->bytes = o + ((size_t)count * sizeof(int) + 255) / 256 * 256;
+        void* dp = nullptr;
+        PLS_HIP(hipMalloc(&dp, b->bytes));
+        b->dev = static_cast<char*>(dp);
+        void* hp = nullptr;
+        PLS_HIP(hipHostMalloc(&hp, b->bytes, hipHostMallocDefault));
+        b->host = static_cast<char*>(hp);
+        std::memset(b->host, 0, b->bytes);
+        b->gram_vpb = pls::gram_vpb((int)b->sz.N, b->tuning.gram_blocks);
+        return PRIOR_LS_OK;
+    });
+    if (rc) {
+        pls::set_thread_error(b->err);
+        prior_ls_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PRIOR_LS_OK;
+}
+
+void prior_ls_batch_destroy(prior_ls_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
+    b->clear_graphs();
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->host) (void)hipHostFree(b->host);
+    hipEvent_t evs[] = {b->ev_fork, b->ev_join, b->ev_done, b->ev_h};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    delete b;
+}
+
+const char* prior_ls_batch_last_error(const prior_ls_batch* b) {
+    return b ? b->err.c_str() : "";
+}
+
+int prior_ls_batch_solve(prior_ls_batch* b, const prior_ls_inputs* in, const prior_ls_params* params,
+                         const prior_ls_outputs* out, prior_ls_stats* stats) {
+    if (!b) return PRIOR_LS_EINVAL;
+    b->err.clear();
+    if (!in || !params) return bfail(b, PRIOR_LS_EINVAL, "inputs and params are required");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = (int)b->hs.size();
+    for (int i = 0; i < n; ++i) {
+        prior_ls_handle* h = b->hs[i];
+        h->err.clear();
+        const int rc = check_inputs(h, &in[i], &params[i]);
+        if (rc) return bfail(b, rc, "problem " + std::to_string(i) + ": " + h->err);
+    }
+    int rc = batch_check_io(b, out, stats);
+    if (rc) return rc;
+    return bguarded(b, [&]() -> int {
+        std::vector<int> target(n);
+        for (int i = 0; i < n; ++i) {
+            prior_ls_handle* h = b->hs[i];
+            enter(h);
+            const int r = load_problem(h, &in[i], &params[i]);
+            if (r) return bfail(b, r, "problem " + std::to_string(i) + ": " + h->err);
+            target[i] = params[i].max_iter;
+        }
+        PLS_HIP(hipSetDevice(b->device));
+        batch_upload_args(b);
+        batch_join_handles(b);
+        std::vector<char> conv;
+        std::vector<int> st;
+        batch_iterate(b, target, conv, st);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        batch_finish(b, out, stats, conv, ms);
+        const int r = first_status(st);
+        if (r) b->err = "a problem of the batch reached a non-finite iterate";
+        return r;
+    });
+}
+
+int prior_ls_batch_step(prior_ls_batch* b, int32_t n_iter, const prior_ls_outputs* out,
+                        prior_ls_stats* stats) {
+    if (!b) return PRIOR_LS_EINVAL;
+    b->err.clear();
+    if (n_iter < 0) return bfail(b, PRIOR_LS_EINVAL, "n_iter must be >= 0");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int n = (int)b->hs.size();
+    for (int i = 0; i < n; ++i) {
+        const prior_ls_handle* h = b->hs[i];
+        if (!h->loaded) return bfail(b, PRIOR_LS_EINVAL, "problem " + std::to_string(i) + " is not loaded");
+        if (h->cur != b->hs[0]->cur)
+            return bfail(b, PRIOR_LS_EINVAL, "the problems of a batch step must have done iterations of one parity");
+    }
+    int rc = batch_check_io(b, out, stats);
+    if (rc) return rc;
+    return bguarded(b, [&]() -> int {
+        for (prior_ls_handle* h : b->hs) enter(h);
+        PLS_HIP(hipSetDevice(b->device));
+        batch_upload_args(b);
+        batch_join_handles(b);
+        std::vector<char> conv;
+        std::vector<int> st;
+        batch_iterate(b, std::vector<int>(n, n_iter), conv, st);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        batch_finish(b, out, stats, conv, ms);
+        const int r = first_status(st);
+        if (r) b->err = "a problem of the batch reached a non-finite iterate";
+        return r;
+    });
+}
+
+}  // extern "C"

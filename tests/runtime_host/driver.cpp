@@ -2,7 +2,7 @@
 // the CPU against stand-ins of HIP and of the kernels: sequences of five geometries (one
 // with fully sampled appended frames, so its sample store grows), four in flight, a budget
 // that forces queueing and evictions, submitted from a second thread; then the synchronous
-// entry points on several handles from several threads at once.
+// entry points on several handles from several threads at once, and batches.
 #include <atomic>
 #include <cstdio>
 #include <random>
@@ -137,6 +137,62 @@ int main() {
             prior_ls_destroy(h);
         });
     for (auto& t : th) t.join();
+    // a batch of three problems of one geometry with their own iteration counts and check
+    // intervals, then a batched step; a batch of mixed geometries is refused
+    {
+        Seq q[3];
+        prior_ls_handle* hb[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < 3; ++k) {
+            q[k].g = kGeo[1];
+            q[k].n_append = 0;
+            make_seq(q[k], rng);
+            if (prior_ls_create(&q[k].rq.dims, nullptr, &hb[k])) ++sync_bad;
+        }
+        prior_ls_batch* b = nullptr;
+        if (prior_ls_batch_create(hb, 3, &b)) ++sync_bad;
+        prior_ls_inputs in[3];
+        prior_ls_params pr[3];
+        prior_ls_outputs out[3];
+        prior_ls_stats st[3];
+        const int iters[3] = {8, 5, 3}, ce[3] = {4, 2, 3};
+        for (int k = 0; k < 3; ++k) {
+            in[k] = prior_ls_inputs{q[k].k0, q[k].m0, q[k].sens, nullptr, nullptr, nullptr, nullptr};
+            pr[k] = q[k].rq.first;
+            pr[k].max_iter = iters[k];
+            pr[k].check_every = ce[k];
+            out[k] = q[k].rq.out;
+            st[k] = prior_ls_stats{};
+            st[k].struct_size = sizeof(prior_ls_stats);
+        }
+        if (prior_ls_batch_solve(b, in, pr, out, st)) ++sync_bad;
+        for (int k = 0; k < 3; ++k)
+            if (st[k].iters != iters[k]) {
+                ++sync_bad;
+                std::printf("batch problem %d: %d iterations\n", k, st[k].iters);
+            }
+        // after 8, 5 and 3 iterations the parities differ: a batched step is refused
+        if (prior_ls_batch_step(b, 2, out, st) != PRIOR_LS_EINVAL) ++sync_bad;
+        prior_ls_batch_destroy(b);
+        prior_ls_handle* h3[2] = {hb[1], hb[2]};       // 5 and 3 iterations: both odd
+        if (prior_ls_batch_create(h3, 2, &b)) ++sync_bad;
+        prior_ls_stats st2[2];
+        for (auto& x : st2) {
+            x = prior_ls_stats{};
+            x.struct_size = sizeof(prior_ls_stats);
+        }
+        if (prior_ls_batch_step(b, 4, nullptr, st2)) ++sync_bad;
+        if (st2[0].iters != 9 || st2[1].iters != 7) {
+            ++sync_bad;
+            std::printf("batched step: %d %d iterations\n", st2[0].iters, st2[1].iters);
+        }
+        prior_ls_batch_destroy(b);
+        prior_ls_handle* other = nullptr;
+        if (prior_ls_create(&seqs[0].rq.dims, nullptr, &other)) ++sync_bad;
+        prior_ls_handle* mixed[2] = {hb[0], other};
+        if (seqs[0].g.nx != kGeo[1].nx && prior_ls_batch_create(mixed, 2, &b) != PRIOR_LS_EINVAL) ++sync_bad;
+        prior_ls_destroy(other);
+        for (auto* h : hb) prior_ls_destroy(h);
+    }
     std::printf("done: bad %d sync_bad %d\n", bad, sync_bad.load());
     return bad || sync_bad.load() || info.evicted == 0;
 }

@@ -21,6 +21,20 @@
 #include <thread>
 #include <vector>
 
+// device-side keywords and built-ins that the shared headers mention (never executed here)
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+struct dim3 {
+    unsigned x, y, z;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct fh_block_index {
+    unsigned x = 0, y = 0, z = 0;
+};
+inline fh_block_index blockIdx;
+
 struct float2 {
     float x, y;
 };

@@ -36,10 +36,13 @@ bool dc_supported(int ny, int nz) { return ny >= 16 && ny <= 256 && nz >= 1 && n
 bool xifft_supported(int nx) { return nx >= 16 && nx <= 256; }
 int dc_blocks(int ny, int nz, int nx, int nt) { return nx * nt; }
 int gram_tiles(int nt) { return nt <= 16 ? 3 : 10; }
-int gram_blocks(int N, int target) {
+int gram_vpb(int N, int target) {
     const int t = target > 0 ? target : 512;
-    int vpb = (N + t - 1) / t;
-    vpb = (vpb + 127) / 128 * 128;
+    const int vpb = (N + t - 1) / t;
+    return (vpb + 127) / 128 * 128;
+}
+int gram_blocks(int N, int target) {
+    const int vpb = gram_vpb(N, target);
     return (N + vpb - 1) / vpb;
 }
 
@@ -220,6 +223,63 @@ void launch_stats(const StatsArgs& a, hipStream_t s) {
         c.stat[3] = 1.0;
         c.stat[7] = 0.0;
     });
+}
+
+// Batched launchers: every problem's argument block (already on the "device") goes
+// through the single-problem stand-in; the activity flags are not consulted (touching a
+// stopped problem's arrays is harmless).
+int launch_gram_batched(int mode, const GramArgs& a0, const Batched<GramArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_gram(mode, a0, s);
+    int r = 0;
+    for (int b = 0; b < bt->count; ++b) r = launch_gram(mode, bt->args[b], s);
+    return r;
+}
+void launch_gram_reduce_batched(const ReduceArgs& a0, const Batched<ReduceArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_gram_reduce(a0.part, a0.blocks, a0.entries, a0.out, s);
+    for (int b = 0; b < bt->count; ++b) {
+        const ReduceArgs& r = bt->args[b];
+        launch_gram_reduce(r.part, r.blocks, r.entries, r.out, s);
+    }
+}
+void launch_eig_batched(const EigArgs& a0, const Batched<EigArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_eig(a0, s);
+    for (int b = 0; b < bt->count; ++b) {
+        EigArgs e = bt->args[b];
+        e.stat += bt->rec_off;
+        launch_eig(e, s);
+    }
+}
+void launch_bp_batched(const BpArgs& a0, const Batched<BpArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_bp(a0, s);
+    for (int b = 0; b < bt->count; ++b) launch_bp(bt->args[b], s);
+}
+int launch_sparse_batched(int levels, const SparseArgs& a0, const Batched<SparseArgs>* bt,
+                          hipStream_t s) {
+    if (!bt) return launch_sparse(levels, a0, s);
+    int r = 0;
+    for (int b = 0; b < bt->count; ++b) r = launch_sparse(levels, bt->args[b], s);
+    return r;
+}
+int launch_sparse_tfft_batched(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_sparse_tfft(a0, s);
+    int r = 0;
+    for (int b = 0; b < bt->count; ++b) r = launch_sparse_tfft(bt->args[b], s);
+    return r;
+}
+void launch_stats_batched(const StatsArgs& a0, const Batched<StatsArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_stats(a0, s);
+    for (int b = 0; b < bt->count; ++b) {
+        StatsArgs c = bt->args[b];
+        c.stat += bt->rec_off;
+        launch_stats(c, s);
+    }
+}
+int launch_dc_batched(int ny, int nz, bool stats, const DcArgs& a0, const Batched<DcArgs>* bt,
+                      hipStream_t s) {
+    if (!bt) return launch_dc(ny, nz, stats, a0, s);
+    int r = 0;
+    for (int b = 0; b < bt->count; ++b) r = launch_dc(ny, nz, stats, bt->args[b], s);
+    return r;
 }
 
 }  // namespace pls

@@ -89,6 +89,21 @@ def test_null_server_and_append_calls():
     assert L.prior_ls_server_info(None, C.byref(st)) == pls.EINVAL
 
 
+def test_null_batch_calls():
+    L = pls.lib()
+    L.prior_ls_batch_destroy(None)
+    assert L.prior_ls_batch_last_error(None) == b""
+    b = C.c_void_p()
+    assert L.prior_ls_batch_create(None, 1, C.byref(b)) == pls.EINVAL
+    assert b.value is None
+    arr = (C.c_void_p * 1)(None)
+    assert L.prior_ls_batch_create(arr, 1, C.byref(b)) == pls.EINVAL      # NULL handle
+    assert L.prior_ls_batch_create(arr, 0, C.byref(b)) == pls.EINVAL      # count 0
+    assert L.prior_ls_batch_create(arr, 1, None) == pls.EINVAL
+    assert L.prior_ls_batch_solve(None, None, None, None, None) == pls.EINVAL
+    assert L.prior_ls_batch_step(None, 1, None, None) == pls.EINVAL
+
+
 def test_server_without_gpu_fails_cleanly():
     import torch
     if torch.cuda.is_available():
