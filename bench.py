@@ -229,6 +229,51 @@ def serving_bench(budget_gib, forms):
     return out
 
 
+def batching_bench(steps, warmup):
+    """Batched iterations (prior_ls_batch_*) of the small configurations: B problems of one
+    geometry advanced with one launch per kernel, against one problem alone."""
+    import torch
+    import synth
+    import paper_1411_6206_amd as pls
+    res = {}
+    for cfg, sizes in ((1, (1, 8, 32)), (2, (1, 4, 8))):
+        p = synth.config(cfg)
+        t = pls.to_device(p)
+        J = 2
+        kw = dict(lambda_L=p.lambda_L, lambda_S=p.lambda_S)
+        # one problem on its own handle (hipGraph chunks of 10 iterations)
+        with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) as h:
+            h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], max_iter=warmup, outputs=(), **kw)
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            h.step(steps, outputs=())
+            torch.cuda.synchronize()
+            alone = steps / (time.perf_counter() - a0)
+        rec = {"workload": f"{p.nx}x{p.ny}x{p.nz} voxels x {p.nt} frames x {p.nc} coil(s)",
+               "alone_iterations_per_s": alone, "batches": {}}
+        for B in sizes:
+            hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) for _ in range(B)]
+            try:
+                with pls.Batch(hs) as b:
+                    prm = pls.make_params(max_iter=warmup, **kw)
+                    b.solve([t] * B, prm, outputs=())
+                    torch.cuda.synchronize()
+                    a0 = time.perf_counter()
+                    b.step(steps, outputs=())
+                    torch.cuda.synchronize()
+                    el = time.perf_counter() - a0
+            finally:
+                for hh in hs:
+                    hh.close()
+            rec["batches"][str(B)] = {"iterations_per_s": B * steps / el,
+                                      "speedup_vs_alone": B * steps / el / alone}
+        res[f"c{cfg}"] = rec
+        del t, p
+        torch.cuda.empty_cache()
+        print(f"[bench] batching c{cfg}: {rec}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +292,8 @@ def main():
     ap.add_argument("--no-transforms", action="store_true",
                     help="skip the temporal-Fourier transform measurement")
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batched small-configuration measurements")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -447,6 +494,8 @@ def main():
         del tg, pg
     del t
     torch.cuda.empty_cache()
+    if not args.no_batching:
+        out["batching"] = batching_bench(args.steps, args.warmup)
     if not args.no_serving:
         # plain FP32 form against the split-BF16 Gram form, one sequence in flight (the
         # server keeps concurrent sequences switched off)
