@@ -89,6 +89,33 @@ def test_same_alone_and_in_the_mix():
             assert torch.equal(outs[k], ref[k]), (i, k)
 
 
+def test_same_alone_and_in_a_queued_mix():
+    # sequences of three geometries (0, 0, 1, 2, 2, 0) submitted at once under a budget
+    # that holds the largest plan and little beside it: they queue, reuse the resident
+    # handle of their geometry (whose state the previous sequence left behind) or evict idle
+    # ones, one sequence in flight at a time; each result must equal, bit for bit, the
+    # result of the sequence served on its own
+    reqs = [make_request(i, n_append=1 + i % 3) for i in (0, 3, 1, 2, 5, 6)]
+    alone = []
+    for q, dims, args in reqs:
+        with pls.Server(max_active=1) as srv:
+            outs, res = srv.wait(submit(srv, dims, args))
+            assert res["status"] == pls.OK, res["message"]
+            alone.append(outs)
+    budget = int(max(pls.plan_bytes(q.nx, q.ny, q.nz, q.nt, q.nc) for q, _, _ in reqs) * 1.2)
+    with pls.Server(max_active=1, hbm_budget=budget) as srv:
+        tickets = [submit(srv, dims, args) for _, dims, args in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+        info = srv.info()
+    print("server:", info)
+    assert info["completed"] == len(reqs) and info["peak_used"] <= budget
+    assert info["reused"] >= 1 and info["evicted"] >= 1
+    for i, ((outs, res), ref) in enumerate(zip(mixed, alone)):
+        assert res["status"] == pls.OK, res["message"]
+        for k in ("L", "S", "X", "M"):
+            assert torch.equal(outs[k], ref[k]), (i, k)
+
+
 def test_admission_respects_budget_and_reuses_plans():
     reqs = [make_request(1, n_append=1) for _ in range(4)]     # one geometry
     need = pls.plan_bytes(24, 32, 8, 7, 3)
