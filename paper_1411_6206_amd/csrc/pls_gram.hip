@@ -367,7 +367,7 @@ void launch_gram_reduce(const double* part, int blocks, int entries, double* out
 // rotations of a round applied at once), warm-started from the previous iteration's
 // eigenvectors: A = V^H G V is then nearly diagonal and one or two sweeps suffice.
 constexpr int kNMax = 32;
-constexpr int kEigThreads = 256;    // one block of four waves: it shares its CU with the sparse update
+constexpr int kEigThreads = 512;    // one block of eight waves: it shares its CU with the sparse update
 constexpr int kMaxSweeps = 30;
 
 __device__ __forceinline__ double gram_real(const double* red, int NB, int c1, int c2) {
