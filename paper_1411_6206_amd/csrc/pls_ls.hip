@@ -246,22 +246,43 @@ int sparse_tfft_blocks(int N) {
     return tiles < 2048 ? tiles : 2048;
 }
 
+// A copy of x the compiler cannot see through, so loads addressed with it are not hoisted
+// out of a loop (which would pin their registers for the loop's duration).
+__device__ __forceinline__ int unhoisted(int x) {
+    int y;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+
+// The operands of both products live in LDS in fragment order (a lane fetches the operands
+// of four consecutive k steps with one 16-byte read), not in registers: 128 fewer VGPRs, so
+// four waves per SIMD instead of two hide the memory latency.
 template <int NB, class SRC>
-__global__ void __launch_bounds__(256) pls_tfft_sparse_kernel(SRC src) {
+__global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
     if (src.skip()) return;
     const SparseArgs a = src.get();
     constexpr int NTP = 16 * NB, K2 = 2 * NTP, MB = K2 / 16, KS = K2 / 4, KH = NTP / 4;
+    constexpr int KQ = KS / 4;                 // groups of four k steps
+    constexpr int NF = MB * KQ * 64;           // 16-byte fragments per operand
     __shared__ double red[4];
+    // element (mb, ks) of lane l of an operand at fragment (mb * KQ + ks / 4) * 64 + l,
+    // component ks % 4
+    __shared__ f4 fragF[NF], fragI[NF];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
-    float Af[MB][KS], Ai[MB][KS];
+    for (int e = threadIdx.x; e < NF; e += 256) {
+        const int l = e & 63, q = (e >> 6) % KQ, mb = e / (64 * KQ);
+        const int row = (16 * mb + (l & 15)) * K2, col = 16 * q + (l >> 4);
+        f4 vf, vi;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            Af[mb][ks] = a.Wf[(16 * mb + i16) * K2 + 4 * ks + g];
-            Ai[mb][ks] = a.Wi[(16 * mb + i16) * K2 + 4 * ks + g];
+        for (int j = 0; j < 4; ++j) {
+            vf[j] = a.Wf[row + col + 4 * j];
+            vi[j] = a.Wi[row + col + 4 * j];
         }
+        fragF[e] = vf;
+        fragI[e] = vi;
+    }
+    __syncthreads();
     const int N = a.nx * a.ny * a.nz;
     const int nt = a.nt;
     const int stride = gridDim.x * 4 * 16;
@@ -297,16 +318,24 @@ __global__ void __launch_bounds__(256) pls_tfft_sparse_kernel(SRC src) {
         load_tile(vn < N ? vn : v0, nb);
         const int v = v0 + i16;
         const int vc = v < N ? v : N - 1;
+        const int fl = unhoisted(lane);
         // Z = F U
         f4 z[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) z[mb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const float b = ks < KH ? cb[ks].x : cb[ks - KH].y;
+        for (int q = 0; q < KQ; ++q) {
+            f4 af[MB];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                z[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[mb][ks], b, z[mb], 0, 0, 0);
+            for (int mb = 0; mb < MB; ++mb) af[mb] = fragF[(mb * KQ + q) * 64 + fl];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ks = 4 * q + j;
+                const float b = ks < KH ? cb[ks].x : cb[ks - KH].y;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    z[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][j], b, z[mb], 0, 0, 0);
+            }
         }
         // soft threshold of frequency f = 16 mb + 4 g + r (real part in z[mb], imaginary
         // part in z[mb + MB/2])
@@ -341,14 +370,19 @@ __global__ void __launch_bounds__(256) pls_tfft_sparse_kernel(SRC src) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) o[mb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb) {
+            // k steps 4 mb .. 4 mb + 3 of the inverse: fragment group mb
+            f4 ai[MB];
+#pragma unroll
+            for (int mo = 0; mo < MB; ++mo) ai[mo] = fragI[(mo * KQ + mb) * 64 + fl];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float b = z[mb][r];
 #pragma unroll
                 for (int mo = 0; mo < MB; ++mo)
-                    o[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ai[mo][4 * mb + r], b, o[mo], 0, 0, 0);
+                    o[mo] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[mo][r], b, o[mo], 0, 0, 0);
             }
+        }
         if (v < N) {
 #pragma unroll
             for (int mb = 0; mb < MB / 2; ++mb)
