@@ -14,19 +14,45 @@ namespace pls {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// A copy of x the compiler cannot see through, so loads addressed with it are not hoisted
+// out of a loop (which would pin their registers for the loop's duration).
+__device__ __forceinline__ int unhoisted(int x) {
+    int y;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+
+// Copies a real-expanded K2 x K2 MFMA A operand (row o, column k at o * K2 + k) into LDS in
+// fragment order: element (mb, ks) of lane l (row 16 mb + l % 16, column 4 ks + l / 16) at
+// fragment (mb * KS / 4 + ks / 4) * 64 + l, component ks % 4, so a lane fetches the operands
+// of four consecutive k steps with one 16-byte read.  The caller adds the barrier.
+template <int K2>
+__device__ __forceinline__ void load_fragments(const float* W, f4* frag) {
+    constexpr int MB = K2 / 16, KQ = K2 / 16, NF = MB * KQ * 64;
+    for (int e = threadIdx.x; e < NF; e += blockDim.x) {
+        const int l = e & 63, q = (e >> 6) % KQ, mb = e / (64 * KQ);
+        const int base = (16 * mb + (l & 15)) * K2 + 16 * q + (l >> 4);
+        f4 v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = W[base + 4 * j];
+        frag[e] = v;
+    }
+}
+
+
 // ---------------------------------------------------------------- back-projection
+// The operand lives in LDS in fragment order rather than in 64 VGPRs, for occupancy.
 template <int NB, class SRC>
 __global__ void __launch_bounds__(256) pls_bp_kernel(SRC src) {
     if (src.skip()) return;
     const BpArgs a = src.get();
     constexpr int NTP = 16 * NB, K2 = 2 * NTP, MB = K2 / 16, KS = K2 / 4, KH = NTP / 4;
+    constexpr int KQ = KS / 4;
+    __shared__ f4 frag[MB * KQ * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
-    float Areg[MB][KS];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) Areg[mb][ks] = a.Wop[(16 * mb + i16) * K2 + 4 * ks + g];
+    load_fragments<K2>(a.Wop, frag);
+    __syncthreads();
     const int N = a.N;
     const int stride = gridDim.x * 4 * 16;
     // frames are clamped into range and voxels into the volume, so every load is valid and
@@ -51,15 +77,23 @@ __global__ void __launch_bounds__(256) pls_bp_kernel(SRC src) {
         float2 nb[KH];
         const int vn = v0 + stride;
         load_tile(vn < N ? vn : v0, nb);
+        const int fl = unhoisted(lane);
         f4 acc[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[mb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const float b = ks < KH ? cb[ks].x : cb[ks - KH].y;
+        for (int q = 0; q < KQ; ++q) {
+            f4 af[MB];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Areg[mb][ks], b, acc[mb], 0, 0, 0);
+            for (int mb = 0; mb < MB; ++mb) af[mb] = frag[(mb * KQ + q) * 64 + fl];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ks = 4 * q + j;
+                const float b = ks < KH ? cb[ks].x : cb[ks - KH].y;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mb][j], b, acc[mb], 0, 0, 0);
+            }
         }
         const int v = v0 + i16;
         if (v < N) {
@@ -246,17 +280,8 @@ int sparse_tfft_blocks(int N) {
     return tiles < 2048 ? tiles : 2048;
 }
 
-// A copy of x the compiler cannot see through, so loads addressed with it are not hoisted
-// out of a loop (which would pin their registers for the loop's duration).
-__device__ __forceinline__ int unhoisted(int x) {
-    int y;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
-    return y;
-}
-
-// The operands of both products live in LDS in fragment order (a lane fetches the operands
-// of four consecutive k steps with one 16-byte read), not in registers: 128 fewer VGPRs, so
-// four waves per SIMD instead of two hide the memory latency.
+// The operands of both products live in LDS in fragment order, not in registers: 128
+// fewer VGPRs, so four waves per SIMD instead of two hide the memory latency.
 template <int NB, class SRC>
 __global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
     if (src.skip()) return;
@@ -270,18 +295,8 @@ __global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
     __shared__ f4 fragF[NF], fragI[NF];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
-    for (int e = threadIdx.x; e < NF; e += 256) {
-        const int l = e & 63, q = (e >> 6) % KQ, mb = e / (64 * KQ);
-        const int row = (16 * mb + (l & 15)) * K2, col = 16 * q + (l >> 4);
-        f4 vf, vi;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            vf[j] = a.Wf[row + col + 4 * j];
-            vi[j] = a.Wi[row + col + 4 * j];
-        }
-        fragF[e] = vf;
-        fragI[e] = vi;
-    }
+    load_fragments<K2>(a.Wf, fragF);
+    load_fragments<K2>(a.Wi, fragI);
     __syncthreads();
     const int N = a.nx * a.ny * a.nz;
     const int nt = a.nt;
