@@ -286,9 +286,8 @@ int prior_ls_batch_solve(prior_ls_batch *b, const prior_ls_inputs *in,
                          const prior_ls_params *params, const prior_ls_outputs *out,
                          prior_ls_stats *stats);
 
-/* prior_ls_step of every problem (all loaded, each having done iterations of the same
- * parity, e.g. all freshly solved): n_iter more iterations under each problem's own
- * parameters of its last solve. */
+/* prior_ls_step of every problem (all loaded): n_iter more iterations under each problem's
+ * own parameters of its last solve or append. */
 int prior_ls_batch_step(prior_ls_batch *b, int32_t n_iter, const prior_ls_outputs *out,
                         prior_ls_stats *stats);
 
@@ -303,17 +302,19 @@ void prior_ls_batch_destroy(prior_ls_batch *b);
  *
  * A request is one sequence: its first window of nt frames is reconstructed by plain L+S
  * (prior_ls_solve with no prior weights and lambda_p = 0), then n_append frames are appended
- * one at a time (prior_ls_append).  The server keeps up to max_active sequences in flight,
- * each on its own handle and streams, so their kernels overlap on the GPU; one dispatcher
- * thread drives them all (it enqueues chunks of iterations and polls their completion, so
- * no sequence waits on another's GPU work and the HIP runtime is called from one thread).
- * A request is
- * admitted when the device bytes it needs (prior_ls_plan_bytes plus the compact k-space of
- * its most sampled frame, in nt slots) fit in hbm_budget beside every resident handle.
+ * one at a time (prior_ls_append).  Up to max_active sequences of one geometry are in
+ * flight together as a group, each on its own handle: one dispatcher thread starts every
+ * member's next window (load or shift) and then advances all members with one batch
+ * (prior_ls_batch_*: one launch per kernel of an iteration for all of them), each running
+ * its own window's iterations and stopping rule.  Requests join a running group at window
+ * boundaries while the oldest pending request has the group's geometry; a request of
+ * another geometry waits until the group drains and then starts the next group.  A request
+ * is admitted when the device bytes it needs (prior_ls_plan_bytes plus the compact k-space
+ * of its most sampled frame, in nt slots) fit in hbm_budget beside every resident handle.
  * Handles of finished sequences stay resident and are reused by later requests of the same
- * geometry; idle ones are destroyed, oldest first, when an admission needs their room.
- * Among pending requests the oldest one that fits is admitted first.  Results do not depend
- * on what else runs: every reduction has a fixed order.
+ * geometry; idle ones are destroyed, oldest first, when an admission needs their room.  A
+ * new group starts with the oldest pending request that fits.  Results do not depend on
+ * what else runs: a member of a group computes exactly what it computes alone.
  * Threads: submit, wait and info may be called from any thread. ---- */
 typedef struct prior_ls_server prior_ls_server;
 
@@ -321,10 +322,11 @@ typedef struct {
     size_t   struct_size;       /* = sizeof(prior_ls_server_config) */
     uint64_t hbm_budget;        /* device bytes for resident sequence state; 0 = 90% of the
                                    free device memory at create */
-    int32_t  max_active;        /* sequences in flight at once, 1..64.  This build keeps one
-                                   in flight whatever the value (concurrent sequences are
-                                   switched off: a run with four large ones in flight ended in
-                                   a host segmentation fault whose cause was not found) */
+    int32_t  max_active;        /* sequences of one geometry in flight at once (one batched
+                                   group), 1..64.  Sequences are never driven independently on
+                                   streams of their own: a run with four large ones in flight
+                                   that way ended in a host segmentation fault whose cause was
+                                   not found */
     int32_t  reserved;          /* must be 0 */
 } prior_ls_server_config;
 

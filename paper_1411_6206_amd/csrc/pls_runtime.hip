@@ -1353,11 +1353,12 @@ struct prior_ls_batch {
     prior_ls_tuning tuning{};
     hipStream_t stream = nullptr, side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr, ev_h = nullptr;
-    char* dev = nullptr;       // argument arrays [kernel][parity][problem] and activity flags
+    char* dev = nullptr;       // argument arrays [kernel][phase][problem] and activity flags
     char* host = nullptr;      // pinned staging of the same layout
     size_t bytes = 0;
     size_t off[8] = {0};       // gram, reduce, eig, bp, sparse, dc, stats, active
     int gram_vpb = 0;
+    std::vector<int> staged_cur;   // every problem's iterate index when the arguments were staged
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
     std::string err;
@@ -1384,24 +1385,30 @@ bool same_geometry(const prior_ls_dims& a, const prior_ls_dims& b) {
            a.transform == b.transform;
 }
 
+// Argument block array of kernel k for phase `phase` (iteration j of a chunk uses phase
+// j % 2).
 template <class T>
-T* barr(prior_ls_batch* b, char* base, int k, int parity) {
-    return reinterpret_cast<T*>(base + b->off[k]) + (size_t)parity * b->hs.size();
+T* barr(prior_ls_batch* b, char* base, int k, int phase) {
+    return reinterpret_cast<T*>(base + b->off[k]) + (size_t)phase * b->hs.size();
 }
 
-// Argument blocks of every problem for both parities of the state (p = index of the
-// current iterate), written to the pinned staging area and copied to the device.
+// Argument blocks of every problem for both phases: phase 0 reads problem i's current
+// iterate (index cur), phase 1 the other one, so problems whose iterate indices differ
+// share a launch.  Written to the pinned staging area and copied to the device; every
+// problem's cur is recorded in b->staged_cur.
 void batch_upload_args(prior_ls_batch* b) {
     const int n = (int)b->hs.size();
     const prior_ls_dims& d = b->d;
     const Sizes& sz = b->sz;
-    for (int p = 0; p < 2; ++p) {
-        const int q = 1 - p;
+    b->staged_cur.resize(n);
+    for (int ph = 0; ph < 2; ++ph) {
         for (int i = 0; i < n; ++i) {
             prior_ls_handle* h = b->hs[i];
-            barr<pls::GramArgs>(b, b->host, 0, p)[i] =
+            const int p = h->cur ^ ph, q = 1 - p;
+            b->staged_cur[i] = h->cur;
+            barr<pls::GramArgs>(b, b->host, 0, ph)[i] =
                 pls::GramArgs{h->C, h->gpart, (int)sz.N, d.nt, b->gram_vpb, b->tuning.gram_blocks};
-            barr<pls::ReduceArgs>(b, b->host, 1, p)[i] =
+            barr<pls::ReduceArgs>(b, b->host, 1, ph)[i] =
                 pls::ReduceArgs{h->gpart, h->gred, pls::gram_blocks((int)sz.N, b->tuning.gram_blocks),
                                 sz.gentries};
             pls::EigArgs ea{};
@@ -1417,8 +1424,8 @@ void batch_upload_args(prior_ls_batch* b) {
             ea.lambda_L = h->params.lambda_L;
             ea.lambda_p = h->params.lambda_p;
             ea.relative = h->params.lambda_L_relative;
-            barr<pls::EigArgs>(b, b->host, 2, p)[i] = ea;
-            barr<pls::BpArgs>(b, b->host, 3, p)[i] =
+            barr<pls::EigArgs>(b, b->host, 2, ph)[i] = ea;
+            barr<pls::BpArgs>(b, b->host, 3, ph)[i] =
                 pls::BpArgs{h->C, h->L[q], h->Wop, (int)sz.N, d.nt, b->tuning.bp_grid};
             pls::SparseArgs sa{};
             sa.C = h->C;
@@ -1435,12 +1442,12 @@ void batch_upload_args(prior_ls_batch* b) {
             sa.lambda_S = (float)h->params.lambda_S;
             sa.Wf = h->Wtf;
             sa.Wi = h->Wti;
-            barr<pls::SparseArgs>(b, b->host, 4, p)[i] = sa;
+            barr<pls::SparseArgs>(b, b->host, 4, ph)[i] = sa;
             DcArgs da = dc_args(h, h->L[q], h->S[q], h->C);
             da.Lold = h->L[p];
             da.Sold = h->S[p];
-            barr<DcArgs>(b, b->host, 5, p)[i] = da;
-            barr<pls::StatsArgs>(b, b->host, 6, p)[i] =
+            barr<DcArgs>(b, b->host, 5, ph)[i] = da;
+            barr<pls::StatsArgs>(b, b->host, 6, ph)[i] =
                 pls::StatsArgs{h->dc_part, sz.dcb, h->sp_part, sz.spb, h->stats_d, (double)sz.P,
                                h->params.lambda_S};
         }
@@ -1449,7 +1456,8 @@ void batch_upload_args(prior_ls_batch* b) {
     PLS_HIP(hipStreamSynchronize(b->stream));
 }
 
-// One iteration of every active problem (the schedule of enqueue_iteration, batched).
+// One iteration of every active problem (the schedule of enqueue_iteration, batched),
+// reading the argument blocks of phase p.
 void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
     const prior_ls_dims& d = b->d;
     const int n = (int)b->hs.size();
@@ -1487,19 +1495,19 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
     }
 }
 
-// m iterations from parity p, captured into a graph per (m, p) when use_graph.
-void run_batch_chunk(prior_ls_batch* b, int m, int p, bool graph) {
+// m iterations (phases 0, 1, 0, ...), captured into a graph per m when use_graph.
+void run_batch_chunk(prior_ls_batch* b, int m, bool graph) {
     if (!graph) {
-        for (int j = 0; j < m; ++j) enqueue_batch_iteration(b, j, j == m - 1, (p + j) & 1);
+        for (int j = 0; j < m; ++j) enqueue_batch_iteration(b, j, j == m - 1, j & 1);
         PLS_HIP(hipGetLastError());
         return;
     }
-    const auto key = std::make_pair(m, p);
+    const auto key = std::make_pair(m, 0);
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         hipGraph_t g = nullptr;
         PLS_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        for (int j = 0; j < m; ++j) enqueue_batch_iteration(b, j, j == m - 1, (p + j) & 1);
+        for (int j = 0; j < m; ++j) enqueue_batch_iteration(b, j, j == m - 1, j & 1);
         hipError_t le = hipGetLastError();
         PLS_HIP(hipStreamEndCapture(b->stream, &g));
         PLS_HIP(le);
@@ -1514,9 +1522,11 @@ void run_batch_chunk(prior_ls_batch* b, int m, int p, bool graph) {
 // Advances problem i by up to target[i] iterations, stopping it early on convergence (tested
 // where it would be alone: after every check_every iterations of its own and after its last)
 // or on a non-finite iterate.  The handles' streams must have reached the batch (their work
-// before this call is ordered by the caller).  conv[i], status[i] out.
+// before this call is ordered by the caller).  conv[i], status[i] out; done_at (optional)
+// receives the host time at which problem i's last chunk was seen complete.
 void batch_iterate(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& conv,
-                   std::vector<int>& status) {
+                   std::vector<int>& status,
+                   std::vector<std::chrono::steady_clock::time_point>* done_at = nullptr) {
     const int n = (int)b->hs.size();
     std::vector<int> done(n, 0);
     int* act = reinterpret_cast<int*>(b->host + b->off[7]);
@@ -1524,19 +1534,24 @@ void batch_iterate(prior_ls_batch* b, const std::vector<int>& target, std::vecto
     conv.assign(n, 0);
     status.assign(n, PRIOR_LS_OK);
     for (int i = 0; i < n; ++i) act[i] = target[i] > 0 ? 1 : 0;
+    if (done_at) done_at->assign(n, std::chrono::steady_clock::now());
     const bool graph = b->hs[0]->params.use_graph != 0;
     for (;;) {
-        int m = kMaxChunk, p = -1;
+        int m = kMaxChunk;
+        bool any = false, restage = b->staged_cur.size() != (size_t)n;
         for (int i = 0; i < n; ++i) {
             if (!act[i]) continue;
             const prior_ls_handle* h = b->hs[i];
             const int ce = std::max(1, std::min(h->params.check_every, kMaxChunk));
             m = std::min(m, std::min(ce - done[i] % ce, target[i] - done[i]));
-            p = h->cur;        // every active problem has done the same number of iterations
+            any = true;
+            if (!restage && b->staged_cur[i] != h->cur) restage = true;
         }
-        if (p < 0) break;
+        if (!any) break;
+        // phase 0 must read every active problem's current iterate
+        if (restage) batch_upload_args(b);
         PLS_HIP(hipMemcpyAsync(act_d, act, n * sizeof(int), hipMemcpyHostToDevice, b->stream));
-        run_batch_chunk(b, m, p, graph);
+        run_batch_chunk(b, m, graph);
         for (int i = 0; i < n; ++i) {
             if (!act[i]) continue;
             prior_ls_handle* h = b->hs[i];
@@ -1552,6 +1567,7 @@ void batch_iterate(prior_ls_batch* b, const std::vector<int>& target, std::vecto
             done[i] += m;
             h->iters += m;
             if (m % 2) h->cur = 1 - h->cur;
+            if (done_at) (*done_at)[i] = std::chrono::steady_clock::now();
             std::memcpy(h->last, h->stats_h, sizeof(h->last));
             if (h->last[7] != 0.0) {
                 status[i] = fail(h, PRIOR_LS_ENONFINITE, "non-finite value in the iterate");
@@ -1627,6 +1643,23 @@ int first_status(const std::vector<int>& st) {
 }
 
 }  // namespace
+
+namespace pls {
+
+int batch_run(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& converged,
+              std::vector<int>& status, std::vector<std::chrono::steady_clock::time_point>& done_at) {
+    if (!b || target.size() != b->hs.size()) return bfail(b, PRIOR_LS_EINVAL, "one target per problem");
+    b->err.clear();
+    return bguarded(b, [&]() -> int {
+        PLS_HIP(hipSetDevice(b->device));
+        batch_upload_args(b);        // loads and shifts may have moved arrays or changed lambdas
+        batch_join_handles(b);
+        batch_iterate(b, target, converged, status, &done_at);
+        return PRIOR_LS_OK;
+    });
+}
+
+}  // namespace pls
 
 extern "C" {
 
@@ -1763,8 +1796,6 @@ int prior_ls_batch_step(prior_ls_batch* b, int32_t n_iter, const prior_ls_output
     for (int i = 0; i < n; ++i) {
         const prior_ls_handle* h = b->hs[i];
         if (!h->loaded) return bfail(b, PRIOR_LS_EINVAL, "problem " + std::to_string(i) + " is not loaded");
-        if (h->cur != b->hs[0]->cur)
-            return bfail(b, PRIOR_LS_EINVAL, "the problems of a batch step must have done iterations of one parity");
     }
     int rc = batch_check_io(b, out, stats);
     if (rc) return rc;

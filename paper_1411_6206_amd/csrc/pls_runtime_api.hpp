@@ -5,6 +5,9 @@
 // handle (prior_ls_last_error).
 #pragma once
 
+#include <chrono>
+#include <vector>
+
 #include "prior_ls.h"
 
 namespace pls {
@@ -28,5 +31,14 @@ int phase_outputs(prior_ls_handle* h, const prior_ls_outputs* out);
 void phase_stats(prior_ls_handle* h, prior_ls_stats* st, int converged, double ms);
 // Iterations of the window (params.max_iter of the last load / shift).
 int phase_max_iter(const prior_ls_handle* h);
+
+// Runs the loaded windows of a batch's handles together: handle i does up to target[i]
+// iterations under the parameters of its last load / shift (its own check interval and
+// tolerance), after the work already queued on its stream.  Blocks until all are done.
+// converged[i], status[i] (ENONFINITE) and done_at[i] (when its last chunk was seen
+// complete) out; returns a status for the batch as a whole (EHIP: message in
+// prior_ls_batch_last_error).
+int batch_run(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& converged,
+              std::vector<int>& status, std::vector<std::chrono::steady_clock::time_point>& done_at);
 
 }  // namespace pls

@@ -1,16 +1,19 @@
 // Serving runtime: continuous batching of recursive (sliding-window) reconstructions.
 //
 // A request is one sequence: a first window of nt frames reconstructed by plain L+S, then
-// n_append frames appended one at a time.  Up to max_active sequences are in flight at
-// once, each on its own handle and streams, so their kernels share the GPU.  One host
-// thread (the dispatcher) drives all of them: it starts a window, enqueues chunks of
-// iterations without waiting, polls their completion, and moves each sequence on as its
-// work finishes, so the HIP runtime is called from a single thread.  A request is
-// admitted when the device bytes it needs fit in the budget beside everything resident;
-// handles of finished sequences stay resident (state, sample store, graphs) and are
-// reused by later requests of the same geometry, and idle ones are evicted (oldest first)
-// when an admission needs their room.  Pending requests are admitted oldest first among
-// those that fit, so a small request is not held behind a large one waiting for memory.
+// n_append frames appended one at a time.  Up to max_active sequences of one geometry are
+// in flight together as a group: one host thread (the dispatcher) starts every member's
+// next window (load or shift, on the member's own handle), then advances all of them with
+// one batch (prior_ls_batch: one launch per kernel of an iteration for every member), each
+// member running its own window's iteration count and stopping rule.  Members join a
+// running group at window boundaries while the oldest pending request has the group's
+// geometry; a request of another geometry waits until the group drains, then starts the
+// next group.  A request is admitted when the device bytes it needs fit in the budget
+// beside everything resident; handles of finished sequences stay resident (state, sample
+// store, graphs) and are reused by later requests of the same geometry, and idle ones are
+// evicted (oldest first) when an admission needs their room.  A new group starts with the
+// oldest pending request that fits, so a small request is not held behind a large one
+// waiting for memory.  Every sequence computes exactly what it computes alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -83,15 +86,10 @@ struct Job {
     prior_ls_result result{};
 };
 
-// A sequence in flight: its window, the iterations left in the window and the chunk on the
-// GPU, if any.
-struct Active {
+// A sequence of the running group: its window and that window's start.
+struct Member {
     Job* j = nullptr;
-    enum State { kStart, kRun, kOutputs } st = kStart;
     int window = 0;
-    int remaining = 0;
-    int inflight = 0;
-    int converged = 0;
     Clock::time_point wstart{};
 };
 
@@ -101,13 +99,12 @@ void set_message(prior_ls_result& r, const std::string& m) {
 
 }  // namespace
 
-// Sequences driven at once.  Several sequences in flight is switched off: a run with four
-// large sequences in flight ended in a host segmentation fault (with one dispatcher thread
-// as with one thread per sequence) whose cause was not found, so requests beyond the first
-// queue until it finishes.  (The host tests build the server with more in flight to
-// exercise its logic on the CPU.)
+// Members of a group at most (max_active is clamped to it).  Sequences only ever share the
+// GPU as members of one batch: independently driven sequences on streams of their own were
+// switched off after a run with four large ones in flight ended in a host segmentation
+// fault whose cause was not found.
 #ifndef PLS_SERVER_MAX_IN_FLIGHT
-#define PLS_SERVER_MAX_IN_FLIGHT 1
+#define PLS_SERVER_MAX_IN_FLIGHT 64
 #endif
 constexpr int kMaxInFlight = PLS_SERVER_MAX_IN_FLIGHT;
 
@@ -130,40 +127,59 @@ struct prior_ls_server {
     bool stopping = false;
     std::thread thread;                       // the dispatcher
     hipStream_t ctl = nullptr;                // the dispatcher's mask read-backs
+    prior_ls_batch* batch = nullptr;          // over the running group's handles
+    std::vector<prior_ls_handle*> batch_of;   // the handles `batch` was built over
 
     // Picks the oldest pending job that fits (reusing an idle handle of its geometry, or
     // evicting idle handles to make room); returns nullptr when none fits.  The handles to
     // destroy are returned through `evict` and destroyed by the caller without the lock.
     Job* admit_locked(std::vector<Resident>& evict) {
         for (auto it = pending.begin(); it != pending.end(); ++it) {
+            if (!reserve_locked(*it, evict)) continue;
             Job* j = *it;
-            auto same = std::find_if(idle.begin(), idle.end(),
-                                     [&](const Resident& r) { return same_dims(r.dims, j->req.dims); });
-            if (same != idle.end()) {
-                j->res = *same;
-                j->reused = true;
-                idle.erase(same);
-                if (j->need > j->res.bytes) {       // the sample store may grow
-                    const uint64_t extra = j->need - j->res.bytes;
-                    if (!make_room_locked(extra, evict)) {
-                        idle.push_front(j->res);
-                        j->res = Resident{};
-                        j->reused = false;
-                        continue;
-                    }
-                    used += extra;
-                    j->res.bytes = j->need;
-                }
-            } else {
-                if (!make_room_locked(j->need, evict)) continue;
-                used += j->need;
-                j->res.bytes = j->need;
-            }
-            peak = std::max(peak, used);
             pending.erase(it);
             return j;
         }
         return nullptr;
+    }
+
+    // The oldest pending job if it has geometry `d` and fits; nullptr otherwise.
+    Job* admit_same_locked(const prior_ls_dims& d, std::vector<Resident>& evict) {
+        if (pending.empty() || !same_dims(pending.front()->req.dims, d)) return nullptr;
+        if (!reserve_locked(pending.front(), evict)) return nullptr;
+        Job* j = pending.front();
+        pending.pop_front();
+        return j;
+    }
+
+    // Reserves job j's device bytes: an idle handle of its geometry (grown if its sample
+    // store needs more) or new room, evicting idle handles as needed.  False if it does not
+    // fit (nothing reserved).
+    bool reserve_locked(Job* j, std::vector<Resident>& evict) {
+        auto same = std::find_if(idle.begin(), idle.end(),
+                                 [&](const Resident& r) { return same_dims(r.dims, j->req.dims); });
+        if (same != idle.end()) {
+            j->res = *same;
+            j->reused = true;
+            idle.erase(same);
+            if (j->need > j->res.bytes) {       // the sample store may grow
+                const uint64_t extra = j->need - j->res.bytes;
+                if (!make_room_locked(extra, evict)) {
+                    idle.push_front(j->res);
+                    j->res = Resident{};
+                    j->reused = false;
+                    return false;
+                }
+                used += extra;
+                j->res.bytes = j->need;
+            }
+        } else {
+            if (!make_room_locked(j->need, evict)) return false;
+            used += j->need;
+            j->res.bytes = j->need;
+        }
+        peak = std::max(peak, used);
+        return true;
     }
 
     // Evicts idle handles (oldest first) until `bytes` more fit in the budget.
@@ -256,80 +272,104 @@ struct prior_ls_server {
         return rc;
     }
 
-    // Ends window a.window: records its statistics and latency.
-    void close_window(Active& a) {
-        prior_ls_request& q = a.j->req;
-        const double ms = ms_between(a.wstart, Clock::now());
-        if (q.latency_ms) q.latency_ms[a.window] = ms;
+    // Ends member m's window: records its statistics and latency.
+    void close_window(Member& m, int converged, double ms) {
+        prior_ls_request& q = m.j->req;
+        if (q.latency_ms) q.latency_ms[m.window] = ms;
         if (q.stats) {
             prior_ls_stats st{};
             st.struct_size = sizeof(prior_ls_stats);
-            pls::phase_stats(a.j->res.h, &st, a.converged, ms);
-            q.stats[a.window] = st;
+            pls::phase_stats(m.j->res.h, &st, converged, ms);
+            q.stats[m.window] = st;
         }
     }
 
-    // Moves one sequence on as far as it can go without waiting.  Returns 1 on progress,
-    // 0 when it waits for the GPU, or a negative status (the sequence has failed).
-    int advance(Active& a) {
-        Job* j = a.j;
-        prior_ls_request& q = j->req;
-        prior_ls_handle* h = j->res.h;
-        const bool last = a.window == q.n_append;
-        if (a.st == Active::kStart) {
-            a.wstart = Clock::now();
-            a.converged = 0;
-            int rc;
-            if (a.window == 0) {
-                prior_ls_inputs in{};
-                in.kspace = q.kspace0;
-                in.mask = q.mask0;
-                in.sens = q.sens;
-                prior_ls_params p = q.first;
-                p.lambda_p = 0.0;                  // the first instance has no priors
-                rc = pls::phase_load(h, &in, &p);
-            } else {
-                const size_t P = (size_t)q.dims.ny * q.dims.nz;
-                const size_t fk = (size_t)q.dims.nc * P * q.dims.nx * 8;
-                rc = pls::phase_shift(h, (const char*)q.kspace_frames + (a.window - 1) * fk,
-                                      q.mask_frames + (a.window - 1) * P, &q.next);
-            }
-            if (rc) return rc;
-            a.remaining = pls::phase_max_iter(h);
-            a.inflight = 0;
-            a.st = Active::kRun;
+    // Starts member m's window: the first window loads the problem, a later one slides the
+    // window by the next frame.
+    int start_window(Member& m) {
+        prior_ls_request& q = m.j->req;
+        prior_ls_handle* h = m.j->res.h;
+        m.wstart = Clock::now();
+        if (m.window == 0) {
+            prior_ls_inputs in{};
+            in.kspace = q.kspace0;
+            in.mask = q.mask0;
+            in.sens = q.sens;
+            prior_ls_params p = q.first;
+            p.lambda_p = 0.0;                      // the first instance has no priors
+            return pls::phase_load(h, &in, &p);
         }
-        if (a.st == Active::kRun) {
-            if (a.inflight) {
-                const int r = pls::phase_query(h);
-                if (r <= 0) return r;
-                const int rc = pls::phase_chunk_finish(h, a.inflight, &a.converged);
-                if (rc) return rc;
-                a.remaining -= a.inflight;
-                a.inflight = 0;
-            }
-            if (a.remaining > 0 && !a.converged) {
-                const int m = pls::phase_chunk_launch(h, a.remaining);
-                if (m < 0) return m;
-                a.inflight = m;
-                return 1;
-            }
-            if (!last) {
-                close_window(a);
-                ++a.window;
-                a.st = Active::kStart;
-                return 1;
-            }
-            const int rc = pls::phase_outputs(h, &q.out);
-            if (rc) return rc;
-            a.st = Active::kOutputs;
-            return 1;
+        const size_t P = (size_t)q.dims.ny * q.dims.nz;
+        const size_t fk = (size_t)q.dims.nc * P * q.dims.nx * 8;
+        return pls::phase_shift(h, (const char*)q.kspace_frames + (m.window - 1) * fk,
+                                q.mask_frames + (m.window - 1) * P, &q.next);
+    }
+
+    // Writes member m's outputs and waits for them.
+    int write_outputs(Member& m) {
+        prior_ls_handle* h = m.j->res.h;
+        int rc = pls::phase_outputs(h, &m.j->req.out);
+        while (rc == PRIOR_LS_OK) {
+            const int r = pls::phase_query(h);
+            if (r == 1) break;
+            if (r < 0) return r;
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
-        // kOutputs
-        const int r = pls::phase_query(h);
-        if (r <= 0) return r;
-        close_window(a);
-        return 2;                                 // done
+        return rc;
+    }
+
+    // One window of every member of the group: start them, advance them together as one
+    // batch, record each window, write the outputs of finished sequences.  Members that
+    // finish or fail leave the group (their jobs are finished through `done`: status per job).
+    void run_window(std::vector<Member>& group, std::vector<std::pair<Job*, int>>& done) {
+        std::vector<Member> live;
+        for (Member& m : group) {
+            const int rc = start_window(m);
+            if (rc) done.push_back({m.j, rc});
+            else live.push_back(m);
+        }
+        group.swap(live);
+        if (group.empty()) return;
+        std::vector<prior_ls_handle*> hs;
+        for (Member& m : group) hs.push_back(m.j->res.h);
+        if (hs != batch_of) {
+            prior_ls_batch_destroy(batch);
+            batch = nullptr;
+            batch_of.clear();
+            const int rc = prior_ls_batch_create(hs.data(), (int32_t)hs.size(), &batch);
+            if (rc) {
+                for (Member& m : group) {
+                    set_message(m.j->result, prior_ls_last_error(nullptr));
+                    done.push_back({m.j, rc});
+                }
+                group.clear();
+                return;
+            }
+            batch_of = hs;
+        }
+        std::vector<int> target, status;
+        std::vector<char> conv;
+        std::vector<Clock::time_point> end;
+        for (Member& m : group) target.push_back(pls::phase_max_iter(m.j->res.h));
+        const int rc = pls::batch_run(batch, target, conv, status, end);
+        live.clear();
+        for (size_t i = 0; i < group.size(); ++i) {
+            Member& m = group[i];
+            const int st = rc ? rc : status[i];
+            if (st) {
+                if (rc) set_message(m.j->result, prior_ls_batch_last_error(batch));
+                done.push_back({m.j, st});
+                continue;
+            }
+            close_window(m, conv[i], ms_between(m.wstart, end[i]));
+            if (m.window == m.j->req.n_append) {
+                done.push_back({m.j, write_outputs(m)});
+                continue;
+            }
+            ++m.window;
+            live.push_back(m);
+        }
+        group.swap(live);
     }
 
     // Ends a job (under the lock): its handle goes to the idle pool, or is destroyed
@@ -361,7 +401,7 @@ struct prior_ls_server {
 
     void dispatcher() {
         (void)hipSetDevice(device);
-        std::vector<Active> act;
+        std::vector<Member> group;
         for (;;) {
             std::vector<Resident> evict, destroy;
             std::vector<Job*> admitted, fresh;
@@ -383,53 +423,50 @@ struct prior_ls_server {
             {
                 std::unique_lock<std::mutex> lk(mu);
                 for (;;) {
-                    while ((int)(act.size() + admitted.size()) < in_flight) {
-                        Job* j = admit_locked(evict);
+                    // a new group takes the oldest pending request that fits; a running one
+                    // takes more requests of its geometry while the oldest is one of them
+                    while ((int)(group.size() + admitted.size()) < in_flight) {
+                        Job* j;
+                        if (!group.empty()) j = admit_same_locked(group[0].j->req.dims, evict);
+                        else if (!admitted.empty()) j = admit_same_locked(admitted[0]->req.dims, evict);
+                        else j = admit_locked(evict);
                         if (!j) break;
                         j->admitted = Clock::now();
                         admitted.push_back(j);
                         ++active;
                         peak_active = std::max(peak_active, active);
                     }
-                    if (!act.empty() || !admitted.empty() || !incoming.empty()) break;
-                    if (stopping && pending.empty()) return;
+                    if (!group.empty() || !admitted.empty() || !incoming.empty()) break;
+                    if (stopping && pending.empty()) {
+                        prior_ls_batch_destroy(batch);
+                        batch = nullptr;
+                        batch_of.clear();
+                        return;
+                    }
                     cv_work.wait(lk);             // a submission, or the stop
                 }
             }
             for (Resident& r : evict) destroy_resident(r);
+            std::vector<std::pair<Job*, int>> done;
             for (Job* j : admitted) {
-                Active a;
-                a.j = j;
                 const int rc = open_handle(j);
-                if (rc) {
-                    std::lock_guard<std::mutex> lk(mu);
-                    finish_locked(j, rc, destroy);
-                    cv_done.notify_all();
-                    continue;
-                }
-                act.push_back(a);
+                if (rc) done.push_back({j, rc});
+                else group.push_back(Member{j, 0, {}});
             }
-            bool progress = false;
-            for (size_t i = 0; i < act.size();) {
-                int r = advance(act[i]);
-                while (r == 1) {                          // as far as it goes without waiting
-                    progress = true;
-                    r = advance(act[i]);
-                }
-                if (r == 0) {
-                    ++i;
-                    continue;
-                }
-                progress = true;
+            if (!group.empty()) run_window(group, done);
+            if (!done.empty()) {
+                // a finished member's handle may go back to the idle pool (or be destroyed):
+                // the batch over it goes first
+                prior_ls_batch_destroy(batch);
+                batch = nullptr;
+                batch_of.clear();
                 {
                     std::lock_guard<std::mutex> lk(mu);
-                    finish_locked(act[i].j, r == 2 ? PRIOR_LS_OK : r, destroy);
+                    for (auto& jd : done) finish_locked(jd.first, jd.second, destroy);
                 }
                 cv_done.notify_all();
-                act.erase(act.begin() + i);
             }
             for (Resident& r : destroy) destroy_resident(r);
-            if (!progress && admitted.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
     }
 };

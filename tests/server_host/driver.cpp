@@ -1,5 +1,6 @@
 // Drives the serving runtime on the CPU with stand-in library phases: 200 requests of six
-// geometries submitted from a thread, four in flight, a budget that forces evictions.
+// geometries submitted from a thread, groups of up to four of one geometry, a budget that
+// forces evictions.
 #include <cstdio>
 #include <thread>
 #include <vector>

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <vector>
 #include "prior_ls.h"
 #include "pls_runtime_api.hpp"
 using Clk = std::chrono::steady_clock;
@@ -25,6 +26,19 @@ int prior_ls_create(const prior_ls_dims* d, void* s, prior_ls_handle** out) {
 void prior_ls_destroy(prior_ls_handle* h) { if (!h) return; if (h->inflight) std::abort(); std::memset(h->pad, 0, sizeof h->pad); delete h; }
 const char* prior_ls_last_error(const prior_ls_handle* h) { return h ? "" : g_err.c_str(); }
 }
+// A batch records its handles; running it reads and writes every one of them, so a batch
+// over a destroyed handle or over a handle with a chunk in flight fails the run.
+struct prior_ls_batch { std::vector<prior_ls_handle*> hs; char pad[256]; };
+extern "C" {
+int prior_ls_batch_create(prior_ls_handle* const* hs, int32_t n, prior_ls_batch** out) {
+  if (!hs || n < 1 || !out) return -1;
+  auto* b = new prior_ls_batch(); b->hs.assign(hs, hs + n);
+  for (auto* h : b->hs) touch(h);
+  *out = b; return 0;
+}
+void prior_ls_batch_destroy(prior_ls_batch* b) { delete b; }
+const char* prior_ls_batch_last_error(const prior_ls_batch*) { return ""; }
+}
 namespace pls {
 int phase_load(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_params* p) {
   if (!in->kspace || !in->mask) return -1; touch(h); h->p = *p; h->iters = 0; return 0; }
@@ -41,4 +55,27 @@ int phase_chunk_finish(prior_ls_handle* h, int m, int* conv) {
 int phase_outputs(prior_ls_handle* h, const prior_ls_outputs*) { h->ready = Clk::now() + std::chrono::microseconds(50); return 0; }
 void phase_stats(prior_ls_handle* h, prior_ls_stats* st, int conv, double ms) { st->iters = h->iters; st->converged = conv; st->ms = ms; }
 int phase_max_iter(const prior_ls_handle* h) { return h->p.max_iter; }
+int batch_run(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& conv,
+              std::vector<int>& status, std::vector<Clk::time_point>& done_at) {
+  const size_t n = b->hs.size();
+  if (target.size() != n) std::abort();
+  conv.assign(n, 0); status.assign(n, 0); done_at.assign(n, Clk::now());
+  int most = 0;
+  for (size_t i = 0; i < n; ++i) {
+    prior_ls_handle* h = b->hs[i];
+    if (h->inflight) std::abort();
+    touch(h);
+    most = target[i] > most ? target[i] : most;
+  }
+  for (int k = 0; k < most; ++k) {
+    std::this_thread::sleep_for(std::chrono::microseconds(30));
+    for (size_t i = 0; i < n; ++i)
+      if (k < target[i]) {
+        touch(b->hs[i]);
+        ++b->hs[i]->iters;
+        if (k + 1 == target[i]) done_at[i] = Clk::now();
+      }
+  }
+  return 0;
+}
 }

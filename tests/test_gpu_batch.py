@@ -131,6 +131,30 @@ def test_batch_step_resumes_like_solve():
             assert torch.equal(outs[k][key], o1[key]), (k, key)
 
 
+def test_batch_step_from_different_iteration_counts():
+    # problems solved for 4 and 5 iterations hold their iterates at different indices; a
+    # batched step takes each from its own and equals solving for the total alone
+    name, g, J, tf = GEOMS[1]
+    ps = problems(g, J, 3, 120)
+    counts = [4, 5, 7]
+    hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J, transform=tf) for p in ps]
+    try:
+        for h, p, k in zip(hs, ps, counts):
+            t = pls.to_device(p)
+            h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], outputs=(),
+                    **params_for(p, max_iter=k, check_every=2))
+        with pls.Batch(hs) as b:
+            outs, sts = b.step(3)
+    finally:
+        for h in hs:
+            h.close()
+    for k, (p, c) in enumerate(zip(ps, counts)):
+        o1, s1 = solo(p, J, tf, max_iter=c + 3, check_every=2)
+        assert sts[k]["iters"] == c + 3
+        for key in KEYS:
+            assert torch.equal(outs[k][key], o1[key]), (k, key)
+
+
 def test_batch_rejects_mixed_geometry_and_reused_handles():
     a = pls.PriorLS(32, 32, 1, 8, 1, wavelet_levels=2)
     b = pls.PriorLS(32, 32, 1, 6, 1, wavelet_levels=2)

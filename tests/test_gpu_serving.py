@@ -116,6 +116,32 @@ def test_same_alone_and_in_a_queued_mix():
             assert torch.equal(outs[k], ref[k]), (i, k)
 
 
+def test_same_alone_and_in_a_batched_group():
+    # requests of two geometries (0, 0, 1, 0, 1, 0, 0) submitted at once with room for all:
+    # those of one geometry run together as a batched group, joining at window boundaries;
+    # each result must equal, bit for bit, the sequence served on its own
+    picks = [0, 3, 1, 6, 4, 9, 12]                  # GEOMS[i % 3]: 0, 0, 1, 0, 1, 0, 0
+    reqs = [make_request(i, n_append=1 + i % 3) for i in picks]
+    alone = []
+    for q, dims, args in reqs:
+        with pls.Server(max_active=1) as srv:
+            outs, res = srv.wait(submit(srv, dims, args))
+            assert res["status"] == pls.OK, res["message"]
+            alone.append((outs, res))
+    with pls.Server(max_active=4) as srv:
+        tickets = [submit(srv, dims, args) for _, dims, args in reqs]
+        grouped = [srv.wait(t) for t in tickets]
+        info = srv.info()
+    print("server:", info)
+    assert info["completed"] == len(reqs) and info["peak_active"] >= 2
+    for i, ((outs, res), (ref, rres)) in enumerate(zip(grouped, alone)):
+        assert res["status"] == pls.OK, res["message"]
+        for k in ("L", "S", "X", "M"):
+            assert torch.equal(outs[k], ref[k]), (i, k)
+        assert [w["iters"] for w in res["windows"]] == [w["iters"] for w in rres["windows"]]
+        assert [w["resid_norm"] for w in res["windows"]] == [w["resid_norm"] for w in rres["windows"]]
+
+
 def test_admission_respects_budget_and_reuses_plans():
     reqs = [make_request(1, n_append=1) for _ in range(4)]     # one geometry
     need = pls.plan_bytes(24, 32, 8, 7, 3)

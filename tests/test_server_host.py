@@ -1,8 +1,8 @@
 """The serving runtime's host logic (admission, budget, eviction, the dispatcher's state
-machine, ticket lifetime) built on the CPU against stand-ins of the library phases and of
-the few HIP host calls it makes, under ThreadSanitizer and AddressSanitizer: 200 requests
-of six geometries from a submitting thread, four in flight, a budget that forces queueing
-and evictions.  The stand-in chunks complete after a delay, so a read before completion,
+machine, ticket lifetime) built on the CPU against stand-ins of the library phases, of its
+batches and of the few HIP host calls it makes, under ThreadSanitizer and AddressSanitizer:
+200 requests of six geometries from a submitting thread, groups of up to four of one
+geometry, a budget that forces queueing and evictions.  The stand-in chunks complete after a delay, so a read before completion,
 two chunks in flight on one handle or a use after destroy fails the run."""
 import os
 import shutil
@@ -44,8 +44,9 @@ RT = os.path.join(HERE, "runtime_host")
 def test_runtime_and_server_host_code_under_sanitizer(tmp_path, san):
     """The library's own runtime (pls_runtime.hip) and server, host code as built for the GPU,
     against a HIP stand-in whose streams run asynchronously on threads and kernel stand-ins
-    that touch their arrays at full extent: sequences of five geometries, four in flight,
-    evictions and sample-store growth, then the synchronous API from four threads."""
+    that touch their arrays at full extent: sequences of five geometries, up to four of one
+    geometry in flight as a batched group, evictions and sample-store growth, then the
+    synchronous API from four threads and batches."""
     if shutil.which("g++") is None:
         pytest.skip("no g++")
     csrc = os.path.join(ROOT, "paper_1411_6206_amd", "csrc")
@@ -63,4 +64,6 @@ def test_runtime_and_server_host_code_under_sanitizer(tmp_path, san):
     assert r.returncode == 0
     assert "WARNING: ThreadSanitizer" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
     assert "failed 0" in r.stdout and "done: bad 0 sync_bad 0" in r.stdout
-    assert "peak_active 4" in r.stdout
+    # sequences of one geometry ran together as a batched group
+    import re
+    assert int(re.search(r"peak_active (\d+)", r.stdout).group(1)) >= 2
