@@ -497,10 +497,10 @@ def main():
     if not args.no_batching:
         out["batching"] = batching_bench(args.steps, args.warmup)
     if not args.no_serving:
-        # plain FP32 form against the split-BF16 Gram form, one sequence in flight (the
-        # server keeps concurrent sequences switched off)
+        # one sequence at a time against groups of up to 8 sequences of one geometry
+        # advanced as batches, and the split-BF16 Gram form grouped
         out["serving"] = serving_bench(args.serving_budget_gib,
-                                       forms=((1, "fp32"), (1, "bf16x3")))
+                                       forms=((1, "fp32"), (8, "fp32"), (8, "bf16x3")))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, min(args.cpu_frames, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

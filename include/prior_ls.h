@@ -308,7 +308,9 @@ void prior_ls_batch_destroy(prior_ls_batch *b);
  * (prior_ls_batch_*: one launch per kernel of an iteration for all of them), each running
  * its own window's iterations and stopping rule.  Requests join a running group at window
  * boundaries while the oldest pending request has the group's geometry; a request of
- * another geometry waits until the group drains and then starts the next group.  A request
+ * another geometry waits until the group drains and then starts the next group, which also
+ * gathers every request of its geometry already waiting (they overtake older requests of
+ * other geometries: they share that group's launches).  A request
  * is admitted when the device bytes it needs (prior_ls_plan_bytes plus the compact k-space
  * of its most sampled frame, in nt slots) fit in hbm_budget beside every resident handle.
  * Handles of finished sequences stay resident and are reused by later requests of the same

@@ -8,12 +8,13 @@
 // member running its own window's iteration count and stopping rule.  Members join a
 // running group at window boundaries while the oldest pending request has the group's
 // geometry; a request of another geometry waits until the group drains, then starts the
-// next group.  A request is admitted when the device bytes it needs fit in the budget
-// beside everything resident; handles of finished sequences stay resident (state, sample
-// store, graphs) and are reused by later requests of the same geometry, and idle ones are
-// evicted (oldest first) when an admission needs their room.  A new group starts with the
-// oldest pending request that fits, so a small request is not held behind a large one
-// waiting for memory.  Every sequence computes exactly what it computes alone.
+// next group, which also gathers every request of its geometry already waiting.  A request
+// is admitted when the device bytes it needs fit in the budget beside everything resident;
+// handles of finished sequences stay resident (state, sample store, graphs) and are reused
+// by later requests of the same geometry, and idle ones are evicted (oldest first) when an
+// admission needs their room.  A new group starts with the oldest pending request that
+// fits, so a small request is not held behind a large one waiting for memory.  Every
+// sequence computes exactly what it computes alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -143,13 +144,20 @@ struct prior_ls_server {
         return nullptr;
     }
 
-    // The oldest pending job if it has geometry `d` and fits; nullptr otherwise.
-    Job* admit_same_locked(const prior_ls_dims& d, std::vector<Resident>& evict) {
-        if (pending.empty() || !same_dims(pending.front()->req.dims, d)) return nullptr;
-        if (!reserve_locked(pending.front(), evict)) return nullptr;
-        Job* j = pending.front();
-        pending.pop_front();
-        return j;
+    // A pending job of geometry `d` that fits: with `oldest_only` only the oldest pending job
+    // qualifies (a running group does not overtake older requests of other geometries),
+    // else the oldest of that geometry (a group being formed gathers what waits for it).
+    Job* admit_same_locked(const prior_ls_dims& d, bool oldest_only, std::vector<Resident>& evict) {
+        for (auto it = pending.begin(); it != pending.end(); ++it) {
+            if (same_dims((*it)->req.dims, d)) {
+                if (!reserve_locked(*it, evict)) return nullptr;
+                Job* j = *it;
+                pending.erase(it);
+                return j;
+            }
+            if (oldest_only) return nullptr;
+        }
+        return nullptr;
     }
 
     // Reserves job j's device bytes: an idle handle of its geometry (grown if its sample
@@ -423,12 +431,13 @@ struct prior_ls_server {
             {
                 std::unique_lock<std::mutex> lk(mu);
                 for (;;) {
-                    // a new group takes the oldest pending request that fits; a running one
-                    // takes more requests of its geometry while the oldest is one of them
+                    // a new group takes the oldest pending request that fits and every
+                    // waiting request of its geometry; a running one takes more requests of
+                    // its geometry while the oldest pending request is one of them
                     while ((int)(group.size() + admitted.size()) < in_flight) {
                         Job* j;
-                        if (!group.empty()) j = admit_same_locked(group[0].j->req.dims, evict);
-                        else if (!admitted.empty()) j = admit_same_locked(admitted[0]->req.dims, evict);
+                        if (!group.empty()) j = admit_same_locked(group[0].j->req.dims, true, evict);
+                        else if (!admitted.empty()) j = admit_same_locked(admitted[0]->req.dims, false, evict);
                         else j = admit_locked(evict);
                         if (!j) break;
                         j->admitted = Clock::now();
