@@ -62,10 +62,9 @@ def test_served_sequence_matches_oracle():
     assert [w["iters"] for w in res["windows"]] == [K0] + [K1] * 3
 
 
-@pytest.mark.skip(reason="concurrent sequences are switched off: a full-size run with four "
-                         "sequences in flight ended in a host segmentation fault whose cause "
-                         "was not found; with one in flight the mix is sequential")
 def test_same_alone_and_in_the_mix():
+    # (sequences are no longer driven independently on streams of their own; with
+    # max_active = 4 the server runs groups of one geometry as batches)
     reqs = [make_request(i, n_append=2 + i % 3) for i in range(6)]
     alone = []
     with pls.Server(max_active=1) as srv:
@@ -73,7 +72,8 @@ def test_same_alone_and_in_the_mix():
             outs, res = srv.wait(submit(srv, dims, args))
             assert res["status"] == pls.OK, res["message"]
             alone.append(outs)
-    # all at once: four in flight, with a budget that forces some to queue
+    # all at once: groups of up to four of one geometry, with a budget that forces some
+    # to queue
     needs = sorted(pls.plan_bytes(q.nx, q.ny, q.nz, q.nt, q.nc) for q, _, _ in reqs)
     budget = int(sum(needs[-2:]) * 1.5)
     with pls.Server(max_active=4, hbm_budget=budget) as srv:
