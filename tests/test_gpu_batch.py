@@ -23,6 +23,7 @@ GEOMS = [
     ("2d_32x32_nt8_nc1", dict(nx=32, ny=32, nz=1, nt=8, nc=1), 2, "haar"),
     ("3d_32x48x8_nt12_nc3", dict(nx=32, ny=48, nz=8, nt=12, nc=3), 2, "haar"),
     ("3d_24x24x4_nt20_nc2_tfft", dict(nx=24, ny=24, nz=4, nt=20, nc=2), 1, "tfft"),
+    ("3d_16x32x14_nt6_nc2", dict(nx=16, ny=32, nz=14, nt=6, nc=2), 1, "haar"),
 ]
 
 
@@ -85,6 +86,26 @@ def test_batch_equals_each_problem_alone_and_the_oracle(geom):
     for key in KEYS:
         e = rel(host(outs[0][key]), r[key])
         assert e < TOL, (key, e)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_batch_gram_modes_equal_each_problem_alone(mode):
+    name, g, J, tf = GEOMS[1]
+    ps = problems(g, J, 2, 140)
+    hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J, gram_mode=mode) for p in ps]
+    try:
+        with pls.Batch(hs) as b:
+            prm = [pls.make_params(**params_for(p)) for p in ps]
+            outs, sts = b.solve([pls.to_device(p) for p in ps], prm)
+    finally:
+        for h in hs:
+            h.close()
+    for k, p in enumerate(ps):
+        with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J, gram_mode=mode) as h:
+            t = pls.to_device(p)
+            o1, s1 = h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], **params_for(p))
+        for key in KEYS:
+            assert torch.equal(outs[k][key], o1[key]), (mode, k, key)
 
 
 def test_batch_stops_each_problem_where_it_stops_alone():
