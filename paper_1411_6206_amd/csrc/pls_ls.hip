@@ -436,13 +436,34 @@ __global__ void __launch_bounds__(NTH) pls_stats_kernel(SRC src) {
     if (src.skip()) return;
     const StatsArgs a = src.get();
     __shared__ double red[4];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int b = threadIdx.x; b < a.dc_blocks; b += 256) {
-        s0 += a.dc_part[4 * b + 0];
-        s1 += a.dc_part[4 * b + 1];
-        s2 += a.dc_part[4 * b + 2];
+    // each thread sums its partials b = tid + 256 m in four interleaved accumulators (m mod
+    // 4, so four loads are in flight) added in a fixed order
+    double p0[4] = {0.0, 0.0, 0.0, 0.0}, p1[4] = {0.0, 0.0, 0.0, 0.0};
+    double p2[4] = {0.0, 0.0, 0.0, 0.0}, p3[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = threadIdx.x;
+    for (; b + 3 * 256 < a.dc_blocks; b += 4 * 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double* q = a.dc_part + 4 * (b + 256 * k);
+            p0[k] += q[0];
+            p1[k] += q[1];
+            p2[k] += q[2];
+        }
     }
-    for (int b = threadIdx.x; b < a.sp_blocks; b += 256) s3 += a.sp_part[b];
+    for (int k = 0; b < a.dc_blocks; b += 256, ++k) {
+        const double* q = a.dc_part + 4 * b;
+        p0[k] += q[0];
+        p1[k] += q[1];
+        p2[k] += q[2];
+    }
+    b = threadIdx.x;
+    for (; b + 3 * 256 < a.sp_blocks; b += 4 * 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) p3[k] += a.sp_part[b + 256 * k];
+    }
+    for (int k = 0; b < a.sp_blocks; b += 256, ++k) p3[k] += a.sp_part[b];
+    double s0 = (p0[0] + p0[1]) + (p0[2] + p0[3]), s1 = (p1[0] + p1[1]) + (p1[2] + p1[3]);
+    double s2 = (p2[0] + p2[1]) + (p2[2] + p2[3]), s3 = (p3[0] + p3[1]) + (p3[2] + p3[3]);
     s0 = block_sum<256>(s0, red);
     s1 = block_sum<256>(s1, red);
     s2 = block_sum<256>(s2, red);
