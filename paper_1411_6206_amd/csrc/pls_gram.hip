@@ -554,57 +554,91 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // D = J^H S J on every 2x2 block; J = [[cs, sn e], [-sn conj(e), cs]]
-            // one pass: items [0, half^2) update A, items [half^2, half^2 + ne half) update V
-            for (int it = tid; it < half * half + ne * half; it += NT) {
-                if (it < half * half) {
-                    const int idx = it;
-                    const int al = idx / half, be = idx % half;
-                    int p, q, u, w;
-                    rr_pair(ne, r, al, p, q);
-                    rr_pair(ne, r, be, u, w);
-                    const double c1 = rc[wv][al], s1 = rs[wv][al], e1r = rer[wv][al], e1i = rei[wv][al];
-                    const double c2 = rc[wv][be], s2 = rs[wv][be], e2r = rer[wv][be], e2i = rei[wv][be];
-                    const double b00r = Sr[p][u], b00i = Si[p][u], b01r = Sr[p][w], b01i = Si[p][w];
-                    const double b10r = Sr[q][u], b10i = Si[q][u], b11r = Sr[q][w], b11i = Si[q][w];
-                    // X = J1^H B, J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
-                    const double x00r = c1 * b00r - s1 * (e1r * b10r - e1i * b10i);
-                    const double x00i = c1 * b00i - s1 * (e1r * b10i + e1i * b10r);
-                    const double x01r = c1 * b01r - s1 * (e1r * b11r - e1i * b11i);
-                    const double x01i = c1 * b01i - s1 * (e1r * b11i + e1i * b11r);
-                    const double x10r = s1 * (e1r * b00r + e1i * b00i) + c1 * b10r;
-                    const double x10i = s1 * (e1r * b00i - e1i * b00r) + c1 * b10i;
-                    const double x11r = s1 * (e1r * b01r + e1i * b01i) + c1 * b11r;
-                    const double x11i = s1 * (e1r * b01i - e1i * b01r) + c1 * b11i;
-                    // Y = X J2: Y[:,0] = X[:,0] c2 - X[:,1] s2 conj(e2); Y[:,1] = X[:,0] s2 e2 + X[:,1] c2
-                    double y00r = c2 * x00r - s2 * (x01r * e2r + x01i * e2i);
-                    double y00i = c2 * x00i - s2 * (x01i * e2r - x01r * e2i);
-                    double y10r = c2 * x10r - s2 * (x11r * e2r + x11i * e2i);
-                    double y10i = c2 * x10i - s2 * (x11i * e2r - x11r * e2i);
-                    double y01r = s2 * (x00r * e2r - x00i * e2i) + c2 * x01r;
-                    double y01i = s2 * (x00r * e2i + x00i * e2r) + c2 * x01i;
-                    double y11r = s2 * (x10r * e2r - x10i * e2i) + c2 * x11r;
-                    double y11i = s2 * (x10r * e2i + x10i * e2r) + c2 * x11i;
-                    if (al == be) {
-                        y01r = y01i = y10r = y10i = 0.0;
-                        y00i = y11i = 0.0;
-                    }
-                    Dr[p][u] = y00r; Di[p][u] = y00i;
-                    Dr[p][w] = y01r; Di[p][w] = y01i;
-                    Dr[q][u] = y10r; Di[q][u] = y10i;
-                    Dr[q][w] = y11r; Di[q][w] = y11i;
-                } else {
-                    // V <- V J
-                    const int idx = it - half * half;
-                    const int i = idx / half, be = idx % half;
-                    int u, w;
-                    rr_pair(ne, r, be, u, w);
-                    const double c2 = rc[wv][be], s2 = rs[wv][be], e2r = rer[wv][be], e2i = rei[wv][be];
-                    const double v0r = Vr[i][u], v0i = Vi[i][u], v1r = Vr[i][w], v1i = Vi[i][w];
-                    Vr[i][u] = c2 * v0r - s2 * (v1r * e2r + v1i * e2i);
-                    Vi[i][u] = c2 * v0i - s2 * (v1i * e2r - v1r * e2i);
-                    Vr[i][w] = s2 * (v0r * e2r - v0i * e2i) + c2 * v1r;
-                    Vi[i][w] = s2 * (v0r * e2i + v0i * e2r) + c2 * v1i;
+            // D = J^H S J on every 2x2 block; J = [[cs, sn e], [-sn conj(e), cs]].  An A item
+            // (al, be) < (half, half) rotates one 2x2 block of S into D; a V item (i, be)
+            // rotates two entries of row i of V in place.  Each item's reads come first and
+            // its writes last, so the caller can interleave two items.
+            struct AItem {
+                int p, q, u, w;
+                bool diag;
+                double c1, s1, e1r, e1i, c2, s2, e2r, e2i;
+                double b00r, b00i, b01r, b01i, b10r, b10i, b11r, b11i;
+            };
+            struct VItem {
+                int i, u, w;
+                double c2, s2, e2r, e2i, v0r, v0i, v1r, v1i;
+            };
+            auto a_load = [&](int idx) __attribute__((always_inline)) {
+                AItem x;
+                const int al = idx / half, be = idx % half;
+                rr_pair(ne, r, al, x.p, x.q);
+                rr_pair(ne, r, be, x.u, x.w);
+                x.diag = al == be;
+                x.c1 = rc[wv][al]; x.s1 = rs[wv][al]; x.e1r = rer[wv][al]; x.e1i = rei[wv][al];
+                x.c2 = rc[wv][be]; x.s2 = rs[wv][be]; x.e2r = rer[wv][be]; x.e2i = rei[wv][be];
+                x.b00r = Sr[x.p][x.u]; x.b00i = Si[x.p][x.u]; x.b01r = Sr[x.p][x.w]; x.b01i = Si[x.p][x.w];
+                x.b10r = Sr[x.q][x.u]; x.b10i = Si[x.q][x.u]; x.b11r = Sr[x.q][x.w]; x.b11i = Si[x.q][x.w];
+                return x;
+            };
+            auto a_finish = [&](const AItem& x) __attribute__((always_inline)) {
+                const double c1 = x.c1, s1 = x.s1, e1r = x.e1r, e1i = x.e1i;
+                const double c2 = x.c2, s2 = x.s2, e2r = x.e2r, e2i = x.e2i;
+                // X = J1^H B, J1^H = [[c1, -s1 e1], [s1 conj(e1), c1]]
+                const double x00r = c1 * x.b00r - s1 * (e1r * x.b10r - e1i * x.b10i);
+                const double x00i = c1 * x.b00i - s1 * (e1r * x.b10i + e1i * x.b10r);
+                const double x01r = c1 * x.b01r - s1 * (e1r * x.b11r - e1i * x.b11i);
+                const double x01i = c1 * x.b01i - s1 * (e1r * x.b11i + e1i * x.b11r);
+                const double x10r = s1 * (e1r * x.b00r + e1i * x.b00i) + c1 * x.b10r;
+                const double x10i = s1 * (e1r * x.b00i - e1i * x.b00r) + c1 * x.b10i;
+                const double x11r = s1 * (e1r * x.b01r + e1i * x.b01i) + c1 * x.b11r;
+                const double x11i = s1 * (e1r * x.b01i - e1i * x.b01r) + c1 * x.b11i;
+                // Y = X J2: Y[:,0] = X[:,0] c2 - X[:,1] s2 conj(e2); Y[:,1] = X[:,0] s2 e2 + X[:,1] c2
+                double y00r = c2 * x00r - s2 * (x01r * e2r + x01i * e2i);
+                double y00i = c2 * x00i - s2 * (x01i * e2r - x01r * e2i);
+                double y10r = c2 * x10r - s2 * (x11r * e2r + x11i * e2i);
+                double y10i = c2 * x10i - s2 * (x11i * e2r - x11r * e2i);
+                double y01r = s2 * (x00r * e2r - x00i * e2i) + c2 * x01r;
+                double y01i = s2 * (x00r * e2i + x00i * e2r) + c2 * x01i;
+                double y11r = s2 * (x10r * e2r - x10i * e2i) + c2 * x11r;
+                double y11i = s2 * (x10r * e2i + x10i * e2r) + c2 * x11i;
+                if (x.diag) {
+                    y01r = y01i = y10r = y10i = 0.0;
+                    y00i = y11i = 0.0;
+                }
+                Dr[x.p][x.u] = y00r; Di[x.p][x.u] = y00i;
+                Dr[x.p][x.w] = y01r; Di[x.p][x.w] = y01i;
+                Dr[x.q][x.u] = y10r; Di[x.q][x.u] = y10i;
+                Dr[x.q][x.w] = y11r; Di[x.q][x.w] = y11i;
+            };
+            auto v_load = [&](int idx) __attribute__((always_inline)) {
+                VItem x;
+                x.i = idx / half;
+                const int be = idx % half;
+                rr_pair(ne, r, be, x.u, x.w);
+                x.c2 = rc[wv][be]; x.s2 = rs[wv][be]; x.e2r = rer[wv][be]; x.e2i = rei[wv][be];
+                x.v0r = Vr[x.i][x.u]; x.v0i = Vi[x.i][x.u]; x.v1r = Vr[x.i][x.w]; x.v1i = Vi[x.i][x.w];
+                return x;
+            };
+            // V <- V J
+            auto v_finish = [&](const VItem& x) __attribute__((always_inline)) {
+                Vr[x.i][x.u] = x.c2 * x.v0r - x.s2 * (x.v1r * x.e2r + x.v1i * x.e2i);
+                Vi[x.i][x.u] = x.c2 * x.v0i - x.s2 * (x.v1i * x.e2r - x.v1r * x.e2i);
+                Vr[x.i][x.w] = x.s2 * (x.v0r * x.e2r - x.v0i * x.e2i) + x.c2 * x.v1r;
+                Vi[x.i][x.w] = x.s2 * (x.v0r * x.e2i + x.v0i * x.e2r) + x.c2 * x.v1i;
+            };
+            if constexpr (NT >= kNMax * kNMax / 2) {
+                // every thread takes at most one A item (half^2 <= 256) and one V item
+                // (ne half <= 512), both loaded before either is written (absent items load
+                // item 0 and write nothing), so their LDS reads overlap
+                const bool has_a = tid < half * half, has_v = tid < ne * half;
+                const AItem xa = a_load(has_a ? tid : 0);
+                const VItem xv = v_load(has_v ? tid : 0);
+                if (has_a) a_finish(xa);
+                if (has_v) v_finish(xv);
+            } else {
+                for (int it = tid; it < half * half + ne * half; it += NT) {
+                    if (it < half * half) a_finish(a_load(it));
+                    else v_finish(v_load(it - half * half));
                 }
             }
             // every entry of D was written (the pairs partition the indices); the next round
