@@ -198,17 +198,20 @@ typedef struct {
     int32_t sparse_fork;        /* 0: the sparse update runs beside the reduction / eigensolve
                                    / back-projection (forked after the Gram pass); 1: beside
                                    the whole chain (forked before the Gram pass) */
-    int32_t reserved;           /* must be 0 */
+    int32_t sparse_grid;        /* Haar sparse update: workgroups at most, each looping over
+                                   tiles (fewer leave more bandwidth to the chain it runs
+                                   beside): 0 (one per tile) or 64..65536 */
     double  ms_per_iteration;   /* prior_ls_tune: measured time per iteration of the choice */
 } prior_ls_tuning;
 
 /* Autotuner.  Loads the problem as prior_ls_solve does, then times params->check_every
  * iterations (replayed as a hipGraph chunk, after one untimed chunk) for candidate launch
- * shapes and schedules: the sparse fork point, the Gram split (256 ... 2048 blocks) and the
- * back-projection grid (1024 ... 8192), one knob at a time starting from the current
- * choice.  It reloads the problem before each trial and at the end, so the handle is left
- * exactly as prior_ls_solve(max_iter = 0) leaves it, with the fastest choice applied;
- * *best (may be NULL) receives it.  Errors as for prior_ls_solve. */
+ * shapes and schedules: the sparse fork point, the Gram split (256 ... 2048 blocks), the
+ * back-projection grid (1024 ... 8192) and, with the Haar transform, the sparse-update grid
+ * (256 ... 2048), one knob at a time starting from the current choice.  It reloads the
+ * problem before each trial and at the end, so the handle is left exactly as
+ * prior_ls_solve(max_iter = 0) leaves it, with the fastest choice applied; *best (may be
+ * NULL) receives it.  Errors as for prior_ls_solve. */
 int prior_ls_tune(prior_ls_handle *h, const prior_ls_inputs *in, const prior_ls_params *params,
                   prior_ls_tuning *best);
 

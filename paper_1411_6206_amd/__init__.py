@@ -90,12 +90,12 @@ class Stats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("gram_blocks", C.c_int32), ("bp_grid", C.c_int32),
-                ("sparse_fork", C.c_int32), ("reserved", C.c_int32),
+                ("sparse_fork", C.c_int32), ("sparse_grid", C.c_int32),
                 ("ms_per_iteration", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_
-                if k not in ("struct_size", "reserved")}
+                if k not in ("struct_size",)}
 
 
 class ServerConfig(C.Structure):
@@ -313,7 +313,8 @@ class PriorLS:
                 book = json.load(fh)
         if key in book:
             t = Tuning(C.sizeof(Tuning), int(book[key]["gram_blocks"]), int(book[key]["bp_grid"]),
-                       int(book[key]["sparse_fork"]), 0, float(book[key]["ms_per_iteration"]))
+                       int(book[key]["sparse_fork"]), int(book[key].get("sparse_grid", 0)),
+                       float(book[key]["ms_per_iteration"]))
             self._check(lib().prior_ls_set_tuning(self._h, C.byref(t)), "prior_ls_set_tuning")
             self.solve(kspace, mask, sens, prior_w, sigma_prev, lambda_L=lambda_L,
                        lambda_S=lambda_S, lambda_p=lambda_p, lambda_L_relative=lambda_L_relative,
@@ -338,8 +339,9 @@ class PriorLS:
                 json.dump(book, fh, indent=1)
         return dict(t.as_dict(), cached=False)
 
-    def set_tuning(self, gram_blocks=0, bp_grid=0, sparse_fork=0):
-        t = Tuning(C.sizeof(Tuning), int(gram_blocks), int(bp_grid), int(sparse_fork), 0, 0.0)
+    def set_tuning(self, gram_blocks=0, bp_grid=0, sparse_fork=0, sparse_grid=0):
+        t = Tuning(C.sizeof(Tuning), int(gram_blocks), int(bp_grid), int(sparse_fork),
+                   int(sparse_grid), 0.0)
         self._check(lib().prior_ls_set_tuning(self._h, C.byref(t)), "prior_ls_set_tuning")
 
     def get_tuning(self):

@@ -120,9 +120,13 @@ struct SparseArgs {
     float lambda_S;
     const float* Wf;       // temporal transform only: MFMA operands of the forward DFT and
     const float* Wi;       // of the inverse (its columns in the forward's output order)
+    int max_grid;          // Haar transform: workgroups at most, each looping over tiles
+                           // (0 = one per tile)
 };
 // returns number of blocks
 int launch_sparse(int levels, const SparseArgs& a, hipStream_t s);
+// workgroups (= partial sums) of the Haar sparse update for a max_grid cap
+int sparse_haar_blocks(int levels, int nx, int ny, int nz, int nt, int max_grid);
 int launch_sparse_tfft(const SparseArgs& a, hipStream_t s);
 int sparse_tfft_blocks(int N);
 

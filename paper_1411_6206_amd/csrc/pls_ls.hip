@@ -183,72 +183,81 @@ __global__ void __launch_bounds__(256) pls_sparse_kernel(SRC src) {
     const int yl = lane % YW, zl = lane / YW;
     const int nyt = (a.ny + 4 * YW - 1) / (4 * YW);
     const int nzt = a.nz / ZW;
-    int tile = blockIdx.x;
-    const int yt = tile % nyt;
-    tile /= nyt;
-    const int zt = tile % nzt;
-    const int xt = tile / nzt;
-    const int t = blockIdx.y;
-    const int y = yt * 4 * YW + wave * YW + yl;
-    const int z = zt * ZW + zl;
-    const bool valid = y < a.ny;
-    // Every lane loads from a valid address (y clamped into the volume, absent arrays
-    // replaced by C) and discards with selects, so the loads of all XW rows and all arrays
-    // are in flight together.
-    const int yc = valid ? y : a.ny - 1;
+    const int tiles = nyt * nzt * (a.nx / B);
     const bool has_s = a.S != nullptr, has_w = a.w != nullptr;
     const float2* Sp = has_s ? a.S : a.C;
     const uint8_t* wp = has_w ? a.w : reinterpret_cast<const uint8_t*>(a.C);
-    float2 v[XW], sv[XW], lv[XW];
-    int gi[XW];
-    uint8_t wq[XW];
-#pragma unroll
-    for (int k = 0; k < XW; ++k) {
-        gi[k] = ((t * a.nx + xt * XW + k) * a.nz + z) * a.ny + yc;
-        v[k] = a.C[gi[k]];
-        sv[k] = Sp[gi[k]];
-        lv[k] = a.Lp[gi[k]];
-        wq[k] = wp[gi[k]];
-    }
-#pragma unroll
-    for (int k = 0; k < XW; ++k) {
-        const float2 u = has_s ? cadd(v[k], sv[k]) : v[k];
-        v[k] = valid ? csub(u, lv[k]) : make_float2(0.f, 0.f);
-    }
-    for (int l = 0; l < J; ++l) haar_level<J, ZA>(v, l, yl, zl, lane);
     float l1 = 0.f;
+    // work item = (frame t, tile); a workgroup takes items blockIdx.x, + gridDim.x, ...
+    for (int item = blockIdx.x; item < tiles * a.nt; item += gridDim.x) {
+        int tile = item % tiles;
+        const int t = item / tiles;
+        const int yt = tile % nyt;
+        tile /= nyt;
+        const int zt = tile % nzt;
+        const int xt = tile / nzt;
+        const int y = yt * 4 * YW + wave * YW + yl;
+        const int z = zt * ZW + zl;
+        const bool valid = y < a.ny;
+        // Every lane loads from a valid address (y clamped into the volume, absent arrays
+        // replaced by C) and discards with selects, so the loads of all XW rows and all
+        // arrays are in flight together.
+        const int yc = valid ? y : a.ny - 1;
+        float2 v[XW], sv[XW], lv[XW];
+        int gi[XW];
+        uint8_t wq[XW];
 #pragma unroll
-    for (int k = 0; k < XW; ++k) {
-        // soft threshold of the complex magnitude: u (1 - tau / |u|) where |u| > tau
-        const float wk = has_w ? (float)wq[k] * (1.0f / 255.0f) : 0.0f;
-        const float tau = a.lambda_S * (1.0f - wk);
-        const float2 u = v[k];
-        const float m2 = fmaf(u.x, u.x, u.y * u.y);
-        const bool keep = valid && m2 > tau * tau;
-        const float rm = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
-        const float sc = fmaf(-tau, rm, 1.0f);
-        v[k] = keep ? make_float2(u.x * sc, u.y * sc) : make_float2(0.f, 0.f);
-        l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
-        if (a.supp && valid) a.supp[gi[k]] = keep ? 255 : 0;
-    }
-    for (int l = J - 1; l >= 0; --l) haar_level<J, ZA>(v, l, yl, zl, lane);
-    if (valid) {
+        for (int k = 0; k < XW; ++k) {
+            gi[k] = ((t * a.nx + xt * XW + k) * a.nz + z) * a.ny + yc;
+            v[k] = a.C[gi[k]];
+            sv[k] = Sp[gi[k]];
+            lv[k] = a.Lp[gi[k]];
+            wq[k] = wp[gi[k]];
+        }
 #pragma unroll
-        for (int k = 0; k < XW; ++k) a.Sout[gi[k]] = v[k];
+        for (int k = 0; k < XW; ++k) {
+            const float2 u = has_s ? cadd(v[k], sv[k]) : v[k];
+            v[k] = valid ? csub(u, lv[k]) : make_float2(0.f, 0.f);
+        }
+        for (int l = 0; l < J; ++l) haar_level<J, ZA>(v, l, yl, zl, lane);
+#pragma unroll
+        for (int k = 0; k < XW; ++k) {
+            // soft threshold of the complex magnitude: u (1 - tau / |u|) where |u| > tau
+            const float wk = has_w ? (float)wq[k] * (1.0f / 255.0f) : 0.0f;
+            const float tau = a.lambda_S * (1.0f - wk);
+            const float2 u = v[k];
+            const float m2 = fmaf(u.x, u.x, u.y * u.y);
+            const bool keep = valid && m2 > tau * tau;
+            const float rm = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
+            const float sc = fmaf(-tau, rm, 1.0f);
+            v[k] = keep ? make_float2(u.x * sc, u.y * sc) : make_float2(0.f, 0.f);
+            l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
+            if (a.supp && valid) a.supp[gi[k]] = keep ? 255 : 0;
+        }
+        for (int l = J - 1; l >= 0; --l) haar_level<J, ZA>(v, l, yl, zl, lane);
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < XW; ++k) a.Sout[gi[k]] = v[k];
+        }
     }
     const double s = block_sum<256>((double)l1, red);
-    if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) a.part[blockIdx.x] = s;
+}
+
+int sparse_haar_blocks(int levels, int nx, int ny, int nz, int nt, int max_grid) {
+    const int B = 1 << levels;
+    const int ZW = nz > 1 ? B : 1;
+    const int YW = 64 / ZW;
+    const int nyt = (ny + 4 * YW - 1) / (4 * YW);
+    const int items = nyt * (nz / ZW) * (nx / B) * nt;
+    return (max_grid > 0 && max_grid < items) ? max_grid : items;
 }
 
 template <int J, bool ZA>
 static int sparse_launch_t(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
-    constexpr int B = 1 << J;
-    constexpr int ZW = ZA ? B : 1;
-    constexpr int YW = 64 / ZW;
-    const int nyt = (a.ny + 4 * YW - 1) / (4 * YW);
-    const int tiles = nyt * (a.nz / ZW) * (a.nx / B);
-    PLS_LAUNCH(dim3(tiles, a.nt), dim3(256), s, a, bt, pls_sparse_kernel, J, ZA);
-    return tiles * a.nt;
+    const int grid = sparse_haar_blocks(J, a.nx, a.ny, a.nz, a.nt, a.max_grid);
+    PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_sparse_kernel, J, ZA);
+    return grid;
 }
 
 int launch_sparse_batched(int levels, const SparseArgs& a, const Batched<SparseArgs>* bt,

@@ -109,6 +109,13 @@ struct Sizes {
     int gblocks, gentries, dcb, spb;
 };
 
+// Workgroups (= partial sums) of one sparse update under a tuning.
+int sparse_launch_blocks(const prior_ls_dims& d, const prior_ls_tuning& t) {
+    if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz);
+    return pls::sparse_haar_blocks(d.wavelet_levels, d.nx, d.ny, d.nz, d.nt, t.sparse_grid);
+}
+
+// Workgroups of the sparse update at most (any tuning): the size of its partial sums.
 int sparse_blocks(const prior_ls_dims& d) {
     if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz);
     const int J = d.wavelet_levels;
@@ -350,6 +357,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     mark(6, s2);
     sa.Wf = h->Wtf;
     sa.Wi = h->Wti;
+    sa.max_grid = h->tuning.sparse_grid;
     const int spb = launch_sparse_any(h, sa, s2);
     mark(7, s2);
     PLS_HIP(hipEventRecord(h->ev_join, s2));
@@ -805,7 +813,8 @@ int check_tuning(prior_ls_handle* h, const prior_ls_tuning* t) {
     if (t->bp_grid != 0 && (t->bp_grid < 64 || t->bp_grid > 65536))
         return fail(h, PRIOR_LS_EINVAL, "bp_grid must be 0 or in [64, 65536]");
     if (t->sparse_fork != 0 && t->sparse_fork != 1) return fail(h, PRIOR_LS_EINVAL, "sparse_fork must be 0 or 1");
-    if (t->reserved != 0) return fail(h, PRIOR_LS_EINVAL, "tuning.reserved must be 0");
+    if (t->sparse_grid != 0 && (t->sparse_grid < 64 || t->sparse_grid > 65536))
+        return fail(h, PRIOR_LS_EINVAL, "sparse_grid must be 0 or in [64, 65536]");
     return PRIOR_LS_OK;
 }
 
@@ -1086,6 +1095,8 @@ int prior_ls_tune(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_
         const int forks[] = {0, 1};
         const int grams[] = {256, 512, 1024, 2048};
         const int grids[] = {1024, 2048, 4096, 8192};
+        // fewer sparse-update workgroups leave more bandwidth to the chain it runs beside
+        const int sgrids[] = {256, 512, 1024, 2048};
         auto trial = [&](prior_ls_tuning t) {
             h->tuning = t;
             h->clear_graphs();
@@ -1110,6 +1121,12 @@ int prior_ls_tune(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_
             t.bp_grid = v;
             if (v != cur.bp_grid) trial(t);
         }
+        if (h->d.transform == PRIOR_LS_T_HAAR)
+            for (int v : sgrids) {
+                prior_ls_tuning t = cur;
+                t.sparse_grid = v;
+                if (v != cur.sparse_grid) trial(t);
+            }
         cur.ms_per_iteration = best_ms;
         h->tuning = cur;
         h->clear_graphs();
@@ -1442,14 +1459,15 @@ void batch_upload_args(prior_ls_batch* b) {
             sa.lambda_S = (float)h->params.lambda_S;
             sa.Wf = h->Wtf;
             sa.Wi = h->Wti;
+            sa.max_grid = b->tuning.sparse_grid;
             barr<pls::SparseArgs>(b, b->host, 4, ph)[i] = sa;
             DcArgs da = dc_args(h, h->L[q], h->S[q], h->C);
             da.Lold = h->L[p];
             da.Sold = h->S[p];
             barr<DcArgs>(b, b->host, 5, ph)[i] = da;
             barr<pls::StatsArgs>(b, b->host, 6, ph)[i] =
-                pls::StatsArgs{h->dc_part, sz.dcb, h->sp_part, sz.spb, h->stats_d, (double)sz.P,
-                               h->params.lambda_S};
+                pls::StatsArgs{h->dc_part, sz.dcb, h->sp_part, sparse_launch_blocks(d, b->tuning),
+                               h->stats_d, (double)sz.P, h->params.lambda_S};
         }
     }
     PLS_HIP(hipMemcpyAsync(b->dev, b->host, b->off[7], hipMemcpyHostToDevice, b->stream));

@@ -172,10 +172,14 @@ void launch_bp(const BpArgs& a, hipStream_t s) {
         work_us(20);
     });
 }
+int sparse_haar_blocks(int levels, int nx, int ny, int nz, int nt, int max_grid) {
+    const int B = 1 << levels, ZW = nz > 1 ? B : 1, YW = 64 / ZW;
+    const int items = ((ny + 4 * YW - 1) / (4 * YW)) * (nz / ZW) * (nx / B) * nt;
+    return (max_grid > 0 && max_grid < items) ? max_grid : items;
+}
 int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
     SparseArgs c = a;
-    const int B = 1 << levels, ZW = c.nz > 1 ? B : 1, YW = 64 / ZW;
-    const int blocks = ((c.ny + 4 * YW - 1) / (4 * YW)) * (c.nz / ZW) * (c.nx / B) * c.nt;
+    const int blocks = sparse_haar_blocks(levels, c.nx, c.ny, c.nz, c.nt, c.max_grid);
     fh_stream(s)->push([c, blocks] {
         const size_t I = (size_t)c.nx * c.ny * c.nz * c.nt;
         look(c.C, I);

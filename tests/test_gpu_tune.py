@@ -42,7 +42,8 @@ def test_tune_then_step_matches_oracle_and_manual_tuning(tmp_path):
         assert e < 1e-4, (key, e)
     # the same choice set by hand, then a plain solve: identical to tune + step
     with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=2) as h2:
-        h2.set_tuning(choice["gram_blocks"], choice["bp_grid"], choice["sparse_fork"])
+        h2.set_tuning(choice["gram_blocks"], choice["bp_grid"], choice["sparse_fork"],
+                      choice["sparse_grid"])
         out2, _ = h2.solve(k, m, s, w, lambda_L=p.lambda_L, lambda_S=p.lambda_S, max_iter=K,
                            check_every=4)
     for key in ("L", "S", "X", "M"):
@@ -57,7 +58,8 @@ def test_tune_then_step_matches_oracle_and_manual_tuning(tmp_path):
     assert len(json.load(open(cache))) == 1
 
 
-@pytest.mark.parametrize("t", [dict(gram_blocks=8), dict(bp_grid=3), dict(sparse_fork=2)])
+@pytest.mark.parametrize("t", [dict(gram_blocks=8), dict(bp_grid=3), dict(sparse_fork=2),
+                               dict(sparse_grid=3)])
 def test_set_tuning_rejects_out_of_range(t):
     with pls.PriorLS(16, 16, 4, 6, 2) as h:
         with pytest.raises(pls.PriorLSError) as e:
@@ -69,8 +71,8 @@ def test_every_choice_agrees_to_rounding():
     p = synth.small(nx=24, ny=32, nz=8, nt=7, nc=2, seed=32)
     k, m, s, w = _inputs(p)
     outs = []
-    for t in (dict(), dict(gram_blocks=64, bp_grid=64, sparse_fork=1),
-              dict(gram_blocks=2048, bp_grid=8192, sparse_fork=0)):
+    for t in (dict(), dict(gram_blocks=64, bp_grid=64, sparse_fork=1, sparse_grid=64),
+              dict(gram_blocks=2048, bp_grid=8192, sparse_fork=0, sparse_grid=1024)):
         with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc) as h:
             h.set_tuning(**t)
             o, _ = h.solve(k, m, s, w, lambda_L=p.lambda_L, lambda_S=p.lambda_S, max_iter=10)
