@@ -296,7 +296,7 @@ def main():
                     help="skip the batched small-configuration measurements")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the iteration shards by x-plane with one Gram all-reduce per iteration; not built)",
               file=sys.stderr)
         sys.exit(2)
