@@ -294,6 +294,9 @@ def main():
     ap.add_argument("--serving-budget-gib", type=float, default=48.0)
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batched small-configuration measurements")
+    ap.add_argument("--no-alone", action="store_true",
+                    help="skip the per-kernel timing with every kernel alone")
+    ap.add_argument("--alone-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -364,6 +367,25 @@ def main():
     print(f"[bench] timed {args.steps} iterations: {value:.1f} it/s; solve latency done",
           file=sys.stderr, flush=True)
 
+    # every kernel alone: the same iterations with the sparse update on the main stream and
+    # one workgroup per tile (outside the timed region; the tuned schedule is restored)
+    alone = {}
+    if not args.no_alone:
+        tuned = h.get_tuning()
+        h.set_tuning(tuned["gram_blocks"], tuned["bp_grid"], 2, 0)
+        h.step(2)
+        ka, _ = h.step_timed(args.alone_steps)
+        h.set_tuning(tuned["gram_blocks"], tuned["bp_grid"], tuned["sparse_fork"],
+                     tuned["sparse_grid"])
+        for name, tot in ka.items():
+            per = tot / args.alone_steps
+            b, f = algorithmic(name, p, nsamp)
+            alone[name] = {"ms_per_launch": per,
+                           "GB_s": (b / (per * 1e-3) / 1e9) if b and per > 0 else None,
+                           "hbm_frac": (b / (per * 1e-3) / 1e9 / HBM_PEAK_GBS) if b and per > 0
+                           else None,
+                           "TFLOP_s": (f / (per * 1e-3) / 1e12) if f and per > 0 else None}
+
     workload = f"c{args.config}"
     kernels = {}
     for name, tot in kms.items():
@@ -416,6 +438,7 @@ def main():
         "solve_iters": args.latency_iters,
         "graph_iterations_per_s": graph_its,
         "kernels": kernels,
+        "kernels_alone": alone,
         "resid_norm": st["resid_norm"],
         "eig_sweeps_last": st["eig_sweeps"],
         "tuning": tuning,
@@ -480,8 +503,10 @@ def main():
                                 rank=5, nblobs=40, seed=synth.MASTER_SEED * 10 + 6, levels=1)
         tg = pls.to_device(pg)
         with pls.PriorLS(256, 256, 14, 20, 1, wavelet_levels=1, gram_mode=args.gram_mode) as hg:
-            hg.solve(tg["kspace"], tg["mask"], tg["sens"], tg["prior_w"], max_iter=args.warmup,
-                     outputs=(), lambda_L=pg.lambda_L, lambda_S=pg.lambda_S)
+            g1 = time.perf_counter()
+            tun = hg.tune(tg["kspace"], tg["mask"], tg["sens"], tg["prior_w"], check_every=10,
+                          lambda_L=pg.lambda_L, lambda_S=pg.lambda_S)
+            hg.step(args.warmup) if args.warmup > 0 else None
             torch.cuda.synchronize()
             a0 = time.perf_counter()
             kmg, _ = hg.step_timed(args.steps)
@@ -489,7 +514,9 @@ def main():
             out["transforms"]["geometry_256x256x14x20"] = {
                 "iterations_per_s": args.steps / (time.perf_counter() - a0),
                 "data_consistency_ms": kmg["data_consistency"] / args.steps,
-                "input_gen_s": a0 - g0,
+                "kernels_ms": {k: v / args.steps for k, v in kmg.items()},
+                "tuning": tun,
+                "input_gen_s": g1 - g0,
                 "note": "the cardiac geometry of the paper's experiments, synthetic phantom"}
         del tg, pg
     del t

@@ -308,7 +308,6 @@ void upload_tfft_operands(prior_ls_handle* h) {
     PLS_HIP(hipStreamSynchronize(h->stream));
 }
 
-// one iteration of Algorithm 1 on the resident state (see the schedule in the header)
 // One iteration of Algorithm 1 on the resident state.  Steps (1)-(2) (Gram, eigensolve,
 // back-projection) run on the main stream while step (3) (sparse update) runs on the side
 // stream from the end of the Gram pass on; both only read C = M - S, S and L of the
@@ -317,15 +316,17 @@ void upload_tfft_operands(prior_ls_handle* h) {
 void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev = nullptr) {
     const prior_ls_dims& d = h->d;
     const Sizes& sz = h->sz;
-    hipStream_t s = h->stream, s2 = h->side;
+    // The sparse update forks off after the Gram pass (it then fills the GPU beside the
+    // one-block eigensolve instead of competing with the Gram for bandwidth), or, with
+    // tuning.sparse_fork = 1, at the start of the iteration.  With sparse_fork = 2 it runs
+    // on the main stream after the Gram pass, so every kernel runs alone.
+    const bool serial = h->tuning.sparse_fork == 2;
+    hipStream_t s = h->stream, s2 = serial ? h->stream : h->side;
     const int p = h->cur, q = 1 - p;
     double* rec = h->stats_d + (size_t)slot * kStatRec;
     auto mark = [&](int k, hipStream_t st) {
         if (ev) PLS_HIP(hipEventRecord(ev[k], st));
     };
-    // The sparse update forks off after the Gram pass (it then fills the GPU beside the
-    // one-block eigensolve instead of competing with the Gram for bandwidth), or, with
-    // tuning.sparse_fork = 1, at the start of the iteration.
     const bool fork_first = h->tuning.sparse_fork == 1;
     if (fork_first) {
         PLS_HIP(hipEventRecord(h->ev_fork, s));
@@ -336,7 +337,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     pls::GramArgs ga{h->C, h->gpart, (int)sz.N, d.nt, 0, h->tuning.gram_blocks};
     const int gb = pls::launch_gram(d.gram_mode, ga, s);
     mark(1, s);
-    if (!fork_first) {
+    if (!fork_first && !serial) {
         PLS_HIP(hipEventRecord(h->ev_fork, s));
         PLS_HIP(hipStreamWaitEvent(s2, h->ev_fork, 0));
     }
@@ -360,7 +361,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     sa.max_grid = h->tuning.sparse_grid;
     const int spb = launch_sparse_any(h, sa, s2);
     mark(7, s2);
-    PLS_HIP(hipEventRecord(h->ev_join, s2));
+    if (!serial) PLS_HIP(hipEventRecord(h->ev_join, s2));
     mark(2, s);
     pls::launch_gram_reduce(h->gpart, gb, sz.gentries, h->gred, s);
     mark(3, s);
@@ -385,7 +386,7 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     pls::launch_bp(ba, s);
     mark(9, s);
     // step (4): data consistency -> C = M_k - S_k   (joins the sparse update)
-    PLS_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
+    if (!serial) PLS_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
     DcArgs da{};
     da.L = h->L[q];
     da.S = h->S[q];
@@ -812,7 +813,7 @@ int check_tuning(prior_ls_handle* h, const prior_ls_tuning* t) {
         return fail(h, PRIOR_LS_EINVAL, "gram_blocks must be 0 or in [64, 2048]");
     if (t->bp_grid != 0 && (t->bp_grid < 64 || t->bp_grid > 65536))
         return fail(h, PRIOR_LS_EINVAL, "bp_grid must be 0 or in [64, 65536]");
-    if (t->sparse_fork != 0 && t->sparse_fork != 1) return fail(h, PRIOR_LS_EINVAL, "sparse_fork must be 0 or 1");
+    if (t->sparse_fork < 0 || t->sparse_fork > 2) return fail(h, PRIOR_LS_EINVAL, "sparse_fork must be 0, 1 or 2");
     if (t->sparse_grid != 0 && (t->sparse_grid < 64 || t->sparse_grid > 65536))
         return fail(h, PRIOR_LS_EINVAL, "sparse_grid must be 0 or in [64, 65536]");
     return PRIOR_LS_OK;
@@ -1479,7 +1480,8 @@ void batch_upload_args(prior_ls_batch* b) {
 void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
     const prior_ls_dims& d = b->d;
     const int n = (int)b->hs.size();
-    hipStream_t s = b->stream, s2 = b->side;
+    const bool serial = b->tuning.sparse_fork == 2;
+    hipStream_t s = b->stream, s2 = serial ? b->stream : b->side;
     const int* act = reinterpret_cast<const int*>(b->dev + b->off[7]);
     const long rec = (long)slot * kStatRec;
     const bool fork_first = b->tuning.sparse_fork == 1;
@@ -1489,7 +1491,7 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
     }
     const pls::Batched<pls::GramArgs> bg{n, barr<pls::GramArgs>(b, b->dev, 0, p), act, 0};
     pls::launch_gram_batched(d.gram_mode, barr<pls::GramArgs>(b, b->host, 0, p)[0], &bg, s);
-    if (!fork_first) {
+    if (!fork_first && !serial) {
         PLS_HIP(hipEventRecord(b->ev_fork, s));
         PLS_HIP(hipStreamWaitEvent(s2, b->ev_fork, 0));
     }
@@ -1497,14 +1499,14 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
     const pls::SparseArgs& sa0 = barr<pls::SparseArgs>(b, b->host, 4, p)[0];
     if (d.transform == PRIOR_LS_T_TFFT) pls::launch_sparse_tfft_batched(sa0, &bs, s2);
     else pls::launch_sparse_batched(d.wavelet_levels, sa0, &bs, s2);
-    PLS_HIP(hipEventRecord(b->ev_join, s2));
+    if (!serial) PLS_HIP(hipEventRecord(b->ev_join, s2));
     const pls::Batched<pls::ReduceArgs> br{n, barr<pls::ReduceArgs>(b, b->dev, 1, p), act, 0};
     pls::launch_gram_reduce_batched(barr<pls::ReduceArgs>(b, b->host, 1, p)[0], &br, s);
     const pls::Batched<pls::EigArgs> be{n, barr<pls::EigArgs>(b, b->dev, 2, p), act, rec};
     pls::launch_eig_batched(barr<pls::EigArgs>(b, b->host, 2, p)[0], &be, s);
     const pls::Batched<pls::BpArgs> bb{n, barr<pls::BpArgs>(b, b->dev, 3, p), act, 0};
     pls::launch_bp_batched(barr<pls::BpArgs>(b, b->host, 3, p)[0], &bb, s);
-    PLS_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
+    if (!serial) PLS_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
     const pls::Batched<DcArgs> bd{n, barr<DcArgs>(b, b->dev, 5, p), act, 0};
     pls::launch_dc_batched(d.ny, d.nz, stats, barr<DcArgs>(b, b->host, 5, p)[0], &bd, s);
     if (stats) {

@@ -58,7 +58,7 @@ def test_tune_then_step_matches_oracle_and_manual_tuning(tmp_path):
     assert len(json.load(open(cache))) == 1
 
 
-@pytest.mark.parametrize("t", [dict(gram_blocks=8), dict(bp_grid=3), dict(sparse_fork=2),
+@pytest.mark.parametrize("t", [dict(gram_blocks=8), dict(bp_grid=3), dict(sparse_fork=3),
                                dict(sparse_grid=3)])
 def test_set_tuning_rejects_out_of_range(t):
     with pls.PriorLS(16, 16, 4, 6, 2) as h:
@@ -72,10 +72,43 @@ def test_every_choice_agrees_to_rounding():
     k, m, s, w = _inputs(p)
     outs = []
     for t in (dict(), dict(gram_blocks=64, bp_grid=64, sparse_fork=1, sparse_grid=64),
-              dict(gram_blocks=2048, bp_grid=8192, sparse_fork=0, sparse_grid=1024)):
+              dict(gram_blocks=2048, bp_grid=8192, sparse_fork=0, sparse_grid=1024),
+              dict(gram_blocks=256, bp_grid=1024, sparse_fork=2, sparse_grid=0)):
         with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc) as h:
             h.set_tuning(**t)
             o, _ = h.solve(k, m, s, w, lambda_L=p.lambda_L, lambda_S=p.lambda_S, max_iter=10)
             outs.append(o["X"].cpu().numpy())
     for o in outs[1:]:
         assert np.linalg.norm(o - outs[0]) / np.linalg.norm(outs[0]) < 1e-5
+
+
+def test_schedules_give_identical_bits():
+    # the fork point and the serial schedule only reorder independent kernels, and the
+    # sparse-update grid only changes which workgroup takes which tile: with one Gram split
+    # every schedule gives the same bits, alone and in a batch
+    ps = [synth.small(nx=24, ny=32, nz=8, nt=7, nc=2, seed=33 + k) for k in range(2)]
+    prm = dict(lambda_L=ps[0].lambda_L, lambda_S=ps[0].lambda_S, max_iter=8, check_every=4)
+    ref = None
+    for fork, grid in ((0, 0), (1, 64), (2, 0), (2, 256)):
+        with pls.PriorLS(24, 32, 8, 7, 2) as h:
+            h.set_tuning(gram_blocks=256, bp_grid=1024, sparse_fork=fork, sparse_grid=grid)
+            o, st = h.solve(*_inputs(ps[0]), **prm)
+        if ref is None:
+            ref = (o, st)
+        else:
+            for key in ("L", "S", "X", "M"):
+                assert torch.equal(o[key], ref[0][key]), (fork, grid, key)
+            assert st["resid_norm"] == ref[1]["resid_norm"]
+    hs = [pls.PriorLS(24, 32, 8, 7, 2) for _ in ps]
+    try:
+        for h in hs:
+            h.set_tuning(gram_blocks=256, bp_grid=1024, sparse_fork=2, sparse_grid=0)
+        with pls.Batch(hs) as b:
+            outs, _ = b.solve([pls.to_device(p) for p in ps],
+                              [pls.make_params(lambda_L=p.lambda_L, lambda_S=p.lambda_S,
+                                               max_iter=8, check_every=4) for p in ps])
+    finally:
+        for h in hs:
+            h.close()
+    for key in ("L", "S", "X", "M"):
+        assert torch.equal(outs[0][key], ref[0][key]), key
