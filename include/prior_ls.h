@@ -235,14 +235,16 @@ const char *prior_ls_last_error(const prior_ls_handle *h);
  * compact k-space, which is sized at solve from the mask).  0 for invalid dims. */
 uint64_t prior_ls_plan_bytes(const prior_ls_dims *dims);
 
-/* Benchmark support.  Runs n_iter iterations exactly as prior_ls_step does, but launches the
- * kernels directly (no hipGraph) with a hipEvent recorded on the handle's stream before and
- * after each one.  kernel_ms (host, PRIOR_LS_NKERNELS doubles) receives, per kernel, the sum
- * of its launch durations over the n_iter iterations, in the order
+/* Benchmark support.  Runs n_iter iterations as one chunk of prior_ls_step (statistics on
+ * the last iteration only), but launches the kernels directly (no hipGraph) with a hipEvent
+ * recorded before and after each one on the stream it runs on.  kernel_ms (host,
+ * PRIOR_LS_NKERNELS doubles) receives, per kernel, the sum of its launch durations over the
+ * n_iter iterations, in the order
  *   0 Gram, 1 Gram reduction, 2 eigensolve, 3 sparse update, 4 back-projection,
- *   5 data consistency, 6 statistics.
- * kernel_launches (host, PRIOR_LS_NKERNELS ints, may be NULL) receives the launch counts. */
-#define PRIOR_LS_NKERNELS 7
+ *   5 data consistency, 6 statistics, 7 change of the iterate (stopping test).
+ * kernel_launches (host, PRIOR_LS_NKERNELS ints, may be NULL) receives the launch counts
+ * (1 for the last two). */
+#define PRIOR_LS_NKERNELS 8
 int prior_ls_step_timed(prior_ls_handle *h, int32_t n_iter, double *kernel_ms,
                         int32_t *kernel_launches, prior_ls_stats *stats);
 

@@ -35,8 +35,9 @@ EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destr
            "prior_ls_tune", "prior_ls_set_tuning", "prior_ls_get_tuning",
            "prior_ls_batch_create", "prior_ls_batch_solve", "prior_ls_batch_step",
            "prior_ls_batch_last_error", "prior_ls_batch_destroy")
-NKERNELS = 7
-KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats")
+NKERNELS = 8
+KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats",
+                "change")
 
 
 class LibraryMissing(RuntimeError):

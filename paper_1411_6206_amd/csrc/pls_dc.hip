@@ -60,22 +60,21 @@ int dc_blocks(int ny, int nz, int nx, int nt) {
     return 0;
 }
 
-int launch_dc_batched(int ny, int nz, bool stats, const DcArgs& a, const Batched<DcArgs>* bt,
-                      hipStream_t s) {
+int launch_dc_batched(int ny, int nz, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s) {
     int r = -1;
     switch (nz) {
-        case 1: r = dc_launch_nz1(ny, stats, a, bt, s); break;
-        case 4: r = dc_launch_nz4(ny, stats, a, bt, s); break;
-        case 8: r = dc_launch_nz8(ny, stats, a, bt, s); break;
-        case 14: r = dc_launch_nz14(ny, stats, a, bt, s); break;
-        case 16: r = dc_launch_nz16(ny, stats, a, bt, s); break;
-        case 32: r = dc_launch_nz32(ny, stats, a, bt, s); break;
+        case 1: r = dc_launch_nz1(ny, a, bt, s); break;
+        case 4: r = dc_launch_nz4(ny, a, bt, s); break;
+        case 8: r = dc_launch_nz8(ny, a, bt, s); break;
+        case 14: r = dc_launch_nz14(ny, a, bt, s); break;
+        case 16: r = dc_launch_nz16(ny, a, bt, s); break;
+        case 32: r = dc_launch_nz32(ny, a, bt, s); break;
     }
     return r < 0 ? 0 : r;
 }
 
-int launch_dc(int ny, int nz, bool stats, const DcArgs& a, hipStream_t s) {
-    return launch_dc_batched(ny, nz, stats, a, nullptr, s);
+int launch_dc(int ny, int nz, const DcArgs& a, hipStream_t s) {
+    return launch_dc_batched(ny, nz, a, nullptr, s);
 }
 
 bool launch_xifft(int nx, const XiArgs& a, hipStream_t s) { return xifft_launch_any(nx, a, s); }

@@ -60,7 +60,7 @@ struct Dist {
     }
 };
 
-template <class G, bool STATS, class SRC>
+template <class G, class SRC>
 __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
     if (src.skip()) return;
     const DcArgs a = src.get();
@@ -144,32 +144,21 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
     stage_load(0, dnext);
 
     float2 Y[G::KEEPY ? Q : 1], acc[Q], v[Q];
-    double dy2 = 0.0, y2 = 0.0;
-    // Y = L + S at element gi; the statistics variant also accumulates |Y - Yold|^2 and
-    // |Yold|^2 over the elements the block owns (Yold = Lold + Sold)
-    auto form_y = [&](int gi, bool ok) __attribute__((always_inline)) {
+    // Y = L + S at element gi
+    auto form_y = [&](int gi) __attribute__((always_inline)) {
         const float2 l = Lp[gi], sv = Sp[gi];
         float2 yv = has_s ? cadd(l, sv) : l;
         if (!has_y) yv = make_float2(0.f, 0.f);
-        if constexpr (STATS) {
-            const float2 lo = a.Lold[gi], so = a.Sold[gi];
-            const float2 yo = cadd(lo, so);
-            const double dx = (double)yv.x - yo.x, dyy = (double)yv.y - yo.y;
-            const double w = ok ? 1.0 : 0.0;
-            dy2 += w * (dx * dx + dyy * dyy);
-            y2 += w * ((double)yo.x * yo.x + (double)yo.y * yo.y);
-        }
         return yv;
     };
 #pragma unroll
     for (int i = 0; i < D0::NB; ++i) {
         const int pbc = min(d0.pb[i], nvalid - 1);
         const int o = plane0 + pbc * P + d0.rel[i];
-        const bool ok = d0.pb[i] < nvalid;
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int q = i * R0 + r;
-            if constexpr (G::KEEPY) Y[q] = form_y(o + r * D0::STEP, ok);
+            if constexpr (G::KEEPY) Y[q] = form_y(o + r * D0::STEP);
             acc[q] = make_float2(0.f, 0.f);
         }
     }
@@ -211,7 +200,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
                     // read one array instead of two
                     const int gi = plane0 + o + r * D0::STEP;
                     if (c == 0) {
-                        yv = form_y(gi, own);
+                        yv = form_y(gi);
                         if (own) a.C[gi] = yv;
                     } else {
                         yv = a.C[gi];
@@ -289,17 +278,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
         }
     }
     const double s0 = block_sum<G::T>(res2, red);
-    double s1 = 0.0, s2 = 0.0;
-    if constexpr (STATS) {
-        s1 = block_sum<G::T>(dy2, red);
-        s2 = block_sum<G::T>(y2, red);
-    }
-    if (tid == 0) {
-        a.part[lb * 4 + 0] = s0;
-        a.part[lb * 4 + 1] = s1;
-        a.part[lb * 4 + 2] = s2;
-        a.part[lb * 4 + 3] = 0.0;
-    }
+    if (tid == 0) a.part[lb] = s0;
 }
 
 // Unitary inverse DFT along kx of every sampled (c, t, kz, ky) line, scaled by 1/sqrt(P),
@@ -371,13 +350,10 @@ inline int dc_grid(int nx, int nt) {
 
 // bt NULL: one problem with argument block a; else the batch *bt (a: problem 0's block)
 template <int NY, int NZ>
-inline int dc_launch_t(bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s) {
+inline int dc_launch_t(const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s) {
     using G = typename DcCfg<NY, NZ>::G;
     const int grid = dc_grid<NY, NZ>(a.nx, a.nt);
-    if (stats)
-        PLS_LAUNCH(dim3(grid), dim3(G::T), s, a, bt, pls_dc_kernel, G, true);
-    else
-        PLS_LAUNCH(dim3(grid), dim3(G::T), s, a, bt, pls_dc_kernel, G, false);
+    PLS_LAUNCH(dim3(grid), dim3(G::T), s, a, bt, pls_dc_kernel, G);
     return grid;
 }
 
@@ -390,12 +366,12 @@ inline void xifft_launch_t(const XiArgs& a, hipStream_t s) {
 
 // Per-nz translation units (pls_dc_nz*.hip) instantiate the kernels; these return -1 when
 // the shape is not theirs.
-int dc_launch_nz1(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
-int dc_launch_nz4(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
-int dc_launch_nz8(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
-int dc_launch_nz14(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
-int dc_launch_nz16(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
-int dc_launch_nz32(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz1(int ny, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz4(int ny, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz8(int ny, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz14(int ny, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz16(int ny, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
+int dc_launch_nz32(int ny, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s);
 bool xifft_launch_any(int nx, const XiArgs& a, hipStream_t s);
 
 }  // namespace pls

@@ -4,14 +4,13 @@
 
 namespace pls {
 
-int dc_launch_nz14(int ny, bool stats, const DcArgs& a, const Batched<DcArgs>* bt,
-                    hipStream_t s) {
+int dc_launch_nz14(int ny, const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s) {
     switch (ny) {
-        case 16: return dc_launch_t<16, 14>(stats, a, bt, s);
-        case 32: return dc_launch_t<32, 14>(stats, a, bt, s);
-        case 64: return dc_launch_t<64, 14>(stats, a, bt, s);
-        case 128: return dc_launch_t<128, 14>(stats, a, bt, s);
-        case 256: return dc_launch_t<256, 14>(stats, a, bt, s);
+        case 16: return dc_launch_t<16, 14>(a, bt, s);
+        case 32: return dc_launch_t<32, 14>(a, bt, s);
+        case 64: return dc_launch_t<64, 14>(a, bt, s);
+        case 128: return dc_launch_t<128, 14>(a, bt, s);
+        case 256: return dc_launch_t<256, 14>(a, bt, s);
     }
     return -1;
 }

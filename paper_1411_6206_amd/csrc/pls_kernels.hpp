@@ -19,8 +19,6 @@ namespace pls {
 struct DcArgs {
     const float2* L;       // new iterate (Y = L + S); L NULL means Y = 0
     const float2* S;       // NULL means S = 0
-    const float2* Lold;    // previous iterate, read only by the statistics variant
-    const float2* Sold;
     float2* C;             // out: C = M - S = L - E^H(E Y - d); also holds Y between coils,
                            // so it must not alias L or S
     const float2* sens;    // [nc][nx][nz][ny]; a single unit coil is an array of ones
@@ -30,7 +28,7 @@ struct DcArgs {
     const int16_t* sidx;
     const float2* twy;     // exp(-2 pi i m / ny)
     const float2* twz;     // exp(-2 pi i m / nz)
-    double* part;          // per block: [0] sum |r|^2 (scaled), [1] sum |Y - Yold|^2, [2] sum |Yold|^2
+    double* part;          // per block: sum |r|^2 of its residual entries (scaled by 1/(ny nz))
     int nx, nt, nc;
     float inv_p;           // 1 / (ny nz)
 };
@@ -51,7 +49,7 @@ bool dc_supported(int ny, int nz);
 bool xifft_supported(int nx);
 // Launch the data-consistency pass over all (t, x) planes.  Returns the number of blocks
 // (rows of DcArgs::part written), 0 if the shape is unsupported.
-int launch_dc(int ny, int nz, bool stats, const DcArgs& a, hipStream_t s);
+int launch_dc(int ny, int nz, const DcArgs& a, hipStream_t s);
 int dc_blocks(int ny, int nz, int nx, int nt);
 bool launch_xifft(int nx, const XiArgs& a, hipStream_t s);
 
@@ -130,9 +128,24 @@ int sparse_haar_blocks(int levels, int nx, int ny, int nz, int nt, int max_grid)
 int launch_sparse_tfft(const SparseArgs& a, hipStream_t s);
 int sparse_tfft_blocks(int N);
 
+// Change of the iterate for the stopping test: per block, sum |Y - Yold|^2 and sum |Yold|^2
+// over its elements (Y = L + S, Yold = Lold + Sold, each formed in FP32, summed in FP64).
+struct ChangeArgs {
+    const float2* L;
+    const float2* S;
+    const float2* Lold;
+    const float2* Sold;
+    double* part;          // [blocks][2]
+    long n;                // complex elements of each array
+};
+int change_blocks(long n);
+void launch_change(const ChangeArgs& a, hipStream_t s);
+
 struct StatsArgs {
     const double* dc_part;
     int dc_blocks;
+    const double* ch_part; // [ch_blocks][2] change partials; ch_blocks 0: stat[1] = stat[2] = 0
+    int ch_blocks;
     const double* sp_part;
     int sp_blocks;
     double* stat;          // per-iteration record
@@ -215,7 +228,7 @@ int launch_sparse_batched(int levels, const SparseArgs& a0, const Batched<Sparse
                           hipStream_t s);
 int launch_sparse_tfft_batched(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s);
 void launch_stats_batched(const StatsArgs& a0, const Batched<StatsArgs>* bt, hipStream_t s);
-int launch_dc_batched(int ny, int nz, bool stats, const DcArgs& a0, const Batched<DcArgs>* bt,
-                      hipStream_t s);
+void launch_change_batched(const ChangeArgs& a0, const Batched<ChangeArgs>* bt, hipStream_t s);
+int launch_dc_batched(int ny, int nz, const DcArgs& a0, const Batched<DcArgs>* bt, hipStream_t s);
 
 }  // namespace pls

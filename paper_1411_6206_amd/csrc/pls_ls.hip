@@ -7,6 +7,8 @@
 //    J-level orthonormal Haar (nonstandard pyramid) computed in place on (2^J)^3 blocks:
 //    x in registers, y and z across the lanes of a wave;
 //  * fixed-order FP64 reduction of the per-block partial sums into one record per iteration.
+#include <algorithm>
+
 #include "pls_common.hpp"
 #include "pls_kernels.hpp"
 
@@ -452,18 +454,22 @@ __global__ void __launch_bounds__(NTH) pls_stats_kernel(SRC src) {
     int b = threadIdx.x;
     for (; b + 3 * 256 < a.dc_blocks; b += 4 * 256) {
 #pragma unroll
+        for (int k = 0; k < 4; ++k) p0[k] += a.dc_part[b + 256 * k];
+    }
+    for (int k = 0; b < a.dc_blocks; b += 256, ++k) p0[k] += a.dc_part[b];
+    b = threadIdx.x;
+    for (; b + 3 * 256 < a.ch_blocks; b += 4 * 256) {
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const double* q = a.dc_part + 4 * (b + 256 * k);
-            p0[k] += q[0];
-            p1[k] += q[1];
-            p2[k] += q[2];
+            const double* q = a.ch_part + 2 * (b + 256 * k);
+            p1[k] += q[0];
+            p2[k] += q[1];
         }
     }
-    for (int k = 0; b < a.dc_blocks; b += 256, ++k) {
-        const double* q = a.dc_part + 4 * b;
-        p0[k] += q[0];
-        p1[k] += q[1];
-        p2[k] += q[2];
+    for (int k = 0; b < a.ch_blocks; b += 256, ++k) {
+        const double* q = a.ch_part + 2 * b;
+        p1[k] += q[0];
+        p2[k] += q[1];
     }
     b = threadIdx.x;
     for (; b + 3 * 256 < a.sp_blocks; b += 4 * 256) {
@@ -491,6 +497,67 @@ __global__ void __launch_bounds__(NTH) pls_stats_kernel(SRC src) {
 void launch_stats_batched(const StatsArgs& a, const Batched<StatsArgs>* bt, hipStream_t s) {
     PLS_LAUNCH(dim3(1), dim3(256), s, a, bt, pls_stats_kernel, 256);
 }
+
+// ---------------------------------------------------------------- change of the iterate
+// ||Y - Yold||^2 and ||Yold||^2 for the stopping test (step (4)'s relative change), a
+// streaming pass over the four image arrays.  Each thread takes pairs of elements (16-byte
+// loads) in a grid-stride loop; the grid depends on n only, so the sums are deterministic.
+constexpr int kChangeThreads = 256;
+constexpr int kChangeMaxBlocks = 2048;
+
+int change_blocks(long n) {
+    const long pairs = (n + 1) / 2;
+    const long per_block = (long)kChangeThreads * 8;   // at least 8 pairs per thread
+    const long b = (pairs + per_block - 1) / per_block;
+    return (int)std::min<long>(std::max<long>(b, 1), kChangeMaxBlocks);
+}
+
+// 32 registers: its waves then fit beside two waves of the data-consistency kernel it runs
+// next to (240 registers each of the SIMD's 512)
+template <int NTH, class SRC>
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_num_vgpr(32)))
+pls_change_kernel(SRC src) {
+    if (src.skip()) return;
+    const ChangeArgs a = src.get();
+    __shared__ double red[NTH / kWave];
+    double d2 = 0.0, y2 = 0.0;
+    auto add = [&](float2 l, float2 sv, float2 lo, float2 so) __attribute__((always_inline)) {
+        const float2 y = cadd(l, sv), yo = cadd(lo, so);
+        const double dx = (double)y.x - yo.x, dy = (double)y.y - yo.y;
+        d2 = fma(dx, dx, fma(dy, dy, d2));
+        y2 = fma((double)yo.x, (double)yo.x, fma((double)yo.y, (double)yo.y, y2));
+    };
+    const long npair = a.n / 2;
+    const float4* L4 = reinterpret_cast<const float4*>(a.L);
+    const float4* S4 = reinterpret_cast<const float4*>(a.S);
+    const float4* Lo4 = reinterpret_cast<const float4*>(a.Lold);
+    const float4* So4 = reinterpret_cast<const float4*>(a.Sold);
+    const long stride = (long)gridDim.x * NTH;
+    for (long i = (long)blockIdx.x * NTH + threadIdx.x; i < npair; i += stride) {
+        const float4 l = L4[i], sv = S4[i], lo = Lo4[i], so = So4[i];
+        add(make_float2(l.x, l.y), make_float2(sv.x, sv.y), make_float2(lo.x, lo.y),
+            make_float2(so.x, so.y));
+        add(make_float2(l.z, l.w), make_float2(sv.z, sv.w), make_float2(lo.z, lo.w),
+            make_float2(so.z, so.w));
+    }
+    if ((a.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const long e = a.n - 1;
+        add(a.L[e], a.S[e], a.Lold[e], a.Sold[e]);
+    }
+    d2 = block_sum<NTH>(d2, red);
+    y2 = block_sum<NTH>(y2, red);
+    if (threadIdx.x == 0) {
+        a.part[2 * blockIdx.x] = d2;
+        a.part[2 * blockIdx.x + 1] = y2;
+    }
+}
+
+void launch_change_batched(const ChangeArgs& a, const Batched<ChangeArgs>* bt, hipStream_t s) {
+    PLS_LAUNCH(dim3(change_blocks(a.n)), dim3(kChangeThreads), s, a, bt, pls_change_kernel,
+               kChangeThreads);
+}
+
+void launch_change(const ChangeArgs& a, hipStream_t s) { launch_change_batched(a, nullptr, s); }
 
 void launch_stats(const StatsArgs& a, hipStream_t s) { launch_stats_batched(a, nullptr, s); }
 

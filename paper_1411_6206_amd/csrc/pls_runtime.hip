@@ -159,6 +159,8 @@ struct prior_ls_handle {
     hipStream_t side = nullptr;      // second stream: the sparse update runs beside the
                                      // Gram / eigensolve / back-projection chain
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_bp = nullptr, ev_chg = nullptr;   // statistics iterations: the change pass
+                                                    // (side stream) after the back-projection
     hipEvent_t ev_chunk = nullptr;   // end of the last enqueued chunk / output write
     int device = 0;
     Sizes sz{};
@@ -191,7 +193,7 @@ struct prior_ls_handle {
     double *V = nullptr, *Wd = nullptr;
     float* Wop = nullptr;
     double* sigma_prev = nullptr;
-    double *dc_part = nullptr, *sp_part = nullptr;
+    double *dc_part = nullptr, *sp_part = nullptr, *ch_part = nullptr;
     double* stats_d = nullptr;
     double* stats_h = nullptr;
     // op scratch (lazy)
@@ -385,13 +387,24 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     mark(8, s);
     pls::launch_bp(ba, s);
     mark(9, s);
+    // the change of the iterate for the stopping test: on the side stream once the
+    // back-projection and the sparse update are done, beside the data-consistency pass (it
+    // reads only the iterates, which nothing overwrites before the statistics kernel)
+    if (stats && !serial) {
+        PLS_HIP(hipEventRecord(h->ev_bp, s));
+        PLS_HIP(hipStreamWaitEvent(s2, h->ev_bp, 0));
+    }
+    mark(14, s2);
+    if (stats)
+        pls::launch_change(pls::ChangeArgs{h->L[q], h->S[q], h->L[p], h->S[p], h->ch_part,
+                                           (long)sz.I}, s2);
+    mark(15, s2);
+    if (stats && !serial) PLS_HIP(hipEventRecord(h->ev_chg, s2));
     // step (4): data consistency -> C = M_k - S_k   (joins the sparse update)
     if (!serial) PLS_HIP(hipStreamWaitEvent(s, h->ev_join, 0));
     DcArgs da{};
     da.L = h->L[q];
     da.S = h->S[q];
-    da.Lold = h->L[p];
-    da.Sold = h->S[p];
     da.C = h->C;
     da.sens = h->has_sens ? h->sens : h->ones;
     da.dh = h->dh;
@@ -406,12 +419,14 @@ void enqueue_iteration(prior_ls_handle* h, int slot, bool stats, hipEvent_t* ev 
     da.nc = d.nc;
     da.inv_p = 1.0f / (float)sz.P;
     mark(10, s);
-    const int dcb = pls::launch_dc(d.ny, d.nz, stats, da, s);
+    const int dcb = pls::launch_dc(d.ny, d.nz, da, s);
     mark(11, s);
     // statistics are reduced only where they are read: the last iteration of a chunk
+    if (stats && !serial) PLS_HIP(hipStreamWaitEvent(s, h->ev_chg, 0));
     mark(12, s);
     if (stats) {
-        pls::StatsArgs st{h->dc_part, dcb, h->sp_part, spb, rec, (double)sz.P, h->params.lambda_S};
+        pls::StatsArgs st{h->dc_part, dcb, h->ch_part, pls::change_blocks((long)sz.I), h->sp_part,
+                          spb, rec, (double)sz.P, h->params.lambda_S};
         pls::launch_stats(st, s);
     }
     mark(13, s);
@@ -641,10 +656,10 @@ int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_p
         pls::launch_pack((const float2*)in->L0, nullptr, h->L[0], d.nt, d.nx, d.ny, d.nz, s);
         pls::launch_pack((const float2*)in->S0, nullptr, h->S[0], d.nt, d.nx, d.ny, d.nz, s);
         DcArgs da = dc_args(h, h->L[0], h->S[0], h->C);
-        pls::launch_dc(d.ny, d.nz, false, da, s);
+        pls::launch_dc(d.ny, d.nz, da, s);
     } else {
         DcArgs da = dc_args(h, nullptr, nullptr, h->C);
-        pls::launch_dc(d.ny, d.nz, false, da, s);
+        pls::launch_dc(d.ny, d.nz, da, s);
         PLS_HIP(hipMemsetAsync(h->S[0], 0, sz.I * sizeof(float2), s));
         PLS_HIP(hipMemcpyAsync(h->L[0], h->C, sz.I * sizeof(float2), hipMemcpyDeviceToDevice, s));
     }
@@ -786,7 +801,7 @@ int shift_window(prior_ls_handle* h, const void* kspace_frame, const uint8_t* ma
     set_identity_V(h, h->V);
     // step (0) of the new window: one data-consistency step from Y = L + S
     DcArgs da = dc_args(h, h->L[h->cur], h->S[h->cur], h->C);
-    pls::launch_dc(d.ny, d.nz, false, da, s);
+    pls::launch_dc(d.ny, d.nz, da, s);
     PLS_HIP(hipGetLastError());
     h->iters = 0;
     std::memset(h->last, 0, sizeof(h->last));
@@ -953,6 +968,8 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
         PLS_HIP(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&h->ev_bp, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&h->ev_chg, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&h->ev_chunk, hipEventDisableTiming));
         const prior_ls_dims& d = h->d;
         h->C = h->alloc<float2>(sz.I * sizeof(float2));
@@ -986,7 +1003,8 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
         h->Wd = h->alloc<double>(2 * 32 * 32 * sizeof(double));
         h->Wop = h->alloc<float>(64 * 64 * sizeof(float));
         h->sigma_prev = h->alloc<double>(64 * sizeof(double));
-        h->dc_part = h->alloc<double>((size_t)sz.dcb * 4 * sizeof(double));
+        h->dc_part = h->alloc<double>((size_t)sz.dcb * sizeof(double));
+        h->ch_part = h->alloc<double>((size_t)pls::change_blocks((long)sz.I) * 2 * sizeof(double));
         h->sp_part = h->alloc<double>((size_t)std::max(sz.spb, 1) * sizeof(double));
         h->stats_d = h->alloc<double>((size_t)kMaxChunk * kStatRec * sizeof(double));
         if (d.transform == PRIOR_LS_T_TFFT) {
@@ -1022,6 +1040,8 @@ void prior_ls_destroy(prior_ls_handle* h) {
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->ev_bp) (void)hipEventDestroy(h->ev_bp);
+    if (h->ev_chg) (void)hipEventDestroy(h->ev_chg);
     if (h->ev_chunk) (void)hipEventDestroy(h->ev_chunk);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->stream) (void)hipStreamDestroy(h->stream);
@@ -1213,7 +1233,7 @@ int prior_ls_step_timed(prior_ls_handle* h, int32_t n_iter, double* kernel_ms,
     if (!kernel_ms) return fail(h, PRIOR_LS_EINVAL, "kernel_ms is NULL");
     if (stats && stats->struct_size != sizeof(prior_ls_stats))
         return fail(h, PRIOR_LS_EINVAL, "stats.struct_size mismatch");
-    constexpr int kEv = 14;
+    constexpr int kEv = 16;
     std::vector<hipEvent_t> ev((size_t)n_iter * kEv, nullptr);
     const int r = guarded(h, [&]() -> int {
         for (auto& e : ev) PLS_HIP(hipEventCreate(&e));
@@ -1226,8 +1246,9 @@ int prior_ls_step_timed(prior_ls_handle* h, int32_t n_iter, double* kernel_ms,
         PLS_HIP(hipStreamSynchronize(h->stream));
         std::memcpy(h->last, h->stats_h, sizeof(h->last));
         h->iters += n_iter;
-        // event pair of each kernel in the ABI order gram, reduce, eig, sparse, bp, dc, stats
-        const int pair[PRIOR_LS_NKERNELS] = {0, 2, 4, 6, 8, 10, 12};
+        // event pair of each kernel in the ABI order gram, reduce, eig, sparse, bp, dc, stats,
+        // change
+        const int pair[PRIOR_LS_NKERNELS] = {0, 2, 4, 6, 8, 10, 12, 14};
         for (int k = 0; k < PRIOR_LS_NKERNELS; ++k) {
             double tot = 0.0;
             for (int j = 0; j < n_iter; ++j) {
@@ -1237,7 +1258,7 @@ int prior_ls_step_timed(prior_ls_handle* h, int32_t n_iter, double* kernel_ms,
                 tot += ms;
             }
             kernel_ms[k] = tot;
-            if (kernel_launches) kernel_launches[k] = n_iter;
+            if (kernel_launches) kernel_launches[k] = k >= 6 ? 1 : n_iter;   // statistics: last iteration
         }
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         fill_stats(h, stats, false, ms);
@@ -1260,9 +1281,9 @@ int prior_ls_op_dc(prior_ls_handle* h, const void* Y, void* M, double* resid_nor
         hipStream_t s = h->stream;
         pls::launch_pack((const float2*)Y, nullptr, h->T1, d.nt, d.nx, d.ny, d.nz, s);
         DcArgs da = dc_args(h, h->T1, nullptr, h->T2);
-        const int dcb = pls::launch_dc(d.ny, d.nz, false, da, s);
+        const int dcb = pls::launch_dc(d.ny, d.nz, da, s);
         double* rec = h->stats_d + (size_t)(kMaxChunk - 1) * kStatRec;
-        pls::StatsArgs st{h->dc_part, dcb, h->sp_part, 0, rec, (double)h->sz.P, 0.0};
+        pls::StatsArgs st{h->dc_part, dcb, nullptr, 0, h->sp_part, 0, rec, (double)h->sz.P, 0.0};
         pls::launch_stats(st, s);
         pls::launch_unpack(h->T2, nullptr, (float2*)M, d.nt, d.nx, d.ny, d.nz, s);
         PLS_HIP(hipGetLastError());
@@ -1371,10 +1392,11 @@ struct prior_ls_batch {
     prior_ls_tuning tuning{};
     hipStream_t stream = nullptr, side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr, ev_h = nullptr;
+    hipEvent_t ev_bp = nullptr, ev_chg = nullptr;
     char* dev = nullptr;       // argument arrays [kernel][phase][problem] and activity flags
     char* host = nullptr;      // pinned staging of the same layout
     size_t bytes = 0;
-    size_t off[8] = {0};       // gram, reduce, eig, bp, sparse, dc, stats, active
+    size_t off[9] = {0};       // gram, reduce, eig, bp, sparse, dc, stats, change, active
     int gram_vpb = 0;
     std::vector<int> staged_cur;   // every problem's iterate index when the arguments were staged
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -1462,16 +1484,16 @@ void batch_upload_args(prior_ls_batch* b) {
             sa.Wi = h->Wti;
             sa.max_grid = b->tuning.sparse_grid;
             barr<pls::SparseArgs>(b, b->host, 4, ph)[i] = sa;
-            DcArgs da = dc_args(h, h->L[q], h->S[q], h->C);
-            da.Lold = h->L[p];
-            da.Sold = h->S[p];
-            barr<DcArgs>(b, b->host, 5, ph)[i] = da;
+            barr<DcArgs>(b, b->host, 5, ph)[i] = dc_args(h, h->L[q], h->S[q], h->C);
             barr<pls::StatsArgs>(b, b->host, 6, ph)[i] =
-                pls::StatsArgs{h->dc_part, sz.dcb, h->sp_part, sparse_launch_blocks(d, b->tuning),
-                               h->stats_d, (double)sz.P, h->params.lambda_S};
+                pls::StatsArgs{h->dc_part, sz.dcb, h->ch_part, pls::change_blocks((long)sz.I),
+                               h->sp_part, sparse_launch_blocks(d, b->tuning), h->stats_d,
+                               (double)sz.P, h->params.lambda_S};
+            barr<pls::ChangeArgs>(b, b->host, 7, ph)[i] =
+                pls::ChangeArgs{h->L[q], h->S[q], h->L[p], h->S[p], h->ch_part, (long)sz.I};
         }
     }
-    PLS_HIP(hipMemcpyAsync(b->dev, b->host, b->off[7], hipMemcpyHostToDevice, b->stream));
+    PLS_HIP(hipMemcpyAsync(b->dev, b->host, b->off[8], hipMemcpyHostToDevice, b->stream));
     PLS_HIP(hipStreamSynchronize(b->stream));
 }
 
@@ -1482,7 +1504,7 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
     const int n = (int)b->hs.size();
     const bool serial = b->tuning.sparse_fork == 2;
     hipStream_t s = b->stream, s2 = serial ? b->stream : b->side;
-    const int* act = reinterpret_cast<const int*>(b->dev + b->off[7]);
+    const int* act = reinterpret_cast<const int*>(b->dev + b->off[8]);
     const long rec = (long)slot * kStatRec;
     const bool fork_first = b->tuning.sparse_fork == 1;
     if (fork_first) {
@@ -1506,10 +1528,21 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
     pls::launch_eig_batched(barr<pls::EigArgs>(b, b->host, 2, p)[0], &be, s);
     const pls::Batched<pls::BpArgs> bb{n, barr<pls::BpArgs>(b, b->dev, 3, p), act, 0};
     pls::launch_bp_batched(barr<pls::BpArgs>(b, b->host, 3, p)[0], &bb, s);
+    // the change of the iterate beside the data-consistency pass (as enqueue_iteration)
+    if (stats) {
+        if (!serial) {
+            PLS_HIP(hipEventRecord(b->ev_bp, s));
+            PLS_HIP(hipStreamWaitEvent(s2, b->ev_bp, 0));
+        }
+        const pls::Batched<pls::ChangeArgs> bc{n, barr<pls::ChangeArgs>(b, b->dev, 7, p), act, 0};
+        pls::launch_change_batched(barr<pls::ChangeArgs>(b, b->host, 7, p)[0], &bc, s2);
+        if (!serial) PLS_HIP(hipEventRecord(b->ev_chg, s2));
+    }
     if (!serial) PLS_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
     const pls::Batched<DcArgs> bd{n, barr<DcArgs>(b, b->dev, 5, p), act, 0};
-    pls::launch_dc_batched(d.ny, d.nz, stats, barr<DcArgs>(b, b->host, 5, p)[0], &bd, s);
+    pls::launch_dc_batched(d.ny, d.nz, barr<DcArgs>(b, b->host, 5, p)[0], &bd, s);
     if (stats) {
+        if (!serial) PLS_HIP(hipStreamWaitEvent(s, b->ev_chg, 0));
         const pls::Batched<pls::StatsArgs> bt{n, barr<pls::StatsArgs>(b, b->dev, 6, p), act, rec};
         pls::launch_stats_batched(barr<pls::StatsArgs>(b, b->host, 6, p)[0], &bt, s);
     }
@@ -1549,8 +1582,8 @@ void batch_iterate(prior_ls_batch* b, const std::vector<int>& target, std::vecto
                    std::vector<std::chrono::steady_clock::time_point>* done_at = nullptr) {
     const int n = (int)b->hs.size();
     std::vector<int> done(n, 0);
-    int* act = reinterpret_cast<int*>(b->host + b->off[7]);
-    int* act_d = reinterpret_cast<int*>(b->dev + b->off[7]);
+    int* act = reinterpret_cast<int*>(b->host + b->off[8]);
+    int* act_d = reinterpret_cast<int*>(b->dev + b->off[8]);
     conv.assign(n, 0);
     status.assign(n, PRIOR_LS_OK);
     for (int i = 0; i < n; ++i) act[i] = target[i] > 0 ? 1 : 0;
@@ -1720,15 +1753,17 @@ int prior_ls_batch_create(prior_ls_handle* const* handles, int32_t count, prior_
         PLS_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
         PLS_HIP(hipEventCreateWithFlags(&b->ev_h, hipEventDisableTiming));
-        const size_t sizes[7] = {sizeof(pls::GramArgs), sizeof(pls::ReduceArgs), sizeof(pls::EigArgs),
+        PLS_HIP(hipEventCreateWithFlags(&b->ev_bp, hipEventDisableTiming));
+        PLS_HIP(hipEventCreateWithFlags(&b->ev_chg, hipEventDisableTiming));
+        const size_t sizes[8] = {sizeof(pls::GramArgs), sizeof(pls::ReduceArgs), sizeof(pls::EigArgs),
                                  sizeof(pls::BpArgs), sizeof(pls::SparseArgs), sizeof(DcArgs),
-                                 sizeof(pls::StatsArgs)};
+                                 sizeof(pls::StatsArgs), sizeof(pls::ChangeArgs)};
         size_t o = 0;
-        for (int k = 0; k < 7; ++k) {
+        for (int k = 0; k < 8; ++k) {
             b->off[k] = o;
             o += (2 * (size_t)count * sizes[k] + 255) / 256 * 256;
         }
-        b->off[7] = o;
+        b->off[8] = o;
         b->bytes = o + ((size_t)count * sizeof(int) + 255) / 256 * 256;
         void* dp = nullptr;
         PLS_HIP(hipMalloc(&dp, b->bytes));
@@ -1756,7 +1791,7 @@ void prior_ls_batch_destroy(prior_ls_batch* b) {
     b->clear_graphs();
     if (b->dev) (void)hipFree(b->dev);
     if (b->host) (void)hipHostFree(b->host);
-    hipEvent_t evs[] = {b->ev_fork, b->ev_join, b->ev_done, b->ev_h};
+    hipEvent_t evs[] = {b->ev_fork, b->ev_join, b->ev_done, b->ev_h, b->ev_bp, b->ev_chg};
     for (hipEvent_t e : evs)
         if (e) (void)hipEventDestroy(e);
     if (b->stream) (void)hipStreamDestroy(b->stream);

@@ -46,16 +46,12 @@ int gram_blocks(int N, int target) {
     return (N + vpb - 1) / vpb;
 }
 
-int launch_dc(int ny, int nz, bool stats, const DcArgs& a, hipStream_t s) {
+int launch_dc(int ny, int nz, const DcArgs& a, hipStream_t s) {
     DcArgs c = a;
-    fh_stream(s)->push([c, ny, nz, stats] {
+    fh_stream(s)->push([c, ny, nz] {
         const size_t P = (size_t)ny * nz, I = P * c.nx * c.nt;
         look(c.L, c.L ? I : 0);
         look(c.S, c.S ? I : 0);
-        if (stats) {
-            look(c.Lold, I);
-            look(c.Sold, I);
-        }
         look(c.sens, c.sens ? (size_t)c.nc * c.nx * P : 0);
         for (int t = 0; t < c.nt; ++t) {
             look(c.sidx + t * P, P);
@@ -63,7 +59,7 @@ int launch_dc(int ny, int nz, bool stats, const DcArgs& a, hipStream_t s) {
             look(c.dh + c.dh_off[t], n ? n : 1);
         }
         touch(c.C, I);
-        touch(c.part, (size_t)c.nx * c.nt * 4);
+        touch(c.part, (size_t)c.nx * c.nt);
         work_us(60);
     });
     return c.nx * c.nt;
@@ -216,10 +212,28 @@ int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
     return blocks;
 }
 
+int change_blocks(long n) {
+    const long b = ((n + 1) / 2 + 2047) / 2048;
+    return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
+void launch_change(const ChangeArgs& a, hipStream_t s) {
+    ChangeArgs c = a;
+    fh_stream(s)->push([c] {
+        look(c.L, (size_t)c.n);
+        look(c.S, (size_t)c.n);
+        look(c.Lold, (size_t)c.n);
+        look(c.Sold, (size_t)c.n);
+        touch(c.part, (size_t)change_blocks(c.n) * 2);
+        work_us(20);
+    });
+}
+
 void launch_stats(const StatsArgs& a, hipStream_t s) {
     StatsArgs c = a;
     fh_stream(s)->push([c] {
-        look(c.dc_part, (size_t)c.dc_blocks * 4);
+        look(c.dc_part, (size_t)c.dc_blocks);
+        look(c.ch_part, (size_t)c.ch_blocks * 2);
         look(c.sp_part, (size_t)c.sp_blocks);
         c.stat[0] = 1.0;
         c.stat[1] = 1.0;
@@ -278,11 +292,14 @@ void launch_stats_batched(const StatsArgs& a0, const Batched<StatsArgs>* bt, hip
         launch_stats(c, s);
     }
 }
-int launch_dc_batched(int ny, int nz, bool stats, const DcArgs& a0, const Batched<DcArgs>* bt,
-                      hipStream_t s) {
-    if (!bt) return launch_dc(ny, nz, stats, a0, s);
+void launch_change_batched(const ChangeArgs& a0, const Batched<ChangeArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_change(a0, s);
+    for (int b = 0; b < bt->count; ++b) launch_change(bt->args[b], s);
+}
+int launch_dc_batched(int ny, int nz, const DcArgs& a0, const Batched<DcArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_dc(ny, nz, a0, s);
     int r = 0;
-    for (int b = 0; b < bt->count; ++b) r = launch_dc(ny, nz, stats, bt->args[b], s);
+    for (int b = 0; b < bt->count; ++b) r = launch_dc(ny, nz, bt->args[b], s);
     return r;
 }
 
