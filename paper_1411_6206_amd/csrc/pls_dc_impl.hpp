@@ -282,16 +282,60 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
 }
 
 // Unitary inverse DFT along kx of every sampled (c, t, kz, ky) line, scaled by 1/sqrt(P),
-// scattered into the compact hybrid layout.
-template <class G>
-__global__ void __launch_bounds__(G::T) pls_xifft_kernel(XiArgs a) {
-    constexpr int Q = G::Q, NX = G::NY, PB = G::PB;
+// scattered into the compact hybrid layout.  A block takes PB consecutive lines (6144
+// points); a line's frame, coil and sample index are looked up once (binary search of the
+// line offsets) into LDS.  Lines are read whole (contiguous in kx); the results go through
+// an LDS transpose so that consecutive lanes write consecutive samples s of one x (the
+// lines of one (t, c) are consecutive in s).
+template <int NX>
+struct XiCfg {
+    static constexpr int Q = DcCfg<NX, 1>::Q;
+    static constexpr int PB = 6144 / NX;
+    using G = Geom<NX, 1, PB, Q, 0, 32, 1, false, false>;
+    static constexpr int LDT = NX + 1;   // transpose row pitch (odd: no bank-aligned columns)
+};
+
+template <int NX>
+__global__ void __launch_bounds__(XiCfg<NX>::G::T) pls_xifft_kernel(XiArgs a) {
+    using X = XiCfg<NX>;
+    using G = typename X::G;
+    constexpr int Q = G::Q, PB = G::PB, T = G::T, LDT = X::LDT;
     constexpr int R0 = radix_in<G>();
     constexpr int RL = radix_out<G>();
-    __shared__ float2 lds[G::LDS_ELEMS];
-    __shared__ float2 twx[NX];
+    constexpr int NLDS = (G::LDS_ELEMS > PB * LDT) ? G::LDS_ELEMS : PB * LDT;
+    __shared__ float2 lds[NLDS];
+    __shared__ float2 twt[G::TW_ELEMS];
+    __shared__ long long lsrc[PB];   // per line: kspace offset of kx = 0, or -1 (no line)
+    __shared__ int ldst[PB];         // per line: dh offset of x = 0
+    __shared__ int lstr[PB];         // per line: dh stride between x (nc * ns[t])
     const int tid = threadIdx.x;
-    for (int m = tid; m < NX; m += G::T) twx[m] = a.twx[m];
+    tw_fill<G>(twt, a.twx, a.twx, tid);
+    for (int pb = tid; pb < PB; pb += T) {
+        const int line = blockIdx.x * PB + pb;
+        long long src = -1;
+        int dst = 0, str = 0;
+        if (line < a.total_lines) {
+            // frame: the last t with line_off[t] <= line (it has lines, so ns[t] > 0)
+            int lo = 0, hi = a.nt - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.line_off[mid] <= line) lo = mid;
+                else hi = mid - 1;
+            }
+            const int t = lo;
+            const int rem = line - a.line_off[t];
+            const int ns = a.ns[t];
+            const int c = rem / ns;
+            const int sidx = rem - c * ns;
+            const int pos = a.plist[(size_t)t * a.P + sidx];
+            src = ((long long)(c * a.nt + t) * a.P + pos) * NX;
+            dst = a.dh_off[t] + c * ns + sidx;
+            str = a.nc * ns;
+        }
+        lsrc[pb] = src;
+        ldst[pb] = dst;
+        lstr[pb] = str;
+    }
     __syncthreads();
     float2 v[Q];
 #pragma unroll
@@ -300,46 +344,39 @@ __global__ void __launch_bounds__(G::T) pls_xifft_kernel(XiArgs a) {
         for (int r = 0; r < R0; ++r) {
             int pb, z, x;
             pos_in<G>(tid, i, r, pb, z, x);
-            const int line = blockIdx.x * PB + pb;
-            float2 val = make_float2(0.f, 0.f);
-            if (line < a.total_lines) {
-                int t = 0;
-                while (line >= a.line_off[t + 1]) ++t;
-                const int rem = line - a.line_off[t];
-                const int c = rem / a.ns[t];
-                const int s = rem % a.ns[t];
-                const int pos = a.plist[(size_t)t * a.P + s];
-                val = a.kspace[((size_t)(c * a.nt + t) * a.P + pos) * NX + x];
-            }
-            v[i * R0 + r] = val;
+            const long long src = lsrc[pb];
+            const float2 val = a.kspace[src < 0 ? 0 : src + x];
+            v[i * R0 + r] = src < 0 ? make_float2(0.f, 0.f) : val;
         }
-    // inverse transform; the plane machinery with NZ = 1 runs only y (= x here) passes
+    // inverse transform along the line (every pass is wave-local: NZ = 1)
     {
         constexpr int NP = G::NPY;
         sfor<NP>([&](auto pI) __attribute__((always_inline)) {
             constexpr int p = decltype(pI)::value;
             constexpr int R = G::PY.r[p];
             constexpr int LS = plan_prod(G::PY, p);
-            fft_pass<G, 0, R, LS, true, p == 0, p == NP - 1>(v, lds, twx, tid);
+            fft_pass<G, 0, R, LS, true, p == 0, p == NP - 1, tw_find(G::TW, R, LS)>(v, lds, twt,
+                                                                                   tid);
         });
     }
+    // transpose through LDS: the last pass left this wave's reads done (wave-local), but
+    // other waves may still read their lines, so wait for all before overwriting
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < Q / RL; ++i)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             int pb, z, x;
             pass_pos<G, 0, RL>(tid, i, r, pb, z, x);
-            const int line = blockIdx.x * PB + pb;
-            if (line < a.total_lines) {
-                int t = 0;
-                while (line >= a.line_off[t + 1]) ++t;
-                const int rem = line - a.line_off[t];
-                const int c = rem / a.ns[t];
-                const int s = rem % a.ns[t];
-                a.dh[a.dh_off[t] + ((size_t)x * a.nc + c) * a.ns[t] + s] =
-                    cscale(v[i * RL + r], a.scale);
-            }
+            lds[pb * LDT + x] = cscale(v[i * RL + r], a.scale);
         }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int e = tid + k * T;          // PB * NX = Q * T entries
+        const int pb = e % PB, x = e / PB;
+        if (lsrc[pb] >= 0) a.dh[ldst[pb] + (size_t)x * lstr[pb]] = lds[pb * LDT + x];
+    }
 }
 
 template <int NY, int NZ>
@@ -359,9 +396,9 @@ inline int dc_launch_t(const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s
 
 template <int NX>
 inline void xifft_launch_t(const XiArgs& a, hipStream_t s) {
-    using G = typename DcCfg<NX, 1>::G;
+    using G = typename XiCfg<NX>::G;
     const int grid = (a.total_lines + G::PB - 1) / G::PB;
-    if (grid > 0) hipLaunchKernelGGL((pls_xifft_kernel<G>), dim3(grid), dim3(G::T), 0, s, a);
+    if (grid > 0) hipLaunchKernelGGL((pls_xifft_kernel<NX>), dim3(grid), dim3(G::T), 0, s, a);
 }
 
 // Per-nz translation units (pls_dc_nz*.hip) instantiate the kernels; these return -1 when
