@@ -228,3 +228,33 @@ def test_gram_modes_svt_and_solve(case, mode):
     for k in ("L", "S", "X", "M"):
         e = rel(host(out[k]), r[k])
         assert e < tol, (mode, k, e)
+
+
+@pytest.mark.parametrize("geom", [dict(nx=16, ny=16, nz=4, nt=6, nc=2),
+                                  dict(nx=24, ny=48, nz=8, nt=5, nc=1)],
+                         ids=["3d_16x16x4_nt6_nc2", "3d_24x48x8_nt5_nc1"])
+def test_empty_and_fully_sampled_frames(geom):
+    # degenerate masks: frame 0 has no samples (no lines in the compact data, an empty
+    # residual) and frame 2 is fully sampled (every entry is replaced by data)
+    p = synth.small(**geom, accel=3, rank=2, nblobs=3, seed=21, levels=1, snr_db=None)
+    m = p.mask.copy()
+    m[0] = 0
+    m[2] = 1
+    p.mask = m
+    p.kspace = synth.sample(p.L_true + p.S_true, m, p.sens)
+    rng = np.random.default_rng(5)
+    X = p.L_true + p.S_true
+    Y = X + 0.1 * (rng.standard_normal(X.shape) + 1j * rng.standard_normal(X.shape))
+    Y = Y.astype(np.complex64).astype(np.complex128)
+    with handle(p, 1) as h:
+        out, st = load(h, p, max_iter=7, check_every=7)
+        M, r0 = h.op_dc(dev(Y))
+    r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=1,
+                     iters=7)
+    for k in ("L", "S", "X", "M"):
+        e = rel(host(out[k]), r[k])
+        assert e < TOL, (k, e)
+    assert st["resid_norm"] == pytest.approx(r["resid"][-1], rel=1e-4)
+    Mo, R = oracle.dc_step(Y, p.kspace, p.mask, p.sens)
+    assert rel(host(M), Mo) < TOL_OP
+    assert r0 == pytest.approx(np.linalg.norm(R), rel=1e-5)
