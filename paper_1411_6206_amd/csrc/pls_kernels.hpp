@@ -126,7 +126,7 @@ int launch_sparse(int levels, const SparseArgs& a, hipStream_t s);
 // workgroups (= partial sums) of the Haar sparse update for a max_grid cap
 int sparse_haar_blocks(int levels, int nx, int ny, int nz, int nt, int max_grid);
 int launch_sparse_tfft(const SparseArgs& a, hipStream_t s);
-int sparse_tfft_blocks(int N);
+int sparse_tfft_blocks(int N, int nt);   // workgroups (= partial sums) of the temporal update
 
 // Change of the iterate for the stopping test: per block, sum |Y - Yold|^2 and sum |Yold|^2
 // over its elements (Y = L + S, Yold = Lold + Sold, each formed in FP32, summed in FP64).

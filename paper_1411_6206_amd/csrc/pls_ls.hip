@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "pls_common.hpp"
+#include "pls_fft.hpp"
 #include "pls_kernels.hpp"
 
 namespace pls {
@@ -286,9 +287,18 @@ int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
 // 16 mb + 4 g + r in register (mb, r) of lane group g, which is the B operand that the
 // second product's instruction 4 mb + r takes from lane group g once the inverse operator's
 // columns are listed in that order (done on the host): no data moves between the two.
-int sparse_tfft_blocks(int N) {
-    const int tiles = (N + 63) / 64;
-    return tiles < 2048 ? tiles : 2048;
+// frame counts whose DFT factors into radices 2, 3, 4, 5 and 7 (an in-register FFT)
+static bool tfft_smooth(int nt) {
+    int m = nt;
+    for (int r : {2, 3, 5, 7})
+        while (m > 1 && m % r == 0) m /= r;
+    return nt >= 1 && nt <= 32 && m == 1;
+}
+
+int sparse_tfft_blocks(int N, int nt) {
+    const int per_block = tfft_smooth(nt) ? 256 : 64;   // voxels per workgroup and step
+    const int b = (N + per_block - 1) / per_block;
+    return b < 2048 ? b : 2048;
 }
 
 // The operands of both products live in LDS in fragment order, not in registers: 128
@@ -425,8 +435,91 @@ __global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
     if (threadIdx.x == 0) a.part[blockIdx.x] = s;
 }
 
+// The same step for frame counts with radices 2, 3, 4, 5 and 7 only: one thread per voxel
+// holds all its frames, U = X - L_prev, and takes the unitary DFT along them as an
+// in-register FFT (natural order in and out), shrinks, and transforms back.  Every load
+// and store of a wave covers 64 consecutive voxels of one frame.  The FFT needs a tenth of
+// the dense product's arithmetic, so the pass is bound by memory, not by the MFMA chain.
+template <int NT, class SRC>
+__global__ void __launch_bounds__(256) pls_tfft_fft_kernel(SRC src) {
+    if (src.skip()) return;
+    const SparseArgs a = src.get();
+    __shared__ double red[4];
+    const int N = a.nx * a.ny * a.nz;
+    const bool has_s = a.S != nullptr, has_w = a.w != nullptr;
+    const float2* Sp = has_s ? a.S : a.C;
+    const uint8_t* wp = has_w ? a.w : reinterpret_cast<const uint8_t*>(a.C);
+    const float scale = 1.0f / sqrtf((float)NT);
+    float l1 = 0.f;
+    for (int v = blockIdx.x * 256 + threadIdx.x; v < N; v += gridDim.x * 256) {
+        float2 x[NT];
+#pragma unroll
+        for (int f = 0; f < NT; ++f) {
+            const size_t i = (size_t)f * N + v;
+            const float2 c = a.C[i], sv = Sp[i], l = a.Lp[i];
+            x[f] = csub(has_s ? cadd(c, sv) : c, l);
+        }
+        dft<NT, false>(x);
+        uint8_t wq[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) wq[k] = wp[(size_t)k * N + v];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const float wk = has_w ? (float)wq[k] * (1.0f / 255.0f) : 0.0f;
+            const float tau = a.lambda_S * (1.0f - wk);
+            const float zr = x[k].x * scale, zi = x[k].y * scale;
+            const float m2 = fmaf(zr, zr, zi * zi);
+            const bool keep = m2 > tau * tau;
+            const float rm = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
+            // shrunk coefficient, with the inverse transform's 1/sqrt(NT) folded in
+            const float sc = keep ? fmaf(-tau, rm, 1.0f) * scale : 0.0f;
+            x[k] = make_float2(zr * sc, zi * sc);
+            l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
+            if (a.supp) a.supp[(size_t)k * N + v] = keep ? 255 : 0;
+        }
+        dft<NT, true>(x);
+#pragma unroll
+        for (int f = 0; f < NT; ++f) a.Sout[(size_t)f * N + v] = x[f];
+    }
+    const double sum = block_sum<256>((double)l1, red);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = sum;
+}
+
+template <int NT>
+static int tfft_fft_launch(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
+    const int grid = sparse_tfft_blocks(a.nx * a.ny * a.nz, NT);
+    PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_tfft_fft_kernel, NT);
+    return grid;
+}
+
 int launch_sparse_tfft_batched(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
-    const int grid = sparse_tfft_blocks(a.nx * a.ny * a.nz);
+    switch (a.nt) {
+        case 1: return tfft_fft_launch<1>(a, bt, s);
+        case 2: return tfft_fft_launch<2>(a, bt, s);
+        case 3: return tfft_fft_launch<3>(a, bt, s);
+        case 4: return tfft_fft_launch<4>(a, bt, s);
+        case 5: return tfft_fft_launch<5>(a, bt, s);
+        case 6: return tfft_fft_launch<6>(a, bt, s);
+        case 7: return tfft_fft_launch<7>(a, bt, s);
+        case 8: return tfft_fft_launch<8>(a, bt, s);
+        case 9: return tfft_fft_launch<9>(a, bt, s);
+        case 10: return tfft_fft_launch<10>(a, bt, s);
+        case 12: return tfft_fft_launch<12>(a, bt, s);
+        case 14: return tfft_fft_launch<14>(a, bt, s);
+        case 15: return tfft_fft_launch<15>(a, bt, s);
+        case 16: return tfft_fft_launch<16>(a, bt, s);
+        case 18: return tfft_fft_launch<18>(a, bt, s);
+        case 20: return tfft_fft_launch<20>(a, bt, s);
+        case 21: return tfft_fft_launch<21>(a, bt, s);
+        case 24: return tfft_fft_launch<24>(a, bt, s);
+        case 25: return tfft_fft_launch<25>(a, bt, s);
+        case 27: return tfft_fft_launch<27>(a, bt, s);
+        case 28: return tfft_fft_launch<28>(a, bt, s);
+        case 30: return tfft_fft_launch<30>(a, bt, s);
+        case 32: return tfft_fft_launch<32>(a, bt, s);
+    }
+    // other frame counts (a prime factor above 7): the dense product on MFMA
+    const int grid = sparse_tfft_blocks(a.nx * a.ny * a.nz, a.nt);
     if (a.nt <= 16)
         PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_tfft_sparse_kernel, 1);
     else

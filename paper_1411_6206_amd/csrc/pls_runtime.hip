@@ -111,13 +111,13 @@ struct Sizes {
 
 // Workgroups (= partial sums) of one sparse update under a tuning.
 int sparse_launch_blocks(const prior_ls_dims& d, const prior_ls_tuning& t) {
-    if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz);
+    if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz, d.nt);
     return pls::sparse_haar_blocks(d.wavelet_levels, d.nx, d.ny, d.nz, d.nt, t.sparse_grid);
 }
 
 // Workgroups of the sparse update at most (any tuning): the size of its partial sums.
 int sparse_blocks(const prior_ls_dims& d) {
-    if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz);
+    if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz, d.nt);
     const int J = d.wavelet_levels;
     const int B = 1 << J;
     const int ZW = d.nz > 1 ? B : 1;

@@ -189,13 +189,17 @@ int launch_sparse(int levels, const SparseArgs& a, hipStream_t s) {
     });
     return blocks;
 }
-int sparse_tfft_blocks(int N) {
-    const int tiles = (N + 63) / 64;
-    return tiles < 2048 ? tiles : 2048;
+int sparse_tfft_blocks(int N, int nt) {
+    int m = nt;
+    for (int r : {2, 3, 5, 7})
+        while (m > 1 && m % r == 0) m /= r;
+    const int per_block = (nt >= 1 && nt <= 32 && m == 1) ? 256 : 64;
+    const int b = (N + per_block - 1) / per_block;
+    return b < 2048 ? b : 2048;
 }
 int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
     SparseArgs c = a;
-    const int blocks = sparse_tfft_blocks(c.nx * c.ny * c.nz);
+    const int blocks = sparse_tfft_blocks(c.nx * c.ny * c.nz, c.nt);
     fh_stream(s)->push([c, blocks] {
         const size_t I = (size_t)c.nx * c.ny * c.nz * c.nt;
         look(c.C, I);

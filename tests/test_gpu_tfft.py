@@ -1,7 +1,9 @@
 """GPU parity of the temporal-Fourier sparsifying transform (PRIOR_LS_T_TFFT): the fused
-forward-DFT / shrink / inverse-DFT kernel on MFMA against the FP64 oracle, for window
-lengths on both operand sizes (nt <= 16 and 16 < nt <= 32), with and without prior
-weights, as one step, as a full solve and through the sliding-window recursion."""
+forward-DFT / shrink / inverse-DFT kernels against the FP64 oracle.  Window lengths whose
+DFT factors into radices 2, 3, 4, 5 and 7 take an in-register FFT per voxel; the others take
+the dense product on MFMA (both operand sizes: nt <= 16 and 16 < nt <= 32).  With and
+without prior weights, as one step, as a full solve and through the sliding-window
+recursion."""
 import numpy as np
 import pytest
 
@@ -62,6 +64,28 @@ def test_tfft_sparse_step(name, weights):
         S = h.op_sparse(_dev(Xm, torch.complex64), _dev(Lp, torch.complex64))
     e = _rel(S, want)
     print(f"{name} weights={weights}: op_sparse rel L2 {e:.2e}")
+    assert e < TOL_OP
+
+
+# frame counts of the in-register FFT (radices 2, 3, 4, 5, 7 and their products up to 32)
+# and of the MFMA fallback (prime factors 11, 13, 31)
+NTS = [2, 5, 7, 9, 12, 14, 21, 25, 27, 28, 32, 11, 26, 31]
+
+
+@pytest.mark.parametrize("nt", NTS)
+def test_tfft_sparse_step_frame_counts(nt):
+    p, w = _problem(dict(nx=16, ny=16, nz=1, nt=nt, nc=1, seed=60 + nt), True)
+    rng = np.random.default_rng(nt)
+    shp = (p.nt, p.nz, p.ny, p.nx)
+    Xm = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) * 0.05
+    Lp = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) * 0.02
+    want, _ = oracle.sparse_step(Xm, Lp, w, p.lambda_S, 0, transform="tfft")
+    k, m, s, wd = _args(p, w)
+    with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, transform="tfft") as h:
+        h.solve(k, m, s, wd, lambda_L=p.lambda_L, lambda_S=p.lambda_S, max_iter=0, outputs=())
+        S = h.op_sparse(_dev(Xm, torch.complex64), _dev(Lp, torch.complex64))
+    e = _rel(S, want)
+    print(f"nt={nt}: op_sparse rel L2 {e:.2e}")
     assert e < TOL_OP
 
 
