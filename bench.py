@@ -239,7 +239,8 @@ def serving_bench(budget_gib, forms):
 
 def batching_bench(steps, warmup):
     """Batched iterations (prior_ls_batch_*) of the small configurations: B problems of one
-    geometry advanced with one launch per kernel, against one problem alone."""
+    geometry advanced with one launch per kernel, against one problem alone (each tuned by
+    its autotuner first)."""
     import torch
     import synth
     import paper_1411_6206_amd as pls
@@ -251,7 +252,8 @@ def batching_bench(steps, warmup):
         kw = dict(lambda_L=p.lambda_L, lambda_S=p.lambda_S)
         # one problem on its own handle (hipGraph chunks of 10 iterations)
         with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) as h:
-            h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], max_iter=warmup, outputs=(), **kw)
+            h.tune(t["kspace"], t["mask"], t["sens"], t["prior_w"], check_every=10, **kw)
+            h.step(warmup, outputs=())
             torch.cuda.synchronize()
             a0 = time.perf_counter()
             h.step(steps, outputs=())
@@ -263,8 +265,10 @@ def batching_bench(steps, warmup):
             hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) for _ in range(B)]
             try:
                 with pls.Batch(hs) as b:
-                    prm = pls.make_params(max_iter=warmup, **kw)
-                    b.solve([t] * B, prm, outputs=())
+                    # the batch autotuner (sparse fork point and grid per problem), then
+                    # the warm-up iterations
+                    tb = b.tune([t] * B, pls.make_params(check_every=10, **kw))
+                    b.step(warmup, outputs=())
                     torch.cuda.synchronize()
                     a0 = time.perf_counter()
                     b.step(steps, outputs=())
@@ -274,7 +278,8 @@ def batching_bench(steps, warmup):
                 for hh in hs:
                     hh.close()
             rec["batches"][str(B)] = {"iterations_per_s": B * steps / el,
-                                      "speedup_vs_alone": B * steps / el / alone}
+                                      "speedup_vs_alone": B * steps / el / alone,
+                                      "tuning": {k: tb[k] for k in ("sparse_fork", "sparse_grid")}}
         res[f"c{cfg}"] = rec
         del t, p
         torch.cuda.empty_cache()

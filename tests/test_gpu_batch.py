@@ -188,3 +188,25 @@ def test_batch_rejects_mixed_geometry_and_reused_handles():
     finally:
         a.close()
         b.close()
+
+
+def test_batch_tune_leaves_the_problems_loaded_and_the_bits_unchanged():
+    # the batch autotuner changes only the sparse fork point and grid, neither of which
+    # changes an iterate: after tuning, a batched step of 6 equals each problem solved alone
+    name, g, J, tf = GEOMS[1]
+    ps = problems(g, J, 3, 160)
+    hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J, transform=tf) for p in ps]
+    try:
+        with pls.Batch(hs) as b:
+            prm = [pls.make_params(**params_for(p)) for p in ps]
+            choice = b.tune([pls.to_device(p) for p in ps], prm)
+            assert choice["sparse_fork"] in (0, 1) and choice["ms_per_iteration"] > 0
+            outs, sts = b.step(6)
+    finally:
+        for h in hs:
+            h.close()
+    for k, p in enumerate(ps):
+        o1, s1 = solo(p, J, tf)
+        assert sts[k]["iters"] == 6
+        for key in KEYS:
+            assert torch.equal(outs[k][key], o1[key]), (k, key)
