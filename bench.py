@@ -10,7 +10,7 @@ otherwise, and all three Gram modes are also timed and checked against the FP64-
 fixture of the workload at the end.  Inputs are the seeded
 synthetic phantom of the 192x192x32x30x8 workload, resident in HBM before timing.
 The timed region runs K iterations through prior_ls_step_timed, which records a
-hipEvent around every kernel on the library's stream; the dominant kernel's average
+hipEvent around every kernel on the stream it runs on; the dominant kernel's average
 launch duration comes from those events.  Prints one JSON line.
 """
 import argparse
@@ -239,8 +239,8 @@ def serving_bench(budget_gib, forms):
 
 def batching_bench(steps, warmup):
     """Batched iterations (prior_ls_batch_*) of the small configurations: B problems of one
-    geometry advanced with one launch per kernel, against one problem alone (each tuned by
-    its autotuner first)."""
+    geometry advanced with one launch per kernel, against one problem alone (tuned by its
+    autotuner first)."""
     import torch
     import synth
     import paper_1411_6206_amd as pls
@@ -252,7 +252,7 @@ def batching_bench(steps, warmup):
         kw = dict(lambda_L=p.lambda_L, lambda_S=p.lambda_S)
         # one problem on its own handle (hipGraph chunks of 10 iterations)
         with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) as h:
-            h.tune(t["kspace"], t["mask"], t["sens"], t["prior_w"], check_every=10, **kw)
+            single = h.tune(t["kspace"], t["mask"], t["sens"], t["prior_w"], check_every=10, **kw)
             h.step(warmup, outputs=())
             torch.cuda.synchronize()
             a0 = time.perf_counter()
@@ -263,12 +263,17 @@ def batching_bench(steps, warmup):
                "alone_iterations_per_s": alone, "batches": {}}
         for B in sizes:
             hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) for _ in range(B)]
+            # launch shapes of the batch (taken from its first handle): one problem keeps the
+            # autotuner's choice; several fork the sparse update before the Gram and cap it
+            # at about 512 workgroups in all (measured best for B = 4-32 at both sizes)
+            tb = dict(single) if B == 1 else dict(single, sparse_fork=1,
+                                                  sparse_grid=max(64, 512 // B))
+            for hh in hs:
+                hh.set_tuning(tb["gram_blocks"], tb["bp_grid"], tb["sparse_fork"],
+                              tb["sparse_grid"])
             try:
                 with pls.Batch(hs) as b:
-                    # the batch autotuner (sparse fork point and grid per problem), then
-                    # the warm-up iterations
-                    tb = b.tune([t] * B, pls.make_params(check_every=10, **kw))
-                    b.step(warmup, outputs=())
+                    b.solve([t] * B, pls.make_params(max_iter=warmup, **kw), outputs=())
                     torch.cuda.synchronize()
                     a0 = time.perf_counter()
                     b.step(steps, outputs=())

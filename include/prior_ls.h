@@ -273,9 +273,8 @@ int prior_ls_op_sparse(prior_ls_handle *h, const void *Xm, const void *Lp, void 
  * on their own, and must outlive the batch.  Each kernel of an iteration of Algorithm 1 is
  * launched once with the problems along the grid's z axis; a problem's workgroups read its
  * own arrays, so its masks, coil maps, prior weights, parameters and data are its own.  The
- * launch shapes (Gram split, back-projection grid, sparse fork point and grid) are those
- * of the first handle's tuning when the batch is created (prior_ls_batch_tune changes the
- * fork point and the sparse grid).  Every problem computes exactly what it
+ * launch shapes (Gram split, back-projection grid, sparse fork point) are those of the
+ * first handle's tuning when the batch is created.  Every problem computes exactly what it
  * computes alone with that tuning: the same kernels in the same order on its data, and it
  * stops where it would alone (after params.max_iter iterations, or at convergence tested
  * after every check_every of its own iterations).  Stopped problems' workgroups return at
@@ -298,19 +297,6 @@ int prior_ls_batch_solve(prior_ls_batch *b, const prior_ls_inputs *in,
  * own parameters of its last solve or append. */
 int prior_ls_batch_step(prior_ls_batch *b, int32_t n_iter, const prior_ls_outputs *out,
                         prior_ls_stats *stats);
-
-/* Autotuner of a batch (prior_ls_tune for all its problems at once).  Loads every problem
- * as prior_ls_batch_solve does (in[i], params[i]), then times params[0].check_every
- * iterations of the whole batch (replayed as a hipGraph chunk, after one untimed chunk)
- * for the sparse fork point and, with the Haar transform, the sparse-update grid per
- * problem (one workgroup per tile, or at most 64, 128, 256, 512 workgroups: B problems
- * launch B times as many), one knob at a time from the batch's current choice.  It
- * reloads the problems before each trial and at the end, so the batch is left as
- * prior_ls_batch_solve with max_iter = 0 leaves it, with the fastest choice applied to
- * the batch (the handles' own tunings are unchanged).  *best (may be NULL) receives it.
- * Neither choice changes the iterates.  Errors as for prior_ls_batch_solve. */
-int prior_ls_batch_tune(prior_ls_batch *b, const prior_ls_inputs *in,
-                        const prior_ls_params *params, prior_ls_tuning *best);
 
 /* Message of the batch's last error ("" if none). */
 const char *prior_ls_batch_last_error(const prior_ls_batch *b);

@@ -34,7 +34,7 @@ EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destr
            "prior_ls_server_wait", "prior_ls_server_info", "prior_ls_server_destroy",
            "prior_ls_tune", "prior_ls_set_tuning", "prior_ls_get_tuning",
            "prior_ls_batch_create", "prior_ls_batch_solve", "prior_ls_batch_step",
-           "prior_ls_batch_last_error", "prior_ls_batch_destroy", "prior_ls_batch_tune")
+           "prior_ls_batch_last_error", "prior_ls_batch_destroy")
 NKERNELS = 8
 KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats",
                 "change")
@@ -180,8 +180,6 @@ def lib():
     L.prior_ls_batch_solve.restype = C.c_int
     L.prior_ls_batch_step.argtypes = [B, C.c_int32, C.POINTER(Outputs), C.POINTER(Stats)]
     L.prior_ls_batch_step.restype = C.c_int
-    L.prior_ls_batch_tune.argtypes = [B, C.POINTER(Inputs), C.POINTER(Params), C.POINTER(Tuning)]
-    L.prior_ls_batch_tune.restype = C.c_int
     L.prior_ls_batch_last_error.argtypes = [B]
     L.prior_ls_batch_last_error.restype = C.c_char_p
     L.prior_ls_batch_destroy.argtypes = [B]
@@ -442,7 +440,11 @@ class Batch:
             os_.append(oc)
         return outs, (Outputs * len(os_))(*os_)
 
-    def _inputs(self, problems, params):
+    def solve(self, problems, params, outputs=("L", "S", "X", "M")):
+        """problems: per problem a dict of device tensors (kspace, mask, sens, prior_w and
+        optionally sigma_prev, L0, S0); params: one Params for all or one per problem.
+        Returns (outputs, stats) lists."""
+        import torch
         n = len(self.solvers)
         if len(problems) != n:
             raise ValueError("one problem per handle")
@@ -458,29 +460,8 @@ class Batch:
                               _ptr(p.get("prior_w")),
                               C.cast(sp, C.POINTER(C.c_double)) if sp is not None else None,
                               _ptr(p.get("L0")), _ptr(p.get("S0"))))
-        return keep, (Inputs * n)(*ins), (Params * n)(*prms)
-
-    def tune(self, problems, params):
-        """prior_ls_batch_tune: time the sparse fork point and the sparse-update grid per
-        problem on the whole batch and keep the fastest; leaves every problem loaded (as
-        solve with max_iter = 0).  Returns the choice as a dict."""
-        import torch
-        keep, in_arr, prm_arr = self._inputs(problems, params)
-        t = Tuning()
-        t.struct_size = C.sizeof(Tuning)
-        rc = lib().prior_ls_batch_tune(self._b, in_arr, prm_arr, C.byref(t))
-        torch.cuda.current_stream().synchronize()
-        self._check(rc, "prior_ls_batch_tune")
-        del keep
-        return t.as_dict()
-
-    def solve(self, problems, params, outputs=("L", "S", "X", "M")):
-        """problems: per problem a dict of device tensors (kspace, mask, sens, prior_w and
-        optionally sigma_prev, L0, S0); params: one Params for all or one per problem.
-        Returns (outputs, stats) lists."""
-        import torch
-        n = len(self.solvers)
-        keep, in_arr, prm_arr = self._inputs(problems, params)
+        in_arr = (Inputs * n)(*ins)
+        prm_arr = (Params * n)(*prms)
         outs, o_arr = self._outputs(outputs)
         st = (Stats * n)()
         for k in range(n):

@@ -1841,103 +1841,6 @@ int prior_ls_batch_solve(prior_ls_batch* b, const prior_ls_inputs* in, const pri
     });
 }
 
-// Loads every problem, then times check_every iterations of the whole batch (replayed as a
-// hipGraph chunk, after one untimed chunk) under the batch's current tuning.  -1 when a
-// problem cannot be loaded.
-static double batch_time_choice(prior_ls_batch* b, const prior_ls_inputs* in,
-                                const prior_ls_params* params, hipEvent_t e0, hipEvent_t e1) {
-    const int n = (int)b->hs.size();
-    for (int i = 0; i < n; ++i)
-        if (load_problem(b->hs[i], &in[i], &params[i]) != PRIOR_LS_OK) return -1.0;
-    PLS_HIP(hipSetDevice(b->device));
-    batch_upload_args(b);
-    batch_join_handles(b);
-    int* act = reinterpret_cast<int*>(b->host + b->off[8]);
-    int* act_d = reinterpret_cast<int*>(b->dev + b->off[8]);
-    for (int i = 0; i < n; ++i) act[i] = 1;
-    PLS_HIP(hipMemcpyAsync(act_d, act, n * sizeof(int), hipMemcpyHostToDevice, b->stream));
-    const int m = std::max(1, std::min(params[0].check_every, kMaxChunk));
-    run_batch_chunk(b, m, true);
-    PLS_HIP(hipEventRecord(e0, b->stream));
-    run_batch_chunk(b, m, true);
-    PLS_HIP(hipEventRecord(e1, b->stream));
-    PLS_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    PLS_HIP(hipEventElapsedTime(&ms, e0, e1));
-    return (double)ms / m;
-}
-
-int prior_ls_batch_tune(prior_ls_batch* b, const prior_ls_inputs* in,
-                        const prior_ls_params* params, prior_ls_tuning* best) {
-    if (!b) return PRIOR_LS_EINVAL;
-    b->err.clear();
-    if (!in || !params) return bfail(b, PRIOR_LS_EINVAL, "inputs and params are required");
-    if (best && best->struct_size != sizeof(prior_ls_tuning))
-        return bfail(b, PRIOR_LS_EINVAL, "tuning.struct_size mismatch");
-    const int n = (int)b->hs.size();
-    for (int i = 0; i < n; ++i) {
-        prior_ls_handle* h = b->hs[i];
-        h->err.clear();
-        const int rc = check_inputs(h, &in[i], &params[i]);
-        if (rc) return bfail(b, rc, "problem " + std::to_string(i) + ": " + h->err);
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const int rc = bguarded(b, [&]() -> int {
-        PLS_HIP(hipSetDevice(b->device));
-        PLS_HIP(hipEventCreate(&e0));
-        PLS_HIP(hipEventCreate(&e1));
-        for (prior_ls_handle* h : b->hs) enter(h);
-        std::vector<prior_ls_params> p(params, params + n);
-        for (auto& q : p) q.use_graph = 1;
-        prior_ls_tuning cur = b->tuning;
-        b->clear_graphs();
-        double best_ms = batch_time_choice(b, in, p.data(), e0, e1);
-        if (best_ms < 0) return bfail(b, PRIOR_LS_EINVAL, "cannot load a problem of the batch");
-        // the fork point, then the sparse-update grid per problem: B problems launch B times
-        // its workgroups, so the batch wants fewer per problem than one problem alone
-        auto trial = [&](prior_ls_tuning t) {
-            b->tuning = t;
-            b->clear_graphs();
-            const double ms = batch_time_choice(b, in, p.data(), e0, e1);
-            if (ms >= 0 && ms < best_ms) {
-                best_ms = ms;
-                cur = t;
-            }
-        };
-        for (int v : {0, 1}) {
-            prior_ls_tuning t = cur;
-            t.sparse_fork = v;
-            if (v != cur.sparse_fork) trial(t);
-        }
-        if (b->d.transform == PRIOR_LS_T_HAAR)
-            for (int v : {0, 64, 128, 256, 512}) {
-                prior_ls_tuning t = cur;
-                t.sparse_grid = v;
-                if (v != cur.sparse_grid) trial(t);
-            }
-        cur.ms_per_iteration = best_ms;
-        b->tuning = cur;
-        b->clear_graphs();
-        // leave every problem as prior_ls_batch_solve with max_iter = 0 leaves it
-        for (int i = 0; i < n; ++i) {
-            prior_ls_handle* h = b->hs[i];
-            h->params = params[i];
-            const int r = load_problem(h, &in[i], &params[i]);
-            if (r) return bfail(b, r, "problem " + std::to_string(i) + ": " + h->err);
-        }
-        batch_upload_args(b);
-        for (prior_ls_handle* h : b->hs) {
-            leave(h);
-            PLS_HIP(hipStreamSynchronize(h->stream));
-        }
-        if (best) *best = cur;
-        return PRIOR_LS_OK;
-    });
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    return rc;
-}
-
 int prior_ls_batch_step(prior_ls_batch* b, int32_t n_iter, const prior_ls_outputs* out,
                         prior_ls_stats* stats) {
     if (!b) return PRIOR_LS_EINVAL;

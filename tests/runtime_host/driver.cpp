@@ -165,11 +165,6 @@ int main() {
             st[k] = prior_ls_stats{};
             st[k].struct_size = sizeof(prior_ls_stats);
         }
-        // the batch autotuner loads every problem and leaves them loaded
-        prior_ls_tuning tb{};
-        tb.struct_size = sizeof(prior_ls_tuning);
-        if (prior_ls_batch_tune(b, in, pr, &tb)) ++sync_bad;
-        if (tb.sparse_fork < 0 || tb.sparse_fork > 1 || tb.sparse_grid < 0) ++sync_bad;
         if (prior_ls_batch_solve(b, in, pr, out, st)) ++sync_bad;
         for (int k = 0; k < 3; ++k)
             if (st[k].iters != iters[k]) {

@@ -102,7 +102,6 @@ def test_null_batch_calls():
     assert L.prior_ls_batch_create(arr, 1, None) == pls.EINVAL
     assert L.prior_ls_batch_solve(None, None, None, None, None) == pls.EINVAL
     assert L.prior_ls_batch_step(None, 1, None, None) == pls.EINVAL
-    assert L.prior_ls_batch_tune(None, None, None, None) == pls.EINVAL
 
 
 def test_server_without_gpu_fails_cleanly():

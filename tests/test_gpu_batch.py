@@ -190,6 +190,9 @@ def test_batch_rejects_mixed_geometry_and_reused_handles():
         b.close()
 
 
+@pytest.mark.skip(reason="the batch autotuner was withdrawn: the process aborted (exit 134, no "
+                         "GPU fault) in the destroy of a new handle after this test's tuned "
+                         "batch, with no cause found; prior_ls_batch_tune is not exported")
 def test_batch_tune_leaves_the_problems_loaded_and_the_bits_unchanged():
     # the batch autotuner changes only the sparse fork point and grid, neither of which
     # changes an iterate: after tuning, a batched step of 6 equals each problem solved alone
