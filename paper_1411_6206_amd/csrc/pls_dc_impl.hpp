@@ -31,7 +31,7 @@ struct DcCfg {
     // Y = L + S is parked in the output array between coils (not kept in registers), and
     // the frame's sample indices of the thread's points stay in registers (two per
     // register) instead of being looked up in LDS for every coil
-    using G = Geom<NY, NZ, PB, Q, 0, 32, 2, false, true>;
+    using G = Geom<NY, NZ, PB, Q, 0, 32, 2>;
 };
 
 // Register distribution of a first pass of radix R along axis AX: element (i, r) of a
@@ -77,7 +77,6 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
     using DL = Dist<G, AXL, RL>;
     __shared__ float2 lds[G::LDS_ELEMS];
     __shared__ float2 twt[G::TW_ELEMS];      // per-pass twiddle tables
-    __shared__ int16_t smap[G::SIDREG ? 1 : P];  // sample index of (kz, ky) in this frame, or -1
     __shared__ float2 dhs[NBUF][NST];
     __shared__ double red[T / kWave];
     const int tid = threadIdx.x;
@@ -104,13 +103,11 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
     const int nst = a.ns[t];
     const float2* dh_t = a.dh + a.dh_off[t];
     const int16_t* sid_t = a.sidx + t * P;
-    if constexpr (!G::SIDREG)
-        for (int m = tid; m < P; m += T) smap[m] = sid_t[m];
     // sample index (or -1) of each point of the thread in the distribution the forward
     // transform leaves, packed two per register; -1 also marks points of absent planes
-    uint32_t sidp[G::SIDREG ? Q / 2 : 1];
-    if constexpr (G::SIDREG) {
-        static_assert(Q % 2 == 0, "sample indices are packed in pairs");
+    static_assert(Q % 2 == 0, "sample indices are packed in pairs");
+    uint32_t sidp[Q / 2];
+    {
         const DL dl(tid);
 #pragma unroll
         for (int i = 0; i < DL::NB; ++i) {
@@ -143,7 +140,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
     float2 dnext[NSTT];
     stage_load(0, dnext);
 
-    float2 Y[G::KEEPY ? Q : 1], acc[Q], v[Q];
+    float2 acc[Q], v[Q];
     // Y = L + S at element gi
     auto form_y = [&](int gi) __attribute__((always_inline)) {
         const float2 l = Lp[gi], sv = Sp[gi];
@@ -152,16 +149,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
         return yv;
     };
 #pragma unroll
-    for (int i = 0; i < D0::NB; ++i) {
-        const int pbc = min(d0.pb[i], nvalid - 1);
-        const int o = plane0 + pbc * P + d0.rel[i];
-#pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            const int q = i * R0 + r;
-            if constexpr (G::KEEPY) Y[q] = form_y(o + r * D0::STEP);
-            acc[q] = make_float2(0.f, 0.f);
-        }
-    }
+    for (int q = 0; q < Q; ++q) acc[q] = make_float2(0.f, 0.f);
 
     double res2 = 0.0;
     __syncthreads();  // twiddle tables and sample map visible
@@ -191,21 +179,17 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 const int q = i * R0 + r;
+                // Y = L + S is formed at the first coil and parked in the output array (each
+                // thread rereads only the entries it wrote), so the later coils read one
+                // array instead of two.  A single coil needs no parking; the wide
+                // configurations (multi-coil volumes) park unconditionally
                 float2 yv;
-                if constexpr (G::KEEPY) {
-                    yv = Y[q];
+                const int gi = plane0 + o + r * D0::STEP;
+                if (c == 0) {
+                    yv = form_y(gi);
+                    if (own && (Q >= 24 || a.nc > 1)) a.C[gi] = yv;
                 } else {
-                    // Y = L + S is formed at the first coil and parked in the output array
-                    // (each thread rereads only the entries it wrote), so the later coils
-                    // read one array instead of two.  A single coil needs no parking; the
-                    // wide configurations (multi-coil volumes) park unconditionally
-                    const int gi = plane0 + o + r * D0::STEP;
-                    if (c == 0) {
-                        yv = form_y(gi);
-                        if (own && (Q >= 24 || a.nc > 1)) a.C[gi] = yv;
-                    } else {
-                        yv = a.C[gi];
-                    }
+                    yv = a.C[gi];
                 }
                 const float2 sv = sc[o + r * D0::STEP];
                 v[q] = cmul(sv, yv);
@@ -224,18 +208,11 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
 #pragma unroll
             for (int i = 0; i < DL::NB; ++i) {
                 const int pbc = min(el.pb[i], nvalid - 1);
-                const bool ok = el.pb[i] < nvalid;
                 const float2* dh_p = dh_t + ((x0 + pbc) * a.nc + c) * nst;
 #pragma unroll
                 for (int r = 0; r < RL; ++r) {
                     const int q = i * RL + r;
-                    int s;
-                    if constexpr (G::SIDREG) {
-                        s = (int)(int16_t)(sidp[q / 2] >> (16 * (q % 2)));
-                    } else {
-                        s = smap[el.rel[i] + r * DL::STEP];
-                        s = ok ? s : -1;
-                    }
+                    const int s = (int)(int16_t)(sidp[q / 2] >> (16 * (q % 2)));
                     const int sc0 = s < 0 ? 0 : s;
                     float2 d;
                     if constexpr (kStaged) d = dhs[buf][pbc * nst + sc0];
@@ -292,7 +269,7 @@ template <int NX>
 struct XiCfg {
     static constexpr int Q = DcCfg<NX, 1>::Q;
     static constexpr int PB = 6144 / NX;
-    using G = Geom<NX, 1, PB, Q, 0, 32, 1, false, false>;
+    using G = Geom<NX, 1, PB, Q, 0, 32, 1>;
     static constexpr int LDT = NX + 1;   // transpose row pitch (odd: no bank-aligned columns)
 };
 

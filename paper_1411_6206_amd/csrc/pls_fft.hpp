@@ -189,13 +189,10 @@ constexpr int tw_find(const TwPlan& t, int R, int LS) {
 }
 
 // ---------------------------------------------------------------- plane geometry
-template <int NY_, int NZ_, int PB_, int Q_, int PADY_, int RMAX_ = 32, int MINW_ = 1,
-          bool KEEPY_ = true, bool SIDREG_ = false>
+template <int NY_, int NZ_, int PB_, int Q_, int PADY_, int RMAX_ = 32, int MINW_ = 1>
 struct Geom {
-    static constexpr bool SIDREG = SIDREG_; // data-consistency: sample indices in registers
     static constexpr int NY = NY_, NZ = NZ_, PB = PB_, Q = Q_;
     static constexpr int MINW = MINW_;   // launch bound: minimum waves per SIMD
-    static constexpr bool KEEPY = KEEPY_; // data-consistency: keep Y in registers across coils
     static constexpr int P = NY * NZ;
     static constexpr int T = PB * P / Q;
     // LDS layout: plane pb, row z, column y at pb * PS + z * LDY + y.  Every access of a
