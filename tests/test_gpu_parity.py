@@ -258,3 +258,29 @@ def test_empty_and_fully_sampled_frames(geom):
     Mo, R = oracle.dc_step(Y, p.kspace, p.mask, p.sens)
     assert rel(host(M), Mo) < TOL_OP
     assert r0 == pytest.approx(np.linalg.norm(R), rel=1e-5)
+
+
+# the largest planes: 256 x 32 (8192 points, 512-thread blocks), 128 x 32 and 96 x 32
+# (radix 3 along y), each with more than one coil
+MAX_PLANES = [dict(nx=16, ny=256, nz=32, nt=3, nc=2), dict(nx=16, ny=128, nz=32, nt=4, nc=3),
+              dict(nx=16, ny=96, nz=32, nt=3, nc=2)]
+
+
+@pytest.mark.parametrize("geom", MAX_PLANES, ids=["256x32", "128x32", "96x32"])
+def test_largest_planes_match_oracle(geom):
+    p = synth.small(**geom, accel=4, rank=2, nblobs=3, seed=23, levels=1)
+    rng = np.random.default_rng(6)
+    Y = p.X_true + 0.1 * (rng.standard_normal(p.X_true.shape)
+                          + 1j * rng.standard_normal(p.X_true.shape))
+    Y = Y.astype(np.complex64).astype(np.complex128)
+    with handle(p, 1) as h:
+        out, st = load(h, p, max_iter=4, check_every=2)
+        M, r0 = h.op_dc(dev(Y))
+    r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=1,
+                     iters=4)
+    for k in ("L", "S", "X", "M"):
+        e = rel(host(out[k]), r[k])
+        assert e < TOL, (k, e)
+    Mo, R = oracle.dc_step(Y, p.kspace, p.mask, p.sens)
+    assert rel(host(M), Mo) < TOL_OP
+    assert r0 == pytest.approx(np.linalg.norm(R), rel=1e-5)
