@@ -112,3 +112,26 @@ def test_schedules_give_identical_bits():
             h.close()
     for key in ("L", "S", "X", "M"):
         assert torch.equal(outs[0][key], ref[0][key]), key
+
+
+@pytest.mark.parametrize("fork", [0, 1, 2])
+def test_step_timed_iterates_like_step(fork):
+    # the benchmark's timed path launches the kernels directly with events around each one
+    # (no hipGraph), statistics on the last iteration: the iterate must be the one a plain
+    # solve of as many iterations reaches, under every schedule
+    p = synth.small(nx=24, ny=32, nz=8, nt=7, nc=2, seed=34)
+    k, m, s, w = _inputs(p)
+    prm = dict(lambda_L=p.lambda_L, lambda_S=p.lambda_S)
+    with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc) as h:
+        h.set_tuning(gram_blocks=256, bp_grid=1024, sparse_fork=fork, sparse_grid=0)
+        want, st_want = h.solve(k, m, s, w, max_iter=5, check_every=5, **prm)
+        h.solve(k, m, s, w, max_iter=0, outputs=(), **prm)
+        kms, st = h.step_timed(5)
+        got, _ = h.step(0)
+    for key in ("L", "S", "X", "M"):
+        assert torch.equal(got[key], want[key]), key
+    assert st["iters"] == 5
+    assert st["resid_norm"] == st_want["resid_norm"]
+    assert st["rel_change"] == st_want["rel_change"]
+    assert set(kms) == set(pls.KERNEL_NAMES)
+    assert all(v >= 0 for v in kms.values()) and kms["data_consistency"] > 0
