@@ -26,6 +26,14 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 __device__ __forceinline__ float2 cmul_pi(float2 a) { return make_float2(-a.y, a.x); }
 
+// 1 - w for a prior weight w = q / 255 (the threshold factor of the support-aware shrink),
+// formed as (255 - q) / 255 so that a full weight gives exactly 0.  Written as 1 - q / 255,
+// the compiler contracts it into fma(-q, 1/255, 1), whose unrounded product leaves -5.9e-8 at
+// q = 255: a negative threshold and a negative term in the weighted l1 norm.
+__device__ __forceinline__ float weight_complement(unsigned q) {
+    return (float)(255u - q) * (1.0f / 255.0f);
+}
+
 // ---------------------------------------------------------------- compile-time trigonometry
 // Taylor series after reduction to [-pi, pi]; used only in constant expressions, so the
 // twiddle constants of the in-register DFTs are exact double values rounded to float.

@@ -226,15 +226,15 @@ __global__ void __launch_bounds__(256) pls_sparse_kernel(SRC src) {
 #pragma unroll
         for (int k = 0; k < XW; ++k) {
             // soft threshold of the complex magnitude: u (1 - tau / |u|) where |u| > tau
-            const float wk = has_w ? (float)wq[k] * (1.0f / 255.0f) : 0.0f;
-            const float tau = a.lambda_S * (1.0f - wk);
+            const float omw = has_w ? weight_complement(wq[k]) : 1.0f;
+            const float tau = a.lambda_S * omw;
             const float2 u = v[k];
             const float m2 = fmaf(u.x, u.x, u.y * u.y);
             const bool keep = valid && m2 > tau * tau;
             const float rm = __builtin_amdgcn_rsqf(keep ? m2 : 1.0f);
             const float sc = fmaf(-tau, rm, 1.0f);
             v[k] = keep ? make_float2(u.x * sc, u.y * sc) : make_float2(0.f, 0.f);
-            l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
+            l1 = fmaf(omw, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
             if (a.supp && valid) a.supp[gi[k]] = keep ? 255 : 0;
         }
         for (int l = J - 1; l >= 0; --l) haar_level<J, ZA>(v, l, yl, zl, lane);
@@ -389,8 +389,8 @@ __global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
             for (int r = 0; r < 4; ++r) {
                 const int f = 16 * mb + 4 * g + r;
                 const bool valid = f < nt && v < N;
-                const float wk = has_w ? (float)wq[mb][r] * (1.0f / 255.0f) : 0.0f;
-                const float tau = a.lambda_S * (1.0f - wk);
+                const float omw = has_w ? weight_complement(wq[mb][r]) : 1.0f;
+                const float tau = a.lambda_S * omw;
                 const float zr = z[mb][r], zi = z[mb + MB / 2][r];
                 const float m2 = fmaf(zr, zr, zi * zi);
                 const bool keep = valid && m2 > tau * tau;
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
                 const float sc = keep ? fmaf(-tau, rm, 1.0f) : 0.0f;
                 z[mb][r] = zr * sc;
                 z[mb + MB / 2][r] = zi * sc;
-                l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
+                l1 = fmaf(omw, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
                 if (a.supp && valid) a.supp[f * N + v] = keep ? 255 : 0;
             }
         // S = F^H Z_s: instruction 4 mb + r takes register (mb, r) as its B operand
@@ -465,8 +465,8 @@ __global__ void __launch_bounds__(256) pls_tfft_fft_kernel(SRC src) {
         for (int k = 0; k < NT; ++k) wq[k] = wp[(size_t)k * N + v];
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
-            const float wk = has_w ? (float)wq[k] * (1.0f / 255.0f) : 0.0f;
-            const float tau = a.lambda_S * (1.0f - wk);
+            const float omw = has_w ? weight_complement(wq[k]) : 1.0f;
+            const float tau = a.lambda_S * omw;
             const float zr = x[k].x * scale, zi = x[k].y * scale;
             const float m2 = fmaf(zr, zr, zi * zi);
             const bool keep = m2 > tau * tau;
@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(256) pls_tfft_fft_kernel(SRC src) {
             // shrunk coefficient, with the inverse transform's 1/sqrt(NT) folded in
             const float sc = keep ? fmaf(-tau, rm, 1.0f) * scale : 0.0f;
             x[k] = make_float2(zr * sc, zi * sc);
-            l1 = fmaf(1.0f - wk, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
+            l1 = fmaf(omw, keep ? fmaf(m2, rm, -tau) : 0.f, l1);
             if (a.supp) a.supp[(size_t)k * N + v] = keep ? 255 : 0;
         }
         dft<NT, true>(x);

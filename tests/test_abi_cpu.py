@@ -190,3 +190,15 @@ def test_valid_dims_without_gpu_fail_cleanly():
     rc, h, msg = _create()
     assert rc == pls.EHIP
     assert h.value is None
+
+
+def test_accepted_shapes_are_exactly_the_advertised_instances():
+    # the (ny, nz) planes and readout lengths create accepts are the instances the parity
+    # sweep (tests/test_gpu_sweep.py) compares with the oracle, no more and no fewer
+    from instances import PLANES, READOUT_NX
+    acc = {(ny, nz) for ny in range(1, 300) for nz in range(1, 40)
+           if pls.plan_bytes(16, ny, nz, 3, 2, wavelet_levels=0) > 0}
+    assert acc == set(PLANES)
+    acc_x = {nx for nx in range(1, 300) if pls.plan_bytes(nx, 16, 4, 3, 2, wavelet_levels=0) > 0}
+    assert acc_x == set(READOUT_NX)
+    assert len(PLANES) == 50
