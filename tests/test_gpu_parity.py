@@ -166,6 +166,11 @@ def test_solve_matches_oracle(case, iters):
     assert st["nuclear_norm"] == pytest.approx(r["nuclear"][-1], rel=1e-4)
     assert st["rel_change"] == pytest.approx(r["rel_change"][-1], rel=1e-3)
     np.testing.assert_allclose(st["sigma"], r["sigma"][-1], rtol=1e-4, atol=1e-5 * r["sigma"][-1][0])
+    # the reported objective 0.5 ||r||^2 + tau_L ||L||_* + lambda_S ||(1 - w) T(S)||_1 and its
+    # parts
+    assert st["tau_L"] == pytest.approx(r["tau_L"][-1], rel=1e-4)
+    assert st["l1_weighted"] == pytest.approx(r["l1w"][-1], rel=1e-4)
+    assert st["objective"] == pytest.approx(r["objective"][-1], rel=1e-4)
 
 
 def test_solve_with_sigma_prior_and_warm_start(case):
