@@ -29,13 +29,30 @@ SQRT_HALF = np.sqrt(0.5)
 # Section 2: the acquisition operator A (here E) and its adjoint (the paper writes the
 # adjoint as A^{-1}, Notations paragraph).
 # --------------------------------------------------------------------------------------
+# The library call that evaluates the DFT: numpy.fft by default; set_fft_workers(n) with
+# n > 1 evaluates the same unitary DFT with scipy.fft on n threads (for timing the oracle on
+# many cores; the tests keep the default).
+_FFT_WORKERS = None
+
+
+def set_fft_workers(n):
+    global _FFT_WORKERS
+    _FFT_WORKERS = int(n) if n and int(n) > 1 else None
+
+
 def fft3(x):
     """Unitary, unshifted 3D DFT over the last three axes (z, y, x); index 0 is DC."""
+    if _FFT_WORKERS:
+        import scipy.fft
+        return scipy.fft.fftn(x, axes=(-3, -2, -1), norm="ortho", workers=_FFT_WORKERS)
     return np.fft.fftn(x, axes=(-3, -2, -1), norm="ortho")
 
 
 def ifft3(x):
     """Inverse of fft3 (its adjoint, since it is unitary)."""
+    if _FFT_WORKERS:
+        import scipy.fft
+        return scipy.fft.ifftn(x, axes=(-3, -2, -1), norm="ortho", workers=_FFT_WORKERS)
     return np.fft.ifftn(x, axes=(-3, -2, -1), norm="ortho")
 
 
@@ -239,7 +256,7 @@ def dc_step(Y, d, mask, sens):
 
 def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=None,
           levels=2, iters=50, tol=0.0, L0=None, S0=None, lambda_L_relative=True,
-          svt_fn=None, transform="haar"):
+          svt_fn=None, transform="haar", on_iteration=None):
     """Algorithm 1 (Priori L+S), step by step, for `iters` iterations or until the
     relative change of the solution drops below tol (Section 3, stopping rule).
 
@@ -251,7 +268,9 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
     per-iteration statistics, and what the next time instance takes as a-priori
     knowledge (Section 3): supp, 255 on the support of T(S) (the coefficients that survive
     the last shrinkage, canonical layout; all 0 when no iteration ran) and sigma_L, the
-    singular values of the returned L (descending; zeros when no iteration ran)."""
+    singular values of the returned L (descending; zeros when no iteration ran).
+    on_iteration (optional) is called with 0 once the set-up is done and with k after
+    iteration k (timing only; it sees nothing of the state)."""
     svt_fn = svt if svt_fn is None else svt_fn
     d = np.asarray(d, np.complex128)
     shape = d.shape[1:]
@@ -268,6 +287,8 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
     supp = np.zeros(shape, np.uint8)
     sigma_L = np.zeros(shape[0])
     it = 0
+    if on_iteration is not None:
+        on_iteration(0)
     for it in range(1, iters + 1):
         Y_prev = L + S
         # step (1) + (2)
@@ -295,6 +316,8 @@ def solve(d, mask, sens, prior_w, lambda_L, lambda_S, lambda_p=0.0, sigma_prev=N
         hist["objective"].append(0.5 * resid ** 2 + tau_L * nuc + lambda_S * l1w)
         hist["sigma"].append(sigma)
         hist["tau_L"].append(tau_L)
+        if on_iteration is not None:
+            on_iteration(it)
         if tol > 0 and rel < tol:
             break
     return dict(L=L, S=S, X=L + S, M=M, iters=it, supp=supp, sigma_L=np.asarray(sigma_L),

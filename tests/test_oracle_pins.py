@@ -113,12 +113,36 @@ def _dft(n):
     return np.exp(-2j * np.pi * np.outer(k, k) / n) / np.sqrt(n)
 
 
-def test_p5_fft_matches_explicit_dft_matrix():
-    x = cg((3, 2, 4, 4))
-    Fz, Fy, Fx = _dft(2), _dft(4), _dft(4)
+@pytest.mark.parametrize("workers", [None, 4], ids=["numpy", "scipy_threads"])
+def test_p5_fft_matches_explicit_dft_matrix(workers):
+    # both library calls the oracle can use (numpy.fft; scipy.fft on threads, for timing)
+    x = cg((3, 2, 4, 6))
+    Fz, Fy, Fx = _dft(2), _dft(4), _dft(6)
     want = np.einsum("az,by,cx,tzyx->tabc", Fz, Fy, Fx, x)
-    np.testing.assert_allclose(oracle.fft3(x), want, atol=1e-14)
-    np.testing.assert_allclose(oracle.ifft3(want), x, atol=1e-14)
+    try:
+        oracle.set_fft_workers(workers)
+        np.testing.assert_allclose(oracle.fft3(x), want, atol=1e-14)
+        np.testing.assert_allclose(oracle.ifft3(want), x, atol=1e-14)
+        y = cg((2, 8, 12, 10))
+        np.testing.assert_allclose(oracle.ifft3(oracle.fft3(y)), y, atol=1e-13)
+    finally:
+        oracle.set_fft_workers(None)
+
+
+def test_threaded_fft_gives_the_same_iterate():
+    # the timing configuration of the oracle computes the same iteration
+    p = synth.small(nx=16, ny=16, nz=4, nt=5, nc=2, accel=3, rank=2, nblobs=2, seed=44)
+    a = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, 0.01, 0.01, levels=2, iters=3)
+    try:
+        oracle.set_fft_workers(4)
+        seen = []
+        b = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, 0.01, 0.01, levels=2, iters=3,
+                         on_iteration=seen.append)
+    finally:
+        oracle.set_fft_workers(None)
+    assert seen == [0, 1, 2, 3]
+    for k in ("L", "S", "M"):
+        np.testing.assert_allclose(b[k], a[k], atol=1e-13)
 
 
 def test_p5_normal_operator_is_identity_when_fully_sampled():
@@ -410,3 +434,29 @@ def test_tfft_full_weight_prior_passes_everything():
     w = np.full(X.shape, 255, np.uint8)
     S, _ = oracle.sparse_step(X, 0 * X, w, 5.0, 0, transform="tfft")
     np.testing.assert_allclose(S, X, atol=1e-12)
+
+
+# ---- PSNR (Section 4's quality measure, magnitude images) ---------------------------------
+def test_psnr_closed_forms():
+    rng = np.random.default_rng(43)
+    ref = rng.standard_normal((3, 2, 5, 7)) + 1j * rng.standard_normal((3, 2, 5, 7))
+    peak = np.abs(ref).max()
+    n = ref.size
+    # every magnitude raised by delta (phase kept): MSE = delta^2
+    delta = 0.0125
+    x = ref * (1.0 + delta / np.abs(ref))
+    assert oracle.psnr(x, ref) == pytest.approx(20 * np.log10(peak / delta), rel=1e-12)
+    # magnitude images: a change of phase alone costs nothing, so it leaves the value
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, ref.shape))
+    assert oracle.psnr(x * ph, ref) == pytest.approx(20 * np.log10(peak / delta), rel=1e-12)
+    # one voxel off by e in magnitude: MSE = e^2 / n; the peak is the reference's, so a
+    # change at the reference's brightest voxel keeps it
+    k = int(np.argmax(np.abs(ref)))
+    e = 0.3
+    y = ref.copy().ravel()
+    y[k] *= (1.0 + e / abs(y[k]))
+    y = y.reshape(ref.shape)
+    assert oracle.psnr(y, ref) == pytest.approx(10 * np.log10(peak ** 2 * n / e ** 2), rel=1e-12)
+    # half the magnitudes everywhere: MSE = mean(|ref|^2) / 4
+    want = 10 * np.log10(peak ** 2 / (np.mean(np.abs(ref) ** 2) / 4))
+    assert oracle.psnr(0.5 * ref, ref) == pytest.approx(want, rel=1e-12)
