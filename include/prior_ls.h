@@ -264,6 +264,34 @@ int prior_ls_op_svt(prior_ls_handle *h, const void *C, void *L, double *sigma);
 /* Step (3): S = T^{-1} soft(T(Xm - Lp), lambda_S (1 - w)) with the handle's weights. */
 int prior_ls_op_sparse(prior_ls_handle *h, const void *Xm, const void *Lp, void *S);
 
+/* ---- Allocation-free steps (1)-(2), for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). ----
+ *
+ * prior_ls_op_svt without a handle: L = U diag(sigma_tilde) V^H for the Casorati matrix of C
+ * (n_vox voxels x nt frames), through the same kernels (Gram on MFMA in gram_mode, FP64
+ * reduction and Jacobi eigensolve, back-projection L = C W).  Every intermediate (Gram
+ * partials, reduced Gram, eigenvectors, W and its MFMA operand, the statistics record) lives
+ * in one static device array of PRIOR_LS_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends; the call allocates nothing, does not synchronise and only enqueues work on
+ * `stream` (a hipStream_t, NULL = the default stream).
+ *   C, L        device complex64 [nt][n_vox] (each frame contiguous, e.g. the image layout
+ *               [nt][nz][ny][nx] with n_vox = nx ny nz); L must not overlap C
+ *   n_vox       a positive multiple of 64, n_vox * nt < 2^31
+ *   nt          1 ... PRIOR_LS_NOALLOC_MAX_NT (larger sizes return ESHAPE: the scratch array
+ *               is sized for 32 frames)
+ *   lambda_L, lambda_L_relative, lambda_p   as prior_ls_params
+ *   sigma_prev  device, nt doubles in descending order; required when lambda_p > 0
+ *   sigma       device, nt doubles (may be NULL): the singular values of C, descending
+ * Every call on one GPU shares that GPU's scratch array: calls that overlap in time on one
+ * GPU (on different streams) race; calls on one stream are ordered.  Errors (EINVAL, ESHAPE,
+ * EHIP: message in prior_ls_last_error(NULL) on this thread) are found before anything is
+ * enqueued, except kernel-launch failures. */
+#define PRIOR_LS_NOALLOC_MAX_NT 32
+#define PRIOR_LS_NOALLOC_SCRATCH_BYTES 5313024
+int prior_ls_svt_noalloc(const void *C, int64_t n_vox, int32_t nt, int32_t gram_mode,
+                         double lambda_L, int32_t lambda_L_relative, double lambda_p,
+                         const double *sigma_prev, void *L, double *sigma, void *stream);
+
 /* ---- Batches: several problems of one geometry advanced together (one launch per kernel
  * of an iteration for all of them), the amortised form of the iteration for problems too
  * small to fill the GPU alone. ----

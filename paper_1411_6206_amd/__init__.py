@@ -34,7 +34,7 @@ EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destr
            "prior_ls_server_wait", "prior_ls_server_info", "prior_ls_server_destroy",
            "prior_ls_tune", "prior_ls_set_tuning", "prior_ls_get_tuning",
            "prior_ls_batch_create", "prior_ls_batch_solve", "prior_ls_batch_step",
-           "prior_ls_batch_last_error", "prior_ls_batch_destroy")
+           "prior_ls_batch_last_error", "prior_ls_batch_destroy", "prior_ls_svt_noalloc")
 NKERNELS = 8
 KERNEL_NAMES = ("gram", "gram_reduce", "eig", "sparse", "backproject", "data_consistency", "stats",
                 "change")
@@ -184,6 +184,10 @@ def lib():
     L.prior_ls_batch_last_error.restype = C.c_char_p
     L.prior_ls_batch_destroy.argtypes = [B]
     L.prior_ls_batch_destroy.restype = None
+    L.prior_ls_svt_noalloc.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_double,
+                                       C.c_int32, C.c_double, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+    L.prior_ls_svt_noalloc.restype = C.c_int
     S = C.c_void_p
     L.prior_ls_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(S)]
     L.prior_ls_server_create.restype = C.c_int
@@ -514,6 +518,28 @@ def to_device(problem, device="cuda"):
 
     return dict(kspace=c64(problem.kspace), mask=u8(problem.mask), sens=c64(problem.sens),
                 prior_w=u8(problem.prior_w))
+
+
+def svt_noalloc(Cmat, lambda_L=0.01, lambda_L_relative=True, lambda_p=0.0, sigma_prev=None,
+                gram_mode="fp64", out=None, sigma=None, stream=None):
+    """prior_ls_svt_noalloc: steps (1)-(2) on the Casorati matrix of Cmat (complex64 CUDA
+    tensor [nt][...], each frame contiguous) without a handle and without allocating in the
+    library; L (out, allocated here by torch when None) and the singular values (sigma, a
+    float64 CUDA tensor of nt entries, allocated here when None) are written on `stream`
+    (default: torch's current stream).  sigma_prev: float64 CUDA tensor, descending."""
+    import torch
+    nt = Cmat.shape[0]
+    n_vox = Cmat.numel() // nt
+    Lout = torch.empty_like(Cmat) if out is None else out
+    sig = torch.empty(nt, dtype=torch.float64, device=Cmat.device) if sigma is None else sigma
+    gm = GRAM_MODES[gram_mode] if isinstance(gram_mode, str) else int(gram_mode)
+    st = _current_stream() if stream is None else C.c_void_p(stream)
+    rc = lib().prior_ls_svt_noalloc(_ptr(Cmat), int(n_vox), int(nt), gm, float(lambda_L),
+                                    1 if lambda_L_relative else 0, float(lambda_p),
+                                    _ptr(sigma_prev), _ptr(Lout), _ptr(sig), st)
+    if rc != OK:
+        raise PriorLSError(rc, f"prior_ls_svt_noalloc: {lib().prior_ls_last_error(None).decode()}")
+    return Lout, sig
 
 
 def make_params(lambda_L=0.01, lambda_S=0.01, lambda_p=0.0, lambda_L_relative=True, max_iter=20,
