@@ -300,7 +300,59 @@ def batching_bench(steps, warmup):
         del t, p
         torch.cuda.empty_cache()
         print(f"[bench] batching c{cfg}: {rec}", file=sys.stderr, flush=True)
+    res["mixed"] = mixed_batch_bench(steps, warmup)
     return res
+
+
+def mixed_batch_bench(steps, warmup):
+    """Problems of different geometry in one batch: the serving stream's 128x128x16 volume with
+    window lengths 24 and 30 and 1, 4 or 8 coils (one plane shape and Gram tile class, so one
+    set of kernel instances), against the same problems run one after another alone."""
+    import torch
+    import synth
+    import paper_1411_6206_amd as pls
+    shapes = [(24, 1), (24, 4), (24, 8), (30, 1), (30, 4), (30, 8)]
+    ps = [synth.make_problem(nx=128, ny=128, nz=16, nt=nt, nc=nc, accel=10.0, snr_db=35.0,
+                             rank=5, nblobs=40, seed=synth.MASTER_SEED * 10 + 40 + k, levels=2)
+          for k, (nt, nc) in enumerate(shapes)]
+    ts = [pls.to_device(p) for p in ps]
+    kw = dict(lambda_L=0.01, lambda_S=0.01)
+    hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=2, gram_mode="fp32")
+          for p in ps]
+    try:
+        # alone: each problem in turn, hipGraph chunks of 10 iterations
+        for h, t in zip(hs, ts):
+            h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], max_iter=warmup, outputs=(),
+                    check_every=10, **kw)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for h in hs:
+            h.step(steps, outputs=())
+        torch.cuda.synchronize()
+        alone_s = time.perf_counter() - a0
+        with pls.Batch(hs) as b:
+            prm = pls.make_params(max_iter=warmup, check_every=10, **kw)
+            b.solve(ts, prm, outputs=())
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            b.step(steps, outputs=())
+            torch.cuda.synchronize()
+            batch_s = time.perf_counter() - a0
+    finally:
+        for h in hs:
+            h.close()
+    work = sum(p.nx * p.ny * p.nz * p.nt * p.nc for p in ps) * steps
+    rec = {"workload": "128x128x16 voxels, window lengths 24 and 30 x 1, 4 and 8 coils (6 "
+                       "problems, one of each), 10x sampling, FP32 Gram, J=2",
+           "alone_problem_iterations_per_s": len(ps) * steps / alone_s,
+           "batch_problem_iterations_per_s": len(ps) * steps / batch_s,
+           "alone_voxel_frame_coil_iterations_per_s": work / alone_s,
+           "batch_voxel_frame_coil_iterations_per_s": work / batch_s,
+           "speedup_vs_alone": alone_s / batch_s}
+    print(f"[bench] batching mixed: {rec}", file=sys.stderr, flush=True)
+    del ts
+    torch.cuda.empty_cache()
+    return rec
 
 
 def main():

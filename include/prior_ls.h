@@ -292,23 +292,27 @@ int prior_ls_svt_noalloc(const void *C, int64_t n_vox, int32_t nt, int32_t gram_
                          double lambda_L, int32_t lambda_L_relative, double lambda_p,
                          const double *sigma_prev, void *L, double *sigma, void *stream);
 
-/* ---- Batches: several problems of one geometry advanced together (one launch per kernel
- * of an iteration for all of them), the amortised form of the iteration for problems too
- * small to fill the GPU alone. ----
+/* ---- Batches: several problems advanced together (one launch per kernel of an iteration
+ * for all of them), the amortised form of the iteration for problems too small to fill the
+ * GPU alone. ----
  *
- * A batch groups `count` existing handles (1 ... 4096) that share nx, ny, nz, nt, nc,
- * wavelet_levels, gram_mode, transform and device.  It does not own them: they stay usable
- * on their own, and must outlive the batch.  Each kernel of an iteration of Algorithm 1 is
- * launched once with the problems along the grid's z axis; a problem's workgroups read its
- * own arrays, so its masks, coil maps, prior weights, parameters and data are its own.  The
- * launch shapes (Gram split, back-projection grid, sparse fork point) are those of the
- * first handle's tuning when the batch is created.  Every problem computes exactly what it
+ * A batch groups `count` existing handles (1 ... 4096) that share the phase-encode plane
+ * (ny, nz), transform, wavelet_levels (Haar), gram_mode, the Gram tile class (all nt <= 16,
+ * or all nt in 17..32; with the temporal transform one nt) and device; nx, nt and nc may
+ * differ from problem to problem.  It does not own them: they stay usable on their own, and
+ * must outlive the batch.  Each kernel of an iteration of Algorithm 1 is launched once with
+ * the problems along the grid's z axis and the largest problem's grid along x; a problem's
+ * workgroups read its own arrays, so its masks, coil maps, prior weights, parameters and
+ * data are its own, and its workgroups beyond its own grid return at once.  The launch
+ * shapes (Gram split, back-projection grid, sparse fork point) are those of the first
+ * handle's tuning when the batch is created.  Every problem computes exactly what it
  * computes alone with that tuning: the same kernels in the same order on its data, and it
  * stops where it would alone (after params.max_iter iterations, or at convergence tested
  * after every check_every of its own iterations).  Stopped problems' workgroups return at
  * once.  Calls on a batch and on its handles must not overlap (one thread at a time).
- * Errors: EINVAL (NULL, count out of range, a handle twice, mixed geometry or device) with
- * the message in prior_ls_last_error(NULL) on this thread; ENOMEM, EHIP. */
+ * Errors: EINVAL (NULL, count out of range, a handle twice, problems that cannot share the
+ * kernel instances, mixed devices) with the message in prior_ls_last_error(NULL) on this
+ * thread; ENOMEM, EHIP. */
 typedef struct prior_ls_batch prior_ls_batch;
 int prior_ls_batch_create(prior_ls_handle *const *handles, int32_t count, prior_ls_batch **out);
 
@@ -337,15 +341,16 @@ void prior_ls_batch_destroy(prior_ls_batch *b);
  *
  * A request is one sequence: its first window of nt frames is reconstructed by plain L+S
  * (prior_ls_solve with no prior weights and lambda_p = 0), then n_append frames are appended
- * one at a time (prior_ls_append).  Up to max_active sequences of one geometry are in
- * flight together as a group, each on its own handle: one dispatcher thread starts every
- * member's next window (load or shift) and then advances all members with one batch
- * (prior_ls_batch_*: one launch per kernel of an iteration for all of them), each running
- * its own window's iterations and stopping rule.  Requests join a running group at window
- * boundaries while the oldest pending request has the group's geometry; a request of
- * another geometry waits until the group drains and then starts the next group, which also
- * gathers every request of its geometry already waiting (they overtake older requests of
- * other geometries: they share that group's launches).  A request
+ * one at a time (prior_ls_append).  Up to max_active sequences of one batch class (see
+ * prior_ls_batch_create: the same plane, transform, Gram mode and tile class; nx, nt and nc
+ * may differ) are in flight together as a group, each on its own handle: one dispatcher
+ * thread starts every member's next window (load or shift) and then advances all members
+ * with one batch (prior_ls_batch_*: one launch per kernel of an iteration for all of them),
+ * each running its own window's iterations and stopping rule.  Requests join a running
+ * group at window boundaries while the oldest pending request is of the group's class; a
+ * request of another class waits until the group drains and then starts the next group,
+ * which also gathers every request of its class already waiting (they overtake older
+ * requests of other classes: they share that group's launches).  A request
  * is admitted when the device bytes it needs (prior_ls_plan_bytes plus the compact k-space
  * of its most sampled frame, in nt slots) fit in hbm_budget beside every resident handle.
  * Handles of finished sequences stay resident and are reused by later requests of the same

@@ -418,8 +418,9 @@ class PriorLS:
 
 
 class Batch:
-    """prior_ls_batch_*: several PriorLS handles of one geometry advanced together, one
-    launch per kernel of an iteration for all of them.  The handles stay owned by the
+    """prior_ls_batch_*: several PriorLS handles advanced together, one launch per kernel
+    of an iteration for all of them.  They share the phase-encode plane, transform, Gram
+    mode and Gram tile class; nx, nt and nc may differ.  The handles stay owned by the
     caller and must outlive the batch."""
 
     def __init__(self, solvers: Sequence["PriorLS"]):

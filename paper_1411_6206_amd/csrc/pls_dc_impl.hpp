@@ -64,6 +64,7 @@ template <class G, class SRC>
 __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
     if (src.skip()) return;
     const DcArgs a = src.get();
+    if ((int)blockIdx.x >= a.blocks) return;   // beyond this problem's grid (batches)
     constexpr int Q = G::Q, P = G::P, NY = G::NY, NZ = G::NZ, PB = G::PB, T = G::T;
     constexpr int R0 = radix_in<G>();
     constexpr int RL = radix_out<G>();
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
 
     // Blocks are dealt round-robin to the 8 XCDs; renumber them so that each XCD works on a
     // contiguous range of (x, t) planes and the coil maps of an x plane stay in its L2.
-    const int nb = gridDim.x;
+    const int nb = a.blocks;
     const int lb = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
     const int t = lb % a.nt;
     const int x0 = (lb / a.nt) * PB;
@@ -363,13 +364,16 @@ inline int dc_grid(int nx, int nt) {
     return ((nx + C::PB - 1) / C::PB) * nt;
 }
 
-// bt NULL: one problem with argument block a; else the batch *bt (a: problem 0's block)
+// bt NULL: one problem with argument block a; else the batch *bt (a: problem 0's block; the
+// launch grid is bt->grid when set).  Returns this problem's (a's) block count.
 template <int NY, int NZ>
-inline int dc_launch_t(const DcArgs& a, const Batched<DcArgs>* bt, hipStream_t s) {
+inline int dc_launch_t(const DcArgs& a0, const Batched<DcArgs>* bt, hipStream_t s) {
     using G = typename DcCfg<NY, NZ>::G;
-    const int grid = dc_grid<NY, NZ>(a.nx, a.nt);
+    DcArgs a = a0;
+    a.blocks = dc_grid<NY, NZ>(a.nx, a.nt);
+    const int grid = (bt && bt->grid > 0) ? bt->grid : a.blocks;
     PLS_LAUNCH(dim3(grid), dim3(G::T), s, a, bt, pls_dc_kernel, G);
-    return grid;
+    return a.blocks;
 }
 
 template <int NX>

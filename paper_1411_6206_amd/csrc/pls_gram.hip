@@ -95,6 +95,7 @@ __global__ void __launch_bounds__(256) pls_gram_f64_kernel(SRC src) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
     const size_t vb = (size_t)blockIdx.x * a.vox_per_block;
+    if (vb >= (size_t)a.N) return;             // beyond this problem's grid (batches)
     const size_t ve = min((size_t)a.N, vb + a.vox_per_block);
     d4 acc[NP];
 #pragma unroll
@@ -184,6 +185,7 @@ __global__ void __launch_bounds__(256) pls_gram_f32_kernel(SRC src) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
     const size_t vb = (size_t)blockIdx.x * a.vox_per_block;
+    if (vb >= (size_t)a.N) return;             // beyond this problem's grid (batches)
     const size_t ve = min((size_t)a.N, vb + a.vox_per_block);
     f4 acc[NP];
 #pragma unroll
@@ -240,6 +242,7 @@ __global__ void __launch_bounds__(256) pls_gram_bf16x3_kernel(SRC src) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, g = lane >> 4;
     const size_t vb = (size_t)blockIdx.x * a.vox_per_block;
+    if (vb >= (size_t)a.N) return;             // beyond this problem's grid (batches)
     const size_t ve = min((size_t)a.N, vb + a.vox_per_block);
     f4 acc[NP];
 #pragma unroll
@@ -293,7 +296,8 @@ int launch_gram_batched(int mode, const GramArgs& a0, const Batched<GramArgs>* b
     GramArgs a = a0;
     const int vpb = gram_vpb(a.N, a.target_blocks);
     a.vox_per_block = vpb;
-    const int grid = (a.N + vpb - 1) / vpb;
+    const int own = (a.N + vpb - 1) / vpb;
+    const int grid = (bt && bt->grid > 0) ? bt->grid : own;
     const bool one = a.nt <= 16;
     if (mode == PRIOR_LS_GRAM_FP32) {
         if (one) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f32_kernel, 1);
@@ -305,7 +309,7 @@ int launch_gram_batched(int mode, const GramArgs& a0, const Batched<GramArgs>* b
         if (one) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f64_kernel, 1);
         else PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f64_kernel, 2);
     }
-    return grid;
+    return own;
 }
 
 int launch_gram(int mode, const GramArgs& a, hipStream_t s) {

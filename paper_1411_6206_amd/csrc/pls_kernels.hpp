@@ -31,6 +31,9 @@ struct DcArgs {
     double* part;          // per block: sum |r|^2 of its residual entries (scaled by 1/(ny nz))
     int nx, nt, nc;
     float inv_p;           // 1 / (ny nz)
+    int blocks;            // this problem's workgroups, (nx / planes per block) nt: the grid
+                           // when launched alone; blocks beyond it (a batch launched with a
+                           // larger problem's grid) return at once
 };
 
 struct XiArgs {
@@ -104,6 +107,7 @@ struct BpArgs {
     int max_grid;          // workgroups at most (0 = default)
 };
 void launch_bp(const BpArgs& a, hipStream_t s);
+int bp_blocks(int N, int max_grid);   // back-projection workgroups of one problem
 
 struct SparseArgs {
     const float2* C;       // M - S (so M - L_prev = C + S - L_prev)
@@ -120,6 +124,8 @@ struct SparseArgs {
     const float* Wi;       // of the inverse (its columns in the forward's output order)
     int max_grid;          // Haar transform: workgroups at most, each looping over tiles
                            // (0 = one per tile)
+    int blocks;            // this problem's workgroups (= partial sums); set by the launcher
+                           // for one problem, by the batch for each of its problems
 };
 // returns number of blocks
 int launch_sparse(int levels, const SparseArgs& a, hipStream_t s);
@@ -137,6 +143,7 @@ struct ChangeArgs {
     const float2* Sold;
     double* part;          // [blocks][2]
     long n;                // complex elements of each array
+    int blocks;            // this problem's workgroups, change_blocks(n); set as for SparseArgs
 };
 int change_blocks(long n);
 void launch_change(const ChangeArgs& a, hipStream_t s);
@@ -186,13 +193,18 @@ struct ArgBatch {
 };
 
 // A batched launch: `count` problems (grid z), their device argument blocks, the per-problem
-// activity flags (device, or NULL) and the record offset.
+// activity flags (device, or NULL), the record offset, and the launch grid along x (the
+// largest of the problems' own grids: problems of a batch may differ in nx, nt and nc; 0 =
+// the grid of problem 0's host argument block).  Every kernel returns at once in the
+// workgroups beyond its problem's own grid, and strides over its problem's work by that own
+// grid, so a problem computes in a batch exactly what it computes alone.
 template <class A>
 struct Batched {
     int count;
     const A* args;
     const int* active;
     long rec_off;
+    int grid;
     ArgBatch<A> src() const { return ArgBatch<A>{args, active, rec_off}; }
 };
 

@@ -113,10 +113,16 @@ __global__ void __launch_bounds__(256) pls_bp_kernel(SRC src) {
     }
 }
 
+int bp_blocks(int N, int max_grid) {
+    const int tiles = (N + 63) / 64;
+    const int cap = max_grid > 0 ? max_grid : 2048;
+    return tiles < cap ? tiles : cap;
+}
+
+// Each output voxel is formed by one lane whatever the grid, so a batch launched with a
+// larger problem's grid computes every problem exactly as alone.
 void launch_bp_batched(const BpArgs& a, const Batched<BpArgs>* bt, hipStream_t s) {
-    const int tiles = (a.N + 63) / 64;
-    const int cap = a.max_grid > 0 ? a.max_grid : 2048;
-    const int grid = tiles < cap ? tiles : cap;
+    const int grid = (bt && bt->grid > 0) ? bt->grid : bp_blocks(a.N, a.max_grid);
     if (a.nt <= 16)
         PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_bp_kernel, 1);
     else
@@ -177,6 +183,7 @@ template <int J, bool ZA, class SRC>
 __global__ void __launch_bounds__(256) pls_sparse_kernel(SRC src) {
     if (src.skip()) return;
     const SparseArgs a = src.get();
+    if ((int)blockIdx.x >= a.blocks) return;   // beyond this problem's grid (batches)
     constexpr int B = 1 << J;
     constexpr int ZW = ZA ? B : 1;
     constexpr int YW = 64 / ZW;
@@ -191,8 +198,8 @@ __global__ void __launch_bounds__(256) pls_sparse_kernel(SRC src) {
     const float2* Sp = has_s ? a.S : a.C;
     const uint8_t* wp = has_w ? a.w : reinterpret_cast<const uint8_t*>(a.C);
     float l1 = 0.f;
-    // work item = (frame t, tile); a workgroup takes items blockIdx.x, + gridDim.x, ...
-    for (int item = blockIdx.x; item < tiles * a.nt; item += gridDim.x) {
+    // work item = (frame t, tile); a workgroup takes items blockIdx.x, + blocks, ...
+    for (int item = blockIdx.x; item < tiles * a.nt; item += a.blocks) {
         int tile = item % tiles;
         const int t = item / tiles;
         const int yt = tile % nyt;
@@ -257,10 +264,12 @@ int sparse_haar_blocks(int levels, int nx, int ny, int nz, int nt, int max_grid)
 }
 
 template <int J, bool ZA>
-static int sparse_launch_t(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
-    const int grid = sparse_haar_blocks(J, a.nx, a.ny, a.nz, a.nt, a.max_grid);
+static int sparse_launch_t(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s) {
+    SparseArgs a = a0;
+    a.blocks = sparse_haar_blocks(J, a.nx, a.ny, a.nz, a.nt, a.max_grid);
+    const int grid = (bt && bt->grid > 0) ? bt->grid : a.blocks;
     PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_sparse_kernel, J, ZA);
-    return grid;
+    return a.blocks;
 }
 
 int launch_sparse_batched(int levels, const SparseArgs& a, const Batched<SparseArgs>* bt,
@@ -307,6 +316,7 @@ template <int NB, class SRC>
 __global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
     if (src.skip()) return;
     const SparseArgs a = src.get();
+    if ((int)blockIdx.x >= a.blocks) return;   // beyond this problem's grid (batches)
     constexpr int NTP = 16 * NB, K2 = 2 * NTP, MB = K2 / 16, KS = K2 / 4, KH = NTP / 4;
     constexpr int KQ = KS / 4;                 // groups of four k steps
     constexpr int NF = MB * KQ * 64;           // 16-byte fragments per operand
@@ -321,7 +331,7 @@ __global__ void __launch_bounds__(256, 4) pls_tfft_sparse_kernel(SRC src) {
     __syncthreads();
     const int N = a.nx * a.ny * a.nz;
     const int nt = a.nt;
-    const int stride = gridDim.x * 4 * 16;
+    const int stride = a.blocks * 4 * 16;
     const bool has_s = a.S != nullptr, has_w = a.w != nullptr;
     const float2* Sp = has_s ? a.S : a.C;
     const uint8_t* wp = has_w ? a.w : reinterpret_cast<const uint8_t*>(a.C);
@@ -444,6 +454,7 @@ template <int NT, class SRC>
 __global__ void __launch_bounds__(256) pls_tfft_fft_kernel(SRC src) {
     if (src.skip()) return;
     const SparseArgs a = src.get();
+    if ((int)blockIdx.x >= a.blocks) return;   // beyond this problem's grid (batches)
     __shared__ double red[4];
     const int N = a.nx * a.ny * a.nz;
     const bool has_s = a.S != nullptr, has_w = a.w != nullptr;
@@ -451,7 +462,7 @@ __global__ void __launch_bounds__(256) pls_tfft_fft_kernel(SRC src) {
     const uint8_t* wp = has_w ? a.w : reinterpret_cast<const uint8_t*>(a.C);
     const float scale = 1.0f / sqrtf((float)NT);
     float l1 = 0.f;
-    for (int v = blockIdx.x * 256 + threadIdx.x; v < N; v += gridDim.x * 256) {
+    for (int v = blockIdx.x * 256 + threadIdx.x; v < N; v += a.blocks * 256) {
         float2 x[NT];
 #pragma unroll
         for (int f = 0; f < NT; ++f) {
@@ -486,10 +497,12 @@ __global__ void __launch_bounds__(256) pls_tfft_fft_kernel(SRC src) {
 }
 
 template <int NT>
-static int tfft_fft_launch(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
-    const int grid = sparse_tfft_blocks(a.nx * a.ny * a.nz, NT);
+static int tfft_fft_launch(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s) {
+    SparseArgs a = a0;
+    a.blocks = sparse_tfft_blocks(a.nx * a.ny * a.nz, NT);
+    const int grid = (bt && bt->grid > 0) ? bt->grid : a.blocks;
     PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_tfft_fft_kernel, NT);
-    return grid;
+    return a.blocks;
 }
 
 int launch_sparse_tfft_batched(const SparseArgs& a, const Batched<SparseArgs>* bt, hipStream_t s) {
@@ -519,12 +532,14 @@ int launch_sparse_tfft_batched(const SparseArgs& a, const Batched<SparseArgs>* b
         case 32: return tfft_fft_launch<32>(a, bt, s);
     }
     // other frame counts (a prime factor above 7): the dense product on MFMA
-    const int grid = sparse_tfft_blocks(a.nx * a.ny * a.nz, a.nt);
+    SparseArgs a1 = a;
+    a1.blocks = sparse_tfft_blocks(a.nx * a.ny * a.nz, a.nt);
+    const int grid = (bt && bt->grid > 0) ? bt->grid : a1.blocks;
     if (a.nt <= 16)
-        PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_tfft_sparse_kernel, 1);
+        PLS_LAUNCH(dim3(grid), dim3(256), s, a1, bt, pls_tfft_sparse_kernel, 1);
     else
-        PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_tfft_sparse_kernel, 2);
-    return grid;
+        PLS_LAUNCH(dim3(grid), dim3(256), s, a1, bt, pls_tfft_sparse_kernel, 2);
+    return a1.blocks;
 }
 
 int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
@@ -612,6 +627,7 @@ __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_num_vgpr(32)))
 pls_change_kernel(SRC src) {
     if (src.skip()) return;
     const ChangeArgs a = src.get();
+    if ((int)blockIdx.x >= a.blocks) return;   // beyond this problem's grid (batches)
     __shared__ double red[NTH / kWave];
     double d2 = 0.0, y2 = 0.0;
     auto add = [&](float2 l, float2 sv, float2 lo, float2 so) __attribute__((always_inline)) {
@@ -625,7 +641,7 @@ pls_change_kernel(SRC src) {
     const float4* S4 = reinterpret_cast<const float4*>(a.S);
     const float4* Lo4 = reinterpret_cast<const float4*>(a.Lold);
     const float4* So4 = reinterpret_cast<const float4*>(a.Sold);
-    const long stride = (long)gridDim.x * NTH;
+    const long stride = (long)a.blocks * NTH;
     for (long i = (long)blockIdx.x * NTH + threadIdx.x; i < npair; i += stride) {
         const float4 l = L4[i], sv = S4[i], lo = Lo4[i], so = So4[i];
         add(make_float2(l.x, l.y), make_float2(sv.x, sv.y), make_float2(lo.x, lo.y),
@@ -645,9 +661,11 @@ pls_change_kernel(SRC src) {
     }
 }
 
-void launch_change_batched(const ChangeArgs& a, const Batched<ChangeArgs>* bt, hipStream_t s) {
-    PLS_LAUNCH(dim3(change_blocks(a.n)), dim3(kChangeThreads), s, a, bt, pls_change_kernel,
-               kChangeThreads);
+void launch_change_batched(const ChangeArgs& a0, const Batched<ChangeArgs>* bt, hipStream_t s) {
+    ChangeArgs a = a0;
+    a.blocks = change_blocks(a.n);
+    const int grid = (bt && bt->grid > 0) ? bt->grid : a.blocks;
+    PLS_LAUNCH(dim3(grid), dim3(kChangeThreads), s, a, bt, pls_change_kernel, kChangeThreads);
 }
 
 void launch_change(const ChangeArgs& a, hipStream_t s) { launch_change_batched(a, nullptr, s); }

@@ -569,6 +569,7 @@ DcArgs dc_args(prior_ls_handle* h, const float2* L, const float2* S, float2* C) 
     da.nt = h->d.nt;
     da.nc = h->d.nc;
     da.inv_p = 1.0f / (float)h->sz.P;
+    da.blocks = h->sz.dcb;
     return da;
 }
 
@@ -1031,11 +1032,13 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
 
 void prior_ls_destroy(prior_ls_handle* h) {
     if (!h) return;
+    // everything queued on either stream completes before any graph, array or buffer the
+    // work may still use is released
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     h->clear_graphs();
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->stats_h) (void)hipHostFree(h->stats_h);
-    if (h->side) (void)hipStreamSynchronize(h->side);
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
@@ -1378,11 +1381,15 @@ int prior_ls_op_sparse(prior_ls_handle* h, const void* Xm, const void* Lp, void*
 }  // extern "C"
 
 // ================================================================ batches
-// A batch advances several loaded handles of one geometry together: every kernel of an
-// iteration is launched once for all of them (grid z = problem), each problem's blocks
-// reading its argument block from device memory.  Problems stop on their own terms (their
-// iteration count, or convergence checked at their own chunk boundaries, as when run
-// alone); the blocks of a stopped problem return at once.
+// A batch advances several loaded handles together: every kernel of an iteration is launched
+// once for all of them (grid z = problem), each problem's blocks reading its argument block
+// from device memory.  The problems share the phase-encode plane (ny, nz), the sparsifying
+// transform and its depth, the Gram mode and the Gram tile class (nt <= 16 or 17..32), which
+// fix the kernel instances; nx, nt and nc may differ.  Each launch takes the largest of the
+// problems' grids; a problem's blocks beyond its own grid return at once and its blocks
+// stride over its work by its own grid, so it computes exactly what it computes alone.
+// Problems stop on their own terms (their iteration count, or convergence checked at their
+// own chunk boundaries, as when run alone); the blocks of a stopped problem return at once.
 
 struct prior_ls_batch {
     std::vector<prior_ls_handle*> hs;
@@ -1397,7 +1404,7 @@ struct prior_ls_batch {
     char* host = nullptr;      // pinned staging of the same layout
     size_t bytes = 0;
     size_t off[9] = {0};       // gram, reduce, eig, bp, sparse, dc, stats, change, active
-    int gram_vpb = 0;
+    int grid[8] = {0};         // launch grid per kernel (as off): the largest problem's
     std::vector<int> staged_cur;   // every problem's iterate index when the arguments were staged
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
@@ -1419,11 +1426,6 @@ int bfail(prior_ls_batch* b, int code, const std::string& m) {
     return code;
 }
 
-bool same_geometry(const prior_ls_dims& a, const prior_ls_dims& b) {
-    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.nt == b.nt && a.nc == b.nc &&
-           a.wavelet_levels == b.wavelet_levels && a.gram_mode == b.gram_mode &&
-           a.transform == b.transform;
-}
 
 // Argument block array of kernel k for phase `phase` (iteration j of a chunk uses phase
 // j % 2).
@@ -1438,19 +1440,21 @@ T* barr(prior_ls_batch* b, char* base, int k, int phase) {
 // problem's cur is recorded in b->staged_cur.
 void batch_upload_args(prior_ls_batch* b) {
     const int n = (int)b->hs.size();
-    const prior_ls_dims& d = b->d;
-    const Sizes& sz = b->sz;
     b->staged_cur.resize(n);
+    for (int k = 0; k < 8; ++k) b->grid[k] = 1;
     for (int ph = 0; ph < 2; ++ph) {
         for (int i = 0; i < n; ++i) {
             prior_ls_handle* h = b->hs[i];
+            const prior_ls_dims& d = h->d;
+            const Sizes& sz = h->sz;
             const int p = h->cur ^ ph, q = 1 - p;
             b->staged_cur[i] = h->cur;
+            const int gb = pls::gram_blocks((int)sz.N, b->tuning.gram_blocks);
             barr<pls::GramArgs>(b, b->host, 0, ph)[i] =
-                pls::GramArgs{h->C, h->gpart, (int)sz.N, d.nt, b->gram_vpb, b->tuning.gram_blocks};
+                pls::GramArgs{h->C, h->gpart, (int)sz.N, d.nt,
+                              pls::gram_vpb((int)sz.N, b->tuning.gram_blocks), b->tuning.gram_blocks};
             barr<pls::ReduceArgs>(b, b->host, 1, ph)[i] =
-                pls::ReduceArgs{h->gpart, h->gred, pls::gram_blocks((int)sz.N, b->tuning.gram_blocks),
-                                sz.gentries};
+                pls::ReduceArgs{h->gpart, h->gred, gb, sz.gentries};
             pls::EigArgs ea{};
             ea.gram = h->gred;
             ea.V = h->V;
@@ -1483,14 +1487,19 @@ void batch_upload_args(prior_ls_batch* b) {
             sa.Wf = h->Wtf;
             sa.Wi = h->Wti;
             sa.max_grid = b->tuning.sparse_grid;
+            sa.blocks = sparse_launch_blocks(d, b->tuning);
             barr<pls::SparseArgs>(b, b->host, 4, ph)[i] = sa;
             barr<DcArgs>(b, b->host, 5, ph)[i] = dc_args(h, h->L[q], h->S[q], h->C);
+            const int chb = pls::change_blocks((long)sz.I);
             barr<pls::StatsArgs>(b, b->host, 6, ph)[i] =
-                pls::StatsArgs{h->dc_part, sz.dcb, h->ch_part, pls::change_blocks((long)sz.I),
-                               h->sp_part, sparse_launch_blocks(d, b->tuning), h->stats_d,
-                               (double)sz.P, h->params.lambda_S};
+                pls::StatsArgs{h->dc_part, sz.dcb, h->ch_part, chb, h->sp_part, sa.blocks,
+                               h->stats_d, (double)sz.P, h->params.lambda_S};
             barr<pls::ChangeArgs>(b, b->host, 7, ph)[i] =
-                pls::ChangeArgs{h->L[q], h->S[q], h->L[p], h->S[p], h->ch_part, (long)sz.I};
+                pls::ChangeArgs{h->L[q], h->S[q], h->L[p], h->S[p], h->ch_part, (long)sz.I, chb};
+            // launch grids: the largest problem's (per kernel, as the offsets)
+            const int own[8] = {gb, 0, 1, pls::bp_blocks((int)sz.N, b->tuning.bp_grid), sa.blocks,
+                                sz.dcb, 1, chb};
+            for (int k = 0; k < 8; ++k) b->grid[k] = std::max(b->grid[k], own[k]);
         }
     }
     PLS_HIP(hipMemcpyAsync(b->dev, b->host, b->off[8], hipMemcpyHostToDevice, b->stream));
@@ -1511,22 +1520,22 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
         PLS_HIP(hipEventRecord(b->ev_fork, s));
         PLS_HIP(hipStreamWaitEvent(s2, b->ev_fork, 0));
     }
-    const pls::Batched<pls::GramArgs> bg{n, barr<pls::GramArgs>(b, b->dev, 0, p), act, 0};
+    const pls::Batched<pls::GramArgs> bg{n, barr<pls::GramArgs>(b, b->dev, 0, p), act, 0, b->grid[0]};
     pls::launch_gram_batched(d.gram_mode, barr<pls::GramArgs>(b, b->host, 0, p)[0], &bg, s);
     if (!fork_first && !serial) {
         PLS_HIP(hipEventRecord(b->ev_fork, s));
         PLS_HIP(hipStreamWaitEvent(s2, b->ev_fork, 0));
     }
-    const pls::Batched<pls::SparseArgs> bs{n, barr<pls::SparseArgs>(b, b->dev, 4, p), act, 0};
+    const pls::Batched<pls::SparseArgs> bs{n, barr<pls::SparseArgs>(b, b->dev, 4, p), act, 0, b->grid[4]};
     const pls::SparseArgs& sa0 = barr<pls::SparseArgs>(b, b->host, 4, p)[0];
     if (d.transform == PRIOR_LS_T_TFFT) pls::launch_sparse_tfft_batched(sa0, &bs, s2);
     else pls::launch_sparse_batched(d.wavelet_levels, sa0, &bs, s2);
     if (!serial) PLS_HIP(hipEventRecord(b->ev_join, s2));
-    const pls::Batched<pls::ReduceArgs> br{n, barr<pls::ReduceArgs>(b, b->dev, 1, p), act, 0};
+    const pls::Batched<pls::ReduceArgs> br{n, barr<pls::ReduceArgs>(b, b->dev, 1, p), act, 0, 0};
     pls::launch_gram_reduce_batched(barr<pls::ReduceArgs>(b, b->host, 1, p)[0], &br, s);
-    const pls::Batched<pls::EigArgs> be{n, barr<pls::EigArgs>(b, b->dev, 2, p), act, rec};
+    const pls::Batched<pls::EigArgs> be{n, barr<pls::EigArgs>(b, b->dev, 2, p), act, rec, 0};
     pls::launch_eig_batched(barr<pls::EigArgs>(b, b->host, 2, p)[0], &be, s);
-    const pls::Batched<pls::BpArgs> bb{n, barr<pls::BpArgs>(b, b->dev, 3, p), act, 0};
+    const pls::Batched<pls::BpArgs> bb{n, barr<pls::BpArgs>(b, b->dev, 3, p), act, 0, b->grid[3]};
     pls::launch_bp_batched(barr<pls::BpArgs>(b, b->host, 3, p)[0], &bb, s);
     // the change of the iterate beside the data-consistency pass (as enqueue_iteration)
     if (stats) {
@@ -1534,16 +1543,16 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
             PLS_HIP(hipEventRecord(b->ev_bp, s));
             PLS_HIP(hipStreamWaitEvent(s2, b->ev_bp, 0));
         }
-        const pls::Batched<pls::ChangeArgs> bc{n, barr<pls::ChangeArgs>(b, b->dev, 7, p), act, 0};
+        const pls::Batched<pls::ChangeArgs> bc{n, barr<pls::ChangeArgs>(b, b->dev, 7, p), act, 0, b->grid[7]};
         pls::launch_change_batched(barr<pls::ChangeArgs>(b, b->host, 7, p)[0], &bc, s2);
         if (!serial) PLS_HIP(hipEventRecord(b->ev_chg, s2));
     }
     if (!serial) PLS_HIP(hipStreamWaitEvent(s, b->ev_join, 0));
-    const pls::Batched<DcArgs> bd{n, barr<DcArgs>(b, b->dev, 5, p), act, 0};
+    const pls::Batched<DcArgs> bd{n, barr<DcArgs>(b, b->dev, 5, p), act, 0, b->grid[5]};
     pls::launch_dc_batched(d.ny, d.nz, barr<DcArgs>(b, b->host, 5, p)[0], &bd, s);
     if (stats) {
         if (!serial) PLS_HIP(hipStreamWaitEvent(s, b->ev_chg, 0));
-        const pls::Batched<pls::StatsArgs> bt{n, barr<pls::StatsArgs>(b, b->dev, 6, p), act, rec};
+        const pls::Batched<pls::StatsArgs> bt{n, barr<pls::StatsArgs>(b, b->dev, 6, p), act, rec, 0};
         pls::launch_stats_batched(barr<pls::StatsArgs>(b, b->host, 6, p)[0], &bt, s);
     }
 }
@@ -1699,6 +1708,17 @@ int first_status(const std::vector<int>& st) {
 
 namespace pls {
 
+// Problems that can share a batch's launches: the same kernel instances (plane shape,
+// transform and depth, Gram mode and tile class; the temporal transform's instance depends on
+// nt itself).  nx, nt and nc may differ.
+bool batch_compatible(const prior_ls_dims& a, const prior_ls_dims& b) {
+    if (a.ny != b.ny || a.nz != b.nz || a.gram_mode != b.gram_mode || a.transform != b.transform)
+        return false;
+    if ((a.nt <= 16) != (b.nt <= 16)) return false;
+    if (a.transform == PRIOR_LS_T_TFFT) return a.nt == b.nt;
+    return a.wavelet_levels == b.wavelet_levels;
+}
+
 int batch_run(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& converged,
               std::vector<int>& status, std::vector<std::chrono::steady_clock::time_point>& done_at) {
     if (!b || target.size() != b->hs.size()) return bfail(b, PRIOR_LS_EINVAL, "one target per problem");
@@ -1733,8 +1753,10 @@ int prior_ls_batch_create(prior_ls_handle* const* handles, int32_t count, prior_
                 pls::set_thread_error("a handle appears twice in the batch");
                 return PRIOR_LS_EINVAL;
             }
-        if (!same_geometry(handles[i]->d, handles[0]->d) || handles[i]->device != handles[0]->device) {
-            pls::set_thread_error("the handles of a batch need one geometry, Gram mode, transform and device");
+        if (!pls::batch_compatible(handles[i]->d, handles[0]->d) || handles[i]->device != handles[0]->device) {
+            pls::set_thread_error("the handles of a batch need one phase-encode plane (ny, nz), "
+                                  "transform and depth, Gram mode, Gram tile class (nt <= 16 or "
+                                  "17..32; the temporal transform: one nt) and device");
             return PRIOR_LS_EINVAL;
         }
     }
@@ -1772,7 +1794,6 @@ int prior_ls_batch_create(prior_ls_handle* const* handles, int32_t count, prior_
         PLS_HIP(hipHostMalloc(&hp, b->bytes, hipHostMallocDefault));
         b->host = static_cast<char*>(hp);
         std::memset(b->host, 0, b->bytes);
-        b->gram_vpb = pls::gram_vpb((int)b->sz.N, b->tuning.gram_blocks);
         return PRIOR_LS_OK;
     });
     if (rc) {

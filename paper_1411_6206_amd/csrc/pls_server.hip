@@ -1,14 +1,15 @@
 // Serving runtime: continuous batching of recursive (sliding-window) reconstructions.
 //
 // A request is one sequence: a first window of nt frames reconstructed by plain L+S, then
-// n_append frames appended one at a time.  Up to max_active sequences of one geometry are
-// in flight together as a group: one host thread (the dispatcher) starts every member's
-// next window (load or shift, on the member's own handle), then advances all of them with
-// one batch (prior_ls_batch: one launch per kernel of an iteration for every member), each
-// member running its own window's iteration count and stopping rule.  Members join a
-// running group at window boundaries while the oldest pending request has the group's
-// geometry; a request of another geometry waits until the group drains, then starts the
-// next group, which also gathers every request of its geometry already waiting.  A request
+// n_append frames appended one at a time.  Up to max_active sequences of one batch class
+// (the same phase-encode plane, transform, Gram mode and tile class; their nx, nt and nc may
+// differ) are in flight together as a group: one host thread (the dispatcher) starts every
+// member's next window (load or shift, on the member's own handle), then advances all of
+// them with one batch (prior_ls_batch: one launch per kernel of an iteration for every
+// member), each member running its own window's iteration count and stopping rule.  Members
+// join a running group at window boundaries while the oldest pending request is of the
+// group's class; a request of another class waits until the group drains, then starts the
+// next group, which also gathers every request of its class already waiting.  A request
 // is admitted when the device bytes it needs fit in the budget beside everything resident;
 // handles of finished sequences stay resident (state, sample store, graphs) and are reused
 // by later requests of the same geometry, and idle ones are evicted (oldest first) when an
@@ -144,12 +145,14 @@ struct prior_ls_server {
         return nullptr;
     }
 
-    // A pending job of geometry `d` that fits: with `oldest_only` only the oldest pending job
-    // qualifies (a running group does not overtake older requests of other geometries),
-    // else the oldest of that geometry (a group being formed gathers what waits for it).
+    // A pending job that can share a batch with geometry `d` (pls::batch_compatible: the same
+    // plane, transform, Gram mode and tile class; nx, nt and nc may differ) and fits: with
+    // `oldest_only` only the oldest pending job qualifies (a running group does not overtake
+    // older requests of other classes), else the oldest of that class (a group being formed
+    // gathers what waits for it).
     Job* admit_same_locked(const prior_ls_dims& d, bool oldest_only, std::vector<Resident>& evict) {
         for (auto it = pending.begin(); it != pending.end(); ++it) {
-            if (same_dims((*it)->req.dims, d)) {
+            if (pls::batch_compatible((*it)->req.dims, d)) {
                 if (!reserve_locked(*it, evict)) return nullptr;
                 Job* j = *it;
                 pending.erase(it);

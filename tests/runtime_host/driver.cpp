@@ -6,6 +6,7 @@
 // from several threads at once, and batches.
 #include <atomic>
 #include <cstdio>
+#include <cstring>
 #include <random>
 #include <thread>
 #include <vector>
@@ -16,8 +17,15 @@
 struct Geo {
     int nx, ny, nz, nt, nc, dense_frames;
 };
-static const Geo kGeo[] = {{16, 16, 4, 5, 2, 0}, {24, 32, 8, 7, 3, 0}, {32, 32, 1, 6, 1, 0},
-                           {16, 16, 4, 6, 2, 1}, {48, 32, 8, 8, 2, 0}};
+static const Geo kSmall[] = {{16, 16, 4, 5, 2, 0}, {24, 32, 8, 7, 3, 0}, {32, 32, 1, 6, 1, 0},
+                             {16, 16, 4, 6, 2, 1}, {48, 32, 8, 8, 2, 0}};
+// "full": the serving workload's volume classes at their real sizes, the 192x192x32 x 30
+// frames x 8 coils class among them (four of it in flight), plus one with fully sampled
+// appended frames so its sample store grows
+static const Geo kFull[] = {{192, 192, 32, 30, 8, 0}, {128, 128, 16, 24, 4, 0},
+                            {64, 64, 8, 16, 1, 0}, {192, 192, 32, 16, 4, 1},
+                            {192, 192, 32, 30, 8, 0}};
+static const Geo* kGeo = kSmall;
 
 struct Seq {
     Geo g;
@@ -33,7 +41,8 @@ struct Seq {
 static void* dev_alloc(size_t n) {
     void* p = nullptr;
     hipMalloc(&p, n);
-    std::memset(p, 0, n);
+    // the full-size k-space arrays stay untouched (the stand-in kernels only read them)
+    if (n < ((size_t)64 << 20)) std::memset(p, 0, n);
     return p;
 }
 
@@ -65,17 +74,22 @@ static void make_seq(Seq& q, std::mt19937& rng) {
     r.latency_ms = q.lat.data();
 }
 
-int main() {
+int main(int argc, char** argv) {
+    const bool full = argc > 1 && std::strcmp(argv[1], "full") == 0;
+    if (full) kGeo = kFull;
     std::mt19937 rng(11);
-    const int N = 40;
+    const int N = full ? 12 : 40;
     std::vector<Seq> seqs(N);
     for (int i = 0; i < N; ++i) {
-        seqs[i].g = kGeo[rng() % 5];
-        seqs[i].n_append = rng() % 4;
+        // in "full" mode the first four requests are the 192x192x32 x 30 x 8 class
+        seqs[i].g = (full && i < 4) ? kGeo[0] : kGeo[rng() % 5];
+        seqs[i].n_append = full ? 1 + rng() % 3 : rng() % 4;
         make_seq(seqs[i], rng);
     }
     prior_ls_dims big{sizeof(prior_ls_dims), 48, 32, 8, 8, 2, 2, 0, 0, 0};
-    prior_ls_server_config cfg{sizeof(cfg), (uint64_t)(prior_ls_plan_bytes(&big) * 2.5), 4, 0};
+    if (full) big = prior_ls_dims{sizeof(prior_ls_dims), 192, 192, 32, 30, 8, 2, 0, 0, 0};
+    prior_ls_server_config cfg{sizeof(cfg),
+                               (uint64_t)(prior_ls_plan_bytes(&big) * (full ? 4.6 : 2.5)), 4, 0};
     prior_ls_server* s = nullptr;
     if (prior_ls_server_create(&cfg, &s)) return 1;
     std::vector<int64_t> tk(N, -1);

@@ -160,6 +160,10 @@ void launch_eig(const EigArgs& a, hipStream_t s) {
         work_us(30);
     });
 }
+int bp_blocks(int N, int max_grid) {
+    const int tiles = (N + 63) / 64, cap = max_grid > 0 ? max_grid : 2048;
+    return tiles < cap ? tiles : cap;
+}
 void launch_bp(const BpArgs& a, hipStream_t s) {
     BpArgs c = a;
     fh_stream(s)->push([c] {

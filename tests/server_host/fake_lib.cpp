@@ -55,6 +55,9 @@ int phase_chunk_finish(prior_ls_handle* h, int m, int* conv) {
 int phase_outputs(prior_ls_handle* h, const prior_ls_outputs*) { h->ready = Clk::now() + std::chrono::microseconds(50); return 0; }
 void phase_stats(prior_ls_handle* h, prior_ls_stats* st, int conv, double ms) { st->iters = h->iters; st->converged = conv; st->ms = ms; }
 int phase_max_iter(const prior_ls_handle* h) { return h->p.max_iter; }
+bool batch_compatible(const prior_ls_dims& a, const prior_ls_dims& b) {
+  return a.ny == b.ny && a.nz == b.nz && a.gram_mode == b.gram_mode && a.transform == b.transform &&
+         (a.nt <= 16) == (b.nt <= 16) && a.wavelet_levels == b.wavelet_levels; }
 int batch_run(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& conv,
               std::vector<int>& status, std::vector<Clk::time_point>& done_at) {
   const size_t n = b->hs.size();

@@ -176,18 +176,85 @@ def test_batch_step_from_different_iteration_counts():
             assert torch.equal(outs[k][key], o1[key]), (k, key)
 
 
-def test_batch_rejects_mixed_geometry_and_reused_handles():
+def test_batch_rejects_incompatible_problems_and_reused_handles():
+    # another plane, another Gram tile class (nt 8 against 20), another Haar depth: each
+    # needs other kernel instances
     a = pls.PriorLS(32, 32, 1, 8, 1, wavelet_levels=2)
-    b = pls.PriorLS(32, 32, 1, 6, 1, wavelet_levels=2)
+    others = [pls.PriorLS(32, 48, 1, 8, 1, wavelet_levels=2),
+              pls.PriorLS(32, 32, 1, 20, 1, wavelet_levels=2),
+              pls.PriorLS(32, 32, 1, 8, 1, wavelet_levels=1)]
     try:
-        with pytest.raises(pls.PriorLSError) as e:
-            pls.Batch([a, b])
-        assert e.value.status == pls.EINVAL
+        for o in others:
+            with pytest.raises(pls.PriorLSError) as e:
+                pls.Batch([a, o])
+            assert e.value.status == pls.EINVAL
         with pytest.raises(pls.PriorLSError):
             pls.Batch([a, a])
     finally:
         a.close()
-        b.close()
+        for o in others:
+            o.close()
+
+
+# Problems of different geometry in one batch: one plane shape, transform and Gram tile class,
+# different nx, nt and nc (each kernel is launched with the largest problem's grid)
+MIXED = [
+    ("haar_nt_le16", [dict(nx=32, ny=48, nz=8, nt=12, nc=3), dict(nx=16, ny=48, nz=8, nt=9, nc=1),
+                      dict(nx=48, ny=48, nz=8, nt=16, nc=2)], 2, "haar"),
+    ("haar_nt_17_32", [dict(nx=16, ny=32, nz=4, nt=30, nc=2), dict(nx=32, ny=32, nz=4, nt=17, nc=1),
+                       dict(nx=24, ny=32, nz=4, nt=24, nc=4)], 1, "haar"),
+    ("2d", [dict(nx=32, ny=64, nz=1, nt=8, nc=1), dict(nx=64, ny=64, nz=1, nt=16, nc=2)], 2, "haar"),
+    ("tfft_one_nt", [dict(nx=24, ny=24, nz=4, nt=20, nc=2), dict(nx=48, ny=24, nz=4, nt=20, nc=1)],
+     1, "tfft"),
+]
+
+
+@pytest.mark.parametrize("mix", MIXED, ids=[m[0] for m in MIXED])
+def test_mixed_geometry_batch_equals_each_problem_alone(mix):
+    name, geoms, J, tf = mix
+    extra = dict(prior=False, lambda_S=0.02) if tf == "tfft" else dict(levels=J)
+    ps = [synth.small(**g, accel=3, rank=2, nblobs=3, seed=300 + k, **extra)
+          for k, g in enumerate(geoms)]
+    kws = [dict(), dict(max_iter=4, check_every=2), dict(max_iter=7, check_every=7)][:len(ps)]
+    outs, sts = batch_solve(ps, J, tf, kws)
+    for k, (p, kw) in enumerate(zip(ps, kws)):
+        o1, s1 = solo(p, J, tf, **kw)
+        for key in KEYS:
+            assert torch.equal(outs[k][key], o1[key]), (k, key)
+        assert sts[k]["iters"] == s1["iters"] == params_for(p, **kw)["max_iter"]
+        assert sts[k]["resid_norm"] == s1["resid_norm"]
+        assert sts[k]["l1_weighted"] == s1["l1_weighted"]
+    # the largest problem against the FP64 oracle
+    k = max(range(len(ps)), key=lambda i: ps[i].nx * ps[i].nt * ps[i].nc)
+    p = ps[k]
+    r = oracle.solve(p.kspace, p.mask, p.sens, p.prior_w, p.lambda_L, p.lambda_S, levels=J,
+                     iters=params_for(p, **kws[k])["max_iter"], transform=tf)
+    for key in KEYS:
+        e = rel(host(outs[k][key]), r[key])
+        assert e < TOL, (key, e)
+
+
+def test_mixed_geometry_batched_step_from_different_iteration_counts():
+    name, geoms, J, tf = MIXED[0]
+    ps = [synth.small(**g, accel=3, rank=2, nblobs=3, seed=320 + k, levels=J)
+          for k, g in enumerate(geoms)]
+    counts = [3, 6, 5]
+    hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) for p in ps]
+    try:
+        for h, p, c in zip(hs, ps, counts):
+            t = pls.to_device(p)
+            h.solve(t["kspace"], t["mask"], t["sens"], t["prior_w"], outputs=(),
+                    **params_for(p, max_iter=c, check_every=2))
+        with pls.Batch(hs) as b:
+            outs, sts = b.step(4)
+    finally:
+        for h in hs:
+            h.close()
+    for k, (p, c) in enumerate(zip(ps, counts)):
+        o1, s1 = solo(p, J, tf, max_iter=c + 4, check_every=2)
+        assert sts[k]["iters"] == c + 4
+        for key in KEYS:
+            assert torch.equal(outs[k][key], o1[key]), (k, key)
 
 
 @pytest.mark.skip(reason="the batch autotuner was withdrawn: the process aborted (exit 134, no "
