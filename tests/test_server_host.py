@@ -40,13 +40,16 @@ def test_server_logic_under_sanitizer(tmp_path, san):
 RT = os.path.join(HERE, "runtime_host")
 
 
-@pytest.mark.parametrize("san", ["thread", "address,undefined"])
-def test_runtime_and_server_host_code_under_sanitizer(tmp_path, san):
+@pytest.mark.parametrize("san,mode", [("thread", ""), ("address,undefined", ""),
+                                      ("address,undefined", "full")],
+                         ids=["thread", "address", "address_full_size"])
+def test_runtime_and_server_host_code_under_sanitizer(tmp_path, san, mode):
     """The library's own runtime (pls_runtime.hip) and server, host code as built for the GPU,
     against a HIP stand-in whose streams run asynchronously on threads and kernel stand-ins
     that touch their arrays at full extent: sequences of five geometries, up to four of one
     geometry in flight as a batched group, evictions and sample-store growth, then the
-    synchronous API from four threads and batches."""
+    synchronous API from four threads and batches.  "full": the serving volume classes at
+    their real sizes, four 192x192x32 x 30 frames x 8 coils sequences in flight."""
     if shutil.which("g++") is None:
         pytest.skip("no g++")
     csrc = os.path.join(ROOT, "paper_1411_6206_amd", "csrc")
@@ -59,7 +62,8 @@ def test_runtime_and_server_host_code_under_sanitizer(tmp_path, san):
     subprocess.run(cmd, check=True, capture_output=True)
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1",
                ASAN_OPTIONS="halt_on_error=1:detect_leaks=0")
-    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=600, env=env)
+    r = subprocess.run([str(exe)] + ([mode] if mode else []), capture_output=True, text=True,
+                       timeout=600, env=env)
     print(r.stdout[-2000:], r.stderr[-4000:])
     assert r.returncode == 0
     assert "WARNING: ThreadSanitizer" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
