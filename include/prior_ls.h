@@ -72,6 +72,8 @@ extern "C" {
                                    are then [nt (frequency)][nz][ny][nx] and wavelet_levels
                                    is not used */
 
+/* Frames per window at most.  The Gram tiles in registers, the one-block eigensolver's LDS
+ * and the 64 x 64 back-projection operand are sized for 32 frames; larger nt is ESHAPE. */
 #define PRIOR_LS_MAX_NT 32
 
 typedef struct prior_ls_handle prior_ls_handle;   /* opaque; owns all device state */
@@ -114,8 +116,9 @@ typedef struct {
     const uint8_t *mask;        /* uint8 [nt][nz][ny], required */
     const void    *sens;        /* complex64 [nc][nz][ny][nx]; NULL only when nc == 1 */
     const uint8_t *prior_w;     /* uint8 [nt][nz][ny][nx] canonical Haar layout, or NULL */
-    const double  *sigma_prev;  /* HOST, nt doubles (singular values of L^(t-1), any order);
-                                   required when lambda_p > 0, else ignored */
+    const double  *sigma_prev;  /* HOST, nt doubles (singular values of L^(t-1), any order),
+                                   copied during the call (it is sorted and padded on the
+                                   host); required when lambda_p > 0, else ignored */
     const void    *L0, *S0;     /* complex64 [nt][nz][ny][nx] warm start: both or neither.
                                    Cold: L = X_0 = A^H d, S = 0.  Warm: L = L0, S = S0 and
                                    X_0 = Y - A^H(A Y - d) with Y = L0 + S0 */
