@@ -31,7 +31,12 @@ struct DcCfg {
     // Y = L + S is parked in the output array between coils (not kept in registers), and
     // the frame's sample indices of the thread's points stay in registers (two per
     // register) instead of being looked up in LDS for every coil
-    using G = Geom<NY, NZ, PB, Q, 0, 32, 2>;
+    // LDS rows of the wide configuration are padded by 8 points: a row of 192 points is a
+    // multiple of the 256-byte bank period, so the 8-lane row segments of a y pass from
+    // different rows fell on the same 16 banks; with the padding consecutive rows start 16
+    // banks apart (bank conflicts -32%, 1.59 -> 1.56 ms at 192x32 x 30 frames x 8 coils)
+    static constexpr int PADY = (kWide && Q == 24) ? 8 : 0;
+    using G = Geom<NY, NZ, PB, Q, PADY, 32, 2>;
 };
 
 // Register distribution of a first pass of radix R along axis AX: element (i, r) of a
@@ -229,18 +234,20 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
         };
         if (staged) residual(std::true_type{});
         else residual(std::false_type{});
-        fft2_inv<G>(v, lds, twt, tidc);
+        // the coil map of the accumulation is loaded before the last inverse pass, so the
+        // loads are in flight during its LDS reads and arithmetic
+        fft2_inv<G, 1>(v, lds, twt, tidc);
+        float2 sacc[Q];
 #pragma unroll
         for (int i = 0; i < D0::NB; ++i) {
             const int pbc = min(e0.pb[i], nvalid - 1);
             const int o = pbc * P + e0.rel[i];
 #pragma unroll
-            for (int r = 0; r < R0; ++r) {
-                const int q = i * R0 + r;
-                const float2 sv = sc[o + r * D0::STEP];
-                acc[q] = cadd(acc[q], cmulc(v[q], sv));
-            }
+            for (int r = 0; r < R0; ++r) sacc[i * R0 + r] = sc[o + r * D0::STEP];
         }
+        fft2_inv<G, 2>(v, lds, twt, tidc);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q] = cadd(acc[q], cmulc(v[q], sacc[q]));
     }
 #pragma unroll
     for (int i = 0; i < D0::NB; ++i) {

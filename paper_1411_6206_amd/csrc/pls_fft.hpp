@@ -379,13 +379,16 @@ __device__ __forceinline__ void fft2_fwd(float2 (&v)[G::Q], float2* lds, const f
 
 // Inverse 2D transform (unnormalised): z passes in descending radix order, then y passes
 // in descending order.  Reads the registers fft2_fwd left and returns them in the
-// distribution fft2_fwd read.
-template <class G>
+// distribution fft2_fwd read.  PART selects the passes: 0 all, 1 all but the last (which
+// leaves its result in LDS), 2 the last only (reads LDS, returns the registers), so that a
+// caller can issue global loads between the two.
+template <class G, int PART = 0>
 __device__ __forceinline__ void fft2_inv(float2 (&v)[G::Q], float2* lds, const float2* twt,
                                          int tid) {
     constexpr int NPY = G::NPY, NPZ = G::NPZ, NP = NPY + NPZ;
     sfor<NP>([&](auto pI) __attribute__((always_inline)) {
         constexpr int p = decltype(pI)::value;
+        if constexpr ((PART == 1 && p == NP - 1) || (PART == 2 && p != NP - 1)) return;
         constexpr bool IN_REG = (p == 0);
         constexpr bool OUT_REG = (p == NP - 1);
         if constexpr (p < NPZ) {

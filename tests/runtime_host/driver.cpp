@@ -74,7 +74,55 @@ static void make_seq(Seq& q, std::mt19937& rng) {
     r.latency_ms = q.lat.data();
 }
 
+// "tune": the GPU autotuner test's sequence (32x48x8 x 12 frames x 3 coils, J = 2, chunks of
+// 4): tune, step 12 and destroy; a fresh handle with the choice set by hand solves 12; a
+// third with the choice set solves 0 iterations, steps 12 and is destroyed
+static int tune_sequence(int rounds) {
+    const int nx = 32, ny = 48, nz = 8, nt = 12, nc = 3;
+    const size_t P = (size_t)ny * nz, img = P * nx;
+    std::mt19937 rng(5);
+    void* k = dev_alloc((size_t)nc * nt * img * 8);
+    void* sens = dev_alloc((size_t)nc * img * 8);
+    uint8_t* m = (uint8_t*)dev_alloc((size_t)nt * P);
+    uint8_t* w = (uint8_t*)dev_alloc((size_t)nt * img);
+    void* X[4];
+    for (auto& x : X) x = dev_alloc((size_t)nt * img * 8);
+    for (size_t i = 0; i < (size_t)nt * P; ++i) m[i] = rng() % 3 == 0;
+    prior_ls_dims d{sizeof(prior_ls_dims), nx, ny, nz, nt, nc, 2, 0, 0, 0};
+    prior_ls_params prm{sizeof(prior_ls_params), 0.01, 0.01, 0.0, 0.0, 1, 12, 4, 1};
+    prior_ls_inputs in{k, m, sens, w, nullptr, nullptr, nullptr};
+    prior_ls_outputs out{X[0], X[1], X[2], X[3]};
+    int bad = 0;
+    for (int r = 0; r < rounds; ++r) {
+        prior_ls_tuning best{};
+        best.struct_size = sizeof(best);
+        prior_ls_stats st{};
+        st.struct_size = sizeof(st);
+        prior_ls_handle* h = nullptr;
+        if (prior_ls_create(&d, nullptr, &h) || prior_ls_tune(h, &in, &prm, &best)) ++bad;
+        if (prior_ls_step(h, 12, &out, &st) || st.iters != 12) ++bad;
+        prior_ls_destroy(h);
+        best.ms_per_iteration = 0.0;
+        h = nullptr;
+        if (prior_ls_create(&d, nullptr, &h) || prior_ls_set_tuning(h, &best)) ++bad;
+        if (prior_ls_solve(h, &in, &prm, &out, &st) || st.iters != 12) ++bad;
+        prior_ls_destroy(h);
+        h = nullptr;
+        prior_ls_params p0 = prm;
+        p0.max_iter = 0;
+        if (prior_ls_create(&d, nullptr, &h) || prior_ls_set_tuning(h, &best)) ++bad;
+        if (prior_ls_solve(h, &in, &p0, nullptr, &st) || prior_ls_step(h, 12, &out, &st)) ++bad;
+        prior_ls_destroy(h);
+        std::printf("tune round %d: fork %d gram %d bp %d sparse grid %d\n", r, best.sparse_fork,
+                    best.gram_blocks, best.bp_grid, best.sparse_grid);
+    }
+    for (void* p : {k, sens, (void*)m, (void*)w, X[0], X[1], X[2], X[3]}) hipFree(p);
+    std::printf("tune done: bad %d\n", bad);
+    return bad != 0;
+}
+
 int main(int argc, char** argv) {
+    if (argc > 1 && std::strcmp(argv[1], "tune") == 0) return tune_sequence(5);
     const bool full = argc > 1 && std::strcmp(argv[1], "full") == 0;
     if (full) kGeo = kFull;
     std::mt19937 rng(11);

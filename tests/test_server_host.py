@@ -71,3 +71,30 @@ def test_runtime_and_server_host_code_under_sanitizer(tmp_path, san, mode):
     # sequences of one geometry ran together as a batched group
     import re
     assert int(re.search(r"peak_active (\d+)", r.stdout).group(1)) >= 2
+
+
+@pytest.mark.parametrize("san", ["address,undefined", "thread"])
+def test_autotuner_sequence_host_code_under_sanitizer(tmp_path, san):
+    """The autotuner's host code (prior_ls_tune: a reload, a captured chunk and two replays per
+    candidate, graphs destroyed between candidates) in the GPU tuner test's exact sequence,
+    five times: tune, step, destroy; a fresh handle with the choice set by hand solves; a
+    third loads, steps and is destroyed."""
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    csrc = os.path.join(ROOT, "paper_1411_6206_amd", "csrc")
+    exe = tmp_path / "rt"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", f"-fsanitize={san}", "-DPLS_SERVER_MAX_IN_FLIGHT=4",
+           "-I", RT, "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           "-x", "c++", os.path.join(csrc, "pls_runtime.hip"), os.path.join(csrc, "pls_server.hip"),
+           "-x", "none", os.path.join(RT, "kernels_stub.cpp"), os.path.join(RT, "driver.cpp"),
+           "-o", str(exe), "-lpthread"]
+    subprocess.run(cmd, check=True, capture_output=True)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1",
+               ASAN_OPTIONS="halt_on_error=1:detect_leaks=0:detect_stack_use_after_return=1",
+               UBSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([str(exe), "tune"], capture_output=True, text=True, timeout=600, env=env)
+    print(r.stdout[-2000:], r.stderr[-4000:])
+    assert r.returncode == 0
+    assert "WARNING: ThreadSanitizer" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
+    assert "runtime error" not in r.stderr
+    assert "tune done: bad 0" in r.stdout and r.stdout.count("tune round") == 5
