@@ -31,12 +31,17 @@ struct DcCfg {
     // Y = L + S is parked in the output array between coils (not kept in registers), and
     // the frame's sample indices of the thread's points stay in registers (two per
     // register) instead of being looked up in LDS for every coil
-    // LDS rows of the wide configuration are padded by 8 points: a row of 192 points is a
-    // multiple of the 256-byte bank period, so the 8-lane row segments of a y pass from
-    // different rows fell on the same 16 banks; with the padding consecutive rows start 16
-    // banks apart (bank conflicts -32%, 1.59 -> 1.56 ms at 192x32 x 30 frames x 8 coils)
-    static constexpr int PADY = (kWide && Q == 24) ? 8 : 0;
-    using G = Geom<NY, NZ, PB, Q, PADY, 32, 2>;
+    // LDS rows carry one unused point per 16 (Geom YSW = 16): the first pass of each y
+    // transform (stage length 1) writes butterfly j's points to y = j R + r, a stride of R
+    // points, and with unpadded rows of a power-of-two length a stride of 8 or 16 points put
+    // the lanes of a write on the same few banks.  Measured on one data-consistency pass
+    // (same outputs bit for bit): 128x16 planes -7% (1 coil) and -14% (4 coils), 64x8 -4% /
+    // -10%, 192x32 x 8 coils -3%.  Not for nz = 14 (its 28-point tile then spills
+    // registers, +10%) nor the 12-point 192-wide planes (no conflicts to remove).  Rows are
+    // PADY points longer still where that spreads the row-to-row lanes of a pass further.
+    static constexpr int YSW = (kHas7 || (NY == 192 && Q == 12)) ? 0 : 16;
+    static constexpr int PADY = YSW == 0 ? 0 : (Q == 24 ? 12 : (NY == 48 ? 4 : (NY == 96 ? 2 : 0)));
+    using G = Geom<NY, NZ, PB, Q, PADY, 32, 2, YSW>;
 };
 
 // Register distribution of a first pass of radix R along axis AX: element (i, r) of a

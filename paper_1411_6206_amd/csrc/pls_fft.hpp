@@ -189,15 +189,24 @@ constexpr int tw_find(const TwPlan& t, int R, int LS) {
 }
 
 // ---------------------------------------------------------------- plane geometry
-template <int NY_, int NZ_, int PB_, int Q_, int PADY_, int RMAX_ = 32, int MINW_ = 1>
+template <int NY_, int NZ_, int PB_, int Q_, int PADY_, int RMAX_ = 32, int MINW_ = 1,
+          int YSW_ = 0>
 struct Geom {
     static constexpr int NY = NY_, NZ = NZ_, PB = PB_, Q = Q_;
     static constexpr int MINW = MINW_;   // launch bound: minimum waves per SIMD
     static constexpr int P = NY * NZ;
     static constexpr int T = PB * P / Q;
-    // LDS layout: plane pb, row z, column y at pb * PS + z * LDY + y.  Every access of a
-    // pass is a per-butterfly base plus a compile-time offset (ds_read/ds_write immediate).
-    static constexpr int LDY = NY + PADY_;
+    // LDS layout: plane pb, row z, column y at pb * PS + z * LDY + ycol(y).  With YSW = 0
+    // ycol(y) = y; with YSW = 16 one unused point follows every 16 points of a row,
+    // ycol(y) = y + y / 16, so that the stride-R writes of a radix-R pass of stage length 1
+    // (butterfly j writes y = j R + r) spread over the banks.  Every access of a pass is a
+    // per-butterfly base plus a compile-time offset (ds_read/ds_write immediate); the padded
+    // rows need a second base where a butterfly's points straddle a padding point (YCarry).
+    // Rows are PADY points longer still.
+    static constexpr int YSW = YSW_;
+    static_assert(YSW == 0 || YSW == 16, "row padding: none or one point per 16");
+    static constexpr int LDY = NY + (YSW > 0 ? NY / YSW : 0) + PADY_;
+    __device__ static __forceinline__ int ycol(int y) { return YSW > 0 ? y + (y >> 4) : y; }
     static constexpr int PS = LDY * NZ;
     static constexpr int LDS_ELEMS = PS * PB;
     static constexpr RadixPlan PY = plan_axis(NY, Q, RMAX_);
@@ -255,7 +264,7 @@ struct PassMap {
     // LDS offset of point 0 of a line
     __device__ static __forceinline__ int lbase(int line) {
         if constexpr (AX == 0) return (line / G::NZ) * G::PS + (line % G::NZ) * G::LDY;
-        else return (line / G::NY) * G::PS + (line % G::NY);
+        else return (line / G::NY) * G::PS + G::ycol(line % G::NY);
     }
     // (plane, z, y) of element (i, r) in the distribution a first pass of this radix reads
     __device__ static __forceinline__ void pos(int tid, int i, int r, int& pb, int& z, int& y) {
@@ -280,6 +289,78 @@ __device__ __forceinline__ void pass_pos(int tid, int i, int r, int& pb, int& z,
     PassMap<G, AX, R>::pos(tid, i, r, pb, z, y);
 }
 
+// Padded rows (YSW = 16): a y pass touches y = y0 + c, with y0 the butterfly's
+// lane-dependent part and c = r * step a compile-time constant.  Its column is
+// ycol(y0) + c + c / 16 + carry, carry = ((y0 % 16) + (c % 16)) / 16.  The values y0 % 16
+// can take in the pass are known at compile time; per r the carry is then never, always,
+// or set exactly for the lanes with y0 % 16 >= thr[k] for one of a few thresholds.
+struct YCarry {
+    int cls[32];   // per r: -1 carry never, -2 always, k >= 0 threshold class k
+    int thr[16];
+    int nthr;
+};
+
+// y0 of butterfly k (lane + 64 i) of a y pass of radix R, stage length LS: the first point
+// read (WRITE false) or written (WRITE true).
+constexpr int ypass_y0(int k, int JN, int R, int LS, bool WRITE) {
+    const int j = k % JN;
+    return WRITE ? (j / LS) * LS * R + j % LS : j;
+}
+
+constexpr YCarry ycarry(int NBK, int JN, int R, int LS, bool WRITE) {
+    YCarry c{{}, {}, 0};
+    bool can[16] = {};
+    for (int k = 0; k < NBK; ++k) can[ypass_y0(k, JN, R, LS, WRITE) & 15] = true;
+    for (int r = 0; r < R; ++r) {
+        const int d = (WRITE ? r * LS : r * JN) & 15;
+        // smallest possible y0 % 16 that carries, and whether every possible value does
+        int lo = 16;
+        bool all = true;
+        for (int u = 0; u < 16; ++u) {
+            if (!can[u]) continue;
+            if (u + d >= 16) lo = lo < u ? lo : u;
+            else all = false;
+        }
+        if (lo == 16) {
+            c.cls[r] = -1;
+        } else if (all) {
+            c.cls[r] = -2;
+        } else {
+            int k = 0;
+            while (k < c.nthr && c.thr[k] != lo) ++k;
+            if (k == c.nthr) c.thr[c.nthr++] = lo;
+            c.cls[r] = k;
+        }
+    }
+    return c;
+}
+
+// LDS offsets of the points r of butterfly (base = row base, y0) of a padded y pass, into
+// off[]: one runtime base per threshold class, the rest compile-time immediates.
+template <int R, int STEP, YCarry const& C>
+__device__ __forceinline__ void ypad_offsets(int base, int y0, int (&off)[R]) {
+    const int b0 = base + y0 + (y0 >> 4);
+    int bk[C.nthr > 0 ? C.nthr : 1];
+    sfor<C.nthr>([&](auto kI) __attribute__((always_inline)) {
+        constexpr int k = decltype(kI)::value;
+        constexpr int t = C.thr[k];
+        bk[k] = b0 + ((y0 & 15) >= t ? 1 : 0);
+    });
+    sfor<R>([&](auto rI) __attribute__((always_inline)) {
+        constexpr int r = decltype(rI)::value;
+        constexpr int c = r * STEP;
+        constexpr int cl = C.cls[r];
+        constexpr int imm = c + (c >> 4) + (cl == -2 ? 1 : 0);
+        if constexpr (cl >= 0) off[r] = bk[cl] + imm;
+        else off[r] = b0 + imm;
+    });
+}
+
+template <int NBK, int JN, int R, int LS, bool WRITE>
+struct YCarryOf {
+    static constexpr YCarry value = ycarry(NBK, JN, R, LS, WRITE);
+};
+
 // One Stockham pass.  With TWOFF < 0, tw = exp(-2 pi i m / N), m in [0, N), for this axis'
 // length N; otherwise tw is a block of per-pass tables (TwPlan) and this pass' factors sit at
 // TWOFF + (r - 1) LS + k.  Reads follow a block barrier or a wave-local sync of the previous
@@ -298,12 +379,20 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const f
         M::map(tid, i, line, jj[i]);
         base[i] = M::lbase(line);
     }
+    constexpr bool PADDED = (AX == 0 && G::YSW > 0);
     if constexpr (!IN_REG) {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            const float2* src = lds + base[i] + jj[i] * STRIDE;
+            if constexpr (PADDED) {
+                int off[R];
+                ypad_offsets<R, JN, YCarryOf<64 * NB, JN, R, LS, false>::value>(base[i], jj[i], off);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[i * R + r] = src[r * JN * STRIDE];
+                for (int r = 0; r < R; ++r) v[i * R + r] = lds[off[r]];
+            } else {
+                const float2* src = lds + base[i] + jj[i] * STRIDE;
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i * R + r] = src[r * JN * STRIDE];
+            }
         }
     }
 #pragma unroll
@@ -325,9 +414,17 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[G::Q], float2* lds, const f
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int j = jj[i];
-            float2* dst = lds + base[i] + ((j / LS) * LS * R + (j % LS)) * STRIDE;
+            if constexpr (PADDED) {
+                int off[R];
+                ypad_offsets<R, LS, YCarryOf<64 * NB, JN, R, LS, true>::value>(
+                    base[i], (j / LS) * LS * R + (j % LS), off);
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * LS * STRIDE] = v[i * R + r];
+                for (int r = 0; r < R; ++r) lds[off[r]] = v[i * R + r];
+            } else {
+                float2* dst = lds + base[i] + ((j / LS) * LS * R + (j % LS)) * STRIDE;
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst[r * LS * STRIDE] = v[i * R + r];
+            }
         }
         PLS_WAVE_SYNC();
     }
