@@ -49,7 +49,9 @@ def algorithmic(name, p, nsamp):
         dh = p.nx * p.nc * nsamp * 8      # compact hybrid k-space, sampled entries only
         sens = p.nc * N * 8 if p.nc > 1 else 0
         b = 3 * I + dh + sens + p.nt * P * 2
-        f = p.nc * p.nt * p.nx * 2 * 5 * P * math.log2(P) + p.nc * p.nt * N * 14
+        # two 2D FFTs per coil and frame (5 n log2 n each) and the two coil multiplies
+        # (6 flops each: C_c Y before the forward transform, conj(C_c) (.) after the inverse)
+        f = p.nc * p.nt * p.nx * 2 * 5 * P * math.log2(P) + p.nc * p.nt * N * 12
         return b, f
     if name == "gram":
         return I, 8 * N * p.nt ** 2
