@@ -16,7 +16,8 @@ Conventions (user layout, x fastest):
   d (k-space)       complex [nc][nt][nz][ny][nx], entries off the mask ignored
   mask              uint8   [nt][nz][ny]   (phase-encode lines, broadcast over kx)
   sens              complex [nc][nz][ny][nx] or None (single unit coil)
-  prior_w           uint8   [nt][nz][ny][nx] canonical Haar layout, w = q/255, or None
+  prior_w           uint8   [nt][nz][ny][nx] in T's canonical coefficient layout, w = q/255,
+                    or None
 """
 from __future__ import annotations
 
@@ -155,15 +156,90 @@ def tfft_inv(c):
     return np.fft.ifft(np.asarray(c, np.complex128), axis=0, norm="ortho")
 
 
-TRANSFORMS = ("haar", "tfft")
+# --------------------------------------------------------------------------------------
+# A third sparsifying transform: another wavelet family (Section 2, "such as Wavelets";
+# Section 5 names other transforms as future work).  Reading: the orthonormal Daubechies
+# wavelet with four taps (two vanishing moments), periodic extension, in the standard
+# (tensor-product) decomposition: the full J-level 1D transform along x, then along y, then
+# along z, every spatial axis of size > 1; coefficients in canonical Mallat order along each
+# axis, [a_J | d_J | d_{J-1} | ... | d_1].
+# Analysis: a_k = sum_m h_m u[(2k + m) mod n], d_k = sum_m g_m u[(2k + m) mod n], with
+# g_m = (-1)^m h_{3-m}; synthesis is the adjoint (the filter bank is orthonormal).
+# --------------------------------------------------------------------------------------
+_S3 = np.sqrt(3.0)
+DB4_H = np.array([1 + _S3, 3 + _S3, 3 - _S3, 1 - _S3]) / (4 * np.sqrt(2.0))
+DB4_G = np.array([(-1) ** m * DB4_H[3 - m] for m in range(4)])
+
+
+def _db4_step(u, axis):
+    """One analysis level along `axis` (length n, even): returns [a | d] along that axis."""
+    u = np.moveaxis(np.asarray(u, np.complex128), axis, -1)
+    n = u.shape[-1]
+    a = np.zeros(u.shape[:-1] + (n // 2,), np.complex128)
+    d = np.zeros_like(a)
+    for k in range(n // 2):
+        for m in range(4):
+            v = u[..., (2 * k + m) % n]
+            a[..., k] += DB4_H[m] * v
+            d[..., k] += DB4_G[m] * v
+    return np.moveaxis(np.concatenate([a, d], axis=-1), -1, axis)
+
+
+def _db4_step_inv(c, axis):
+    """Adjoint of _db4_step: u[(2k + m) mod n] += h_m a_k + g_m d_k."""
+    c = np.moveaxis(np.asarray(c, np.complex128), axis, -1)
+    n = c.shape[-1]
+    a, d = c[..., : n // 2], c[..., n // 2:]
+    u = np.zeros_like(c)
+    for k in range(n // 2):
+        for m in range(4):
+            u[..., (2 * k + m) % n] += DB4_H[m] * a[..., k] + DB4_G[m] * d[..., k]
+    return np.moveaxis(u, -1, axis)
+
+
+def db4_fwd(x, levels):
+    """T: image [..., nz, ny, nx] -> coefficients (same shape), J levels along each axis."""
+    c = np.array(x, np.complex128, copy=True)
+    for ax in _active_axes(c.shape[-3:]):
+        n = c.shape[ax]
+        for j in range(levels):
+            m = n >> j
+            idx = [slice(None)] * c.ndim
+            idx[ax] = slice(0, m)
+            c[tuple(idx)] = _db4_step(c[tuple(idx)], ax)
+    return c
+
+
+def db4_inv(c, levels):
+    """T^{-1} = T^H (orthonormal): coefficients -> image."""
+    x = np.array(c, np.complex128, copy=True)
+    for ax in reversed(_active_axes(x.shape[-3:])):
+        n = x.shape[ax]
+        for j in reversed(range(levels)):
+            m = n >> j
+            idx = [slice(None)] * x.ndim
+            idx[ax] = slice(0, m)
+            x[tuple(idx)] = _db4_step_inv(x[tuple(idx)], ax)
+    return x
+
+
+TRANSFORMS = ("haar", "tfft", "db4")
 
 
 def T_fwd(x, levels, transform="haar"):
-    return haar_fwd(x, levels) if transform == "haar" else tfft_fwd(x)
+    if transform == "haar":
+        return haar_fwd(x, levels)
+    if transform == "db4":
+        return db4_fwd(x, levels)
+    return tfft_fwd(x)
 
 
 def T_inv(c, levels, transform="haar"):
-    return haar_inv(c, levels) if transform == "haar" else tfft_inv(c)
+    if transform == "haar":
+        return haar_inv(c, levels)
+    if transform == "db4":
+        return db4_inv(c, levels)
+    return tfft_inv(c)
 
 
 # --------------------------------------------------------------------------------------
@@ -354,7 +430,7 @@ def append_frame(prev, d, mask, sens, d_new, mask_new, lambda_L, lambda_S, lambd
     mask_next = shift_window(mask, mask_new)
     L0 = shift_window(prev["L"], prev["L"][-1])
     S0 = shift_window(prev["S"], prev["S"][-1])
-    if transform == "haar":
+    if transform in ("haar", "db4"):
         w = shift_window(prev["supp"], prev["supp"][-1])
     else:
         w = np.array(prev["supp"], copy=True)

@@ -436,6 +436,106 @@ def test_tfft_full_weight_prior_passes_everything():
     np.testing.assert_allclose(S, X, atol=1e-12)
 
 
+# ---- the Daubechies-4 wavelet (db4), standard decomposition, periodic ----------------------
+def test_db4_filter_taps_and_identities():
+    # the published four-tap Daubechies scaling filter, and the identities that make the
+    # two-channel bank orthonormal with two vanishing moments
+    np.testing.assert_allclose(oracle.DB4_H, [0.48296291314453416, 0.83651630373780794,
+                                              0.22414386804201339, -0.12940952255126037],
+                               atol=1e-15)
+    h, g = oracle.DB4_H, oracle.DB4_G
+    assert h.sum() == pytest.approx(np.sqrt(2.0), abs=1e-15)
+    assert (h * h).sum() == pytest.approx(1.0, abs=1e-15)
+    assert h[0] * h[2] + h[1] * h[3] == pytest.approx(0.0, abs=1e-16)   # even shifts orthogonal
+    assert (g * g).sum() == pytest.approx(1.0, abs=1e-15)
+    assert (h * g).sum() == pytest.approx(0.0, abs=1e-16)
+    assert h[0] * g[2] + h[1] * g[3] == pytest.approx(0.0, abs=1e-16)
+    m = np.arange(4)
+    assert g.sum() == pytest.approx(0.0, abs=1e-15)                     # vanishing moment 0
+    assert (m * g).sum() == pytest.approx(0.0, abs=1e-15)               # vanishing moment 1
+    assert (m * m * g).sum() != pytest.approx(0.0, abs=1e-3)            # but not moment 2
+
+
+@pytest.mark.parametrize("shape,J", [((1, 1, 8), 1), ((1, 1, 16), 2), ((1, 4, 8), 1),
+                                     ((4, 8, 8), 2), ((2, 8, 16), 1)])
+def test_db4_orthonormal(shape, J):
+    # the transform matrix built column by column is unitary (real orthogonal), so the
+    # inverse is its adjoint and energy is kept
+    rng = np.random.default_rng(44 + J)
+    n = int(np.prod(shape))
+    T = np.stack([oracle.db4_fwd(np.eye(n)[k].reshape(shape), J).reshape(-1)
+                  for k in range(n)], 1)
+    np.testing.assert_allclose(T.conj().T @ T, np.eye(n), atol=1e-13)
+    x = rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)
+    c = oracle.db4_fwd(x, J)
+    np.testing.assert_allclose(oracle.db4_inv(c, J), x, atol=1e-13)
+    assert np.linalg.norm(c) == pytest.approx(np.linalg.norm(x), rel=1e-13)
+
+
+def test_db4_vanishing_moments_on_a_ramp():
+    # a linear ramp along x: every detail coefficient whose four-tap window does not wrap
+    # around the periodic boundary is zero; a constant has no detail at all and its
+    # approximation is sqrt(2) times the constant
+    n = 16
+    xs = np.arange(n, dtype=float)
+    ramp = (0.3 - 0.2j) + (0.05 + 0.01j) * xs
+    c = oracle.db4_fwd(ramp.reshape(1, 1, 1, n), 1)[0, 0, 0]
+    d = c[n // 2:]
+    np.testing.assert_allclose(d[: n // 2 - 1], 0.0, atol=1e-14)
+    assert abs(d[-1]) > 1e-3                                           # the wrapped window
+    k = np.full((1, 1, 1, n), 2.5 - 1.0j)
+    c = oracle.db4_fwd(k, 1)[0, 0, 0]
+    np.testing.assert_allclose(c[n // 2:], 0.0, atol=1e-14)
+    np.testing.assert_allclose(c[: n // 2], np.sqrt(2.0) * (2.5 - 1.0j), atol=1e-14)
+
+
+def test_db4_one_level_matches_the_filter_bank_definition():
+    # one level along a periodic axis of length 8, written out as the analysis matrix:
+    # row k of the low half holds h_m at column (2k + m) mod 8, of the high half g_m
+    n = 8
+    A = np.zeros((n, n))
+    for k in range(n // 2):
+        for m in range(4):
+            A[k, (2 * k + m) % n] += oracle.DB4_H[m]
+            A[n // 2 + k, (2 * k + m) % n] += oracle.DB4_G[m]
+    rng = np.random.default_rng(45)
+    u = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    np.testing.assert_allclose(oracle.db4_fwd(u.reshape(1, 1, 1, n), 1)[0, 0, 0], A @ u,
+                               atol=1e-14)
+
+
+def test_db4_standard_decomposition_is_separable():
+    # a separable volume f(z) g(y) h(x) transforms to the outer product of the three 1D
+    # transforms (each axis decomposed fully, independently of the others)
+    rng = np.random.default_rng(46)
+    nz, ny, nx, J = 8, 16, 8, 2
+    f = rng.standard_normal(nz) + 1j * rng.standard_normal(nz)
+    g = rng.standard_normal(ny) + 1j * rng.standard_normal(ny)
+    h = rng.standard_normal(nx) + 1j * rng.standard_normal(nx)
+    vol = f[:, None, None] * g[None, :, None] * h[None, None, :]
+    c = oracle.db4_fwd(vol[None], J)[0]
+    F = oracle.db4_fwd(f.reshape(1, 1, 1, nz), J)[0, 0, 0]
+    G = oracle.db4_fwd(g.reshape(1, 1, 1, ny), J)[0, 0, 0]
+    H = oracle.db4_fwd(h.reshape(1, 1, 1, nx), J)[0, 0, 0]
+    np.testing.assert_allclose(c, F[:, None, None] * G[None, :, None] * H[None, None, :],
+                               atol=1e-13)
+
+
+def test_db4_sparse_step_limits():
+    # lambda_S = 0 keeps X - L_prev; a threshold above every coefficient gives S = 0; a
+    # full-weight prior passes everything through
+    rng = np.random.default_rng(47)
+    X = rng.standard_normal((3, 4, 8, 8)) + 1j * rng.standard_normal((3, 4, 8, 8))
+    L = 0.3 * X
+    S, _ = oracle.sparse_step(X, L, None, 0.0, 2, transform="db4")
+    np.testing.assert_allclose(S, X - L, atol=1e-13)
+    S, Zs = oracle.sparse_step(X, L, None, 1e6, 2, transform="db4")
+    assert np.abs(S).max() == 0.0 and np.abs(Zs).max() == 0.0
+    w = np.full(X.shape, 255, np.uint8)
+    S, _ = oracle.sparse_step(X, L, w, 5.0, 2, transform="db4")
+    np.testing.assert_allclose(S, X - L, atol=1e-13)
+
+
 # ---- PSNR (Section 4's quality measure, magnitude images) ---------------------------------
 def test_psnr_closed_forms():
     rng = np.random.default_rng(43)
