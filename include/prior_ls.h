@@ -71,6 +71,10 @@ extern "C" {
                                    f of voxel v is its temporal frequency f); prior weights
                                    are then [nt (frequency)][nz][ny][nx] and wavelet_levels
                                    is not used */
+#define PRIOR_LS_T_DB4       2  /* orthonormal four-tap Daubechies wavelet, periodic, J =
+                                   wavelet_levels levels along every spatial axis of size > 1
+                                   (standard decomposition); coefficients in canonical Mallat
+                                   order along each axis, [a_J | d_J | ... | d_1] */
 
 /* Frames per window at most.  The Gram tiles in registers, the one-block eigensolver's LDS
  * and the 64 x 64 back-projection operand are sized for 32 frames; larger nt is ESHAPE. */
@@ -82,15 +86,16 @@ typedef struct prior_ls_handle prior_ls_handle;   /* opaque; owns all device sta
  * Supported: ny in {16,24,32,48,64,96,128,192,256} with nz in {1,4,8,16,32} (nz = 1 is the
  * 2D case), or nz = 14 with ny in {16,32,64,128,256} (radix 7 along z);
  * nx in {16,24,32,48,64,96,128,192,256}, 1 <= nt <= 32, 1 <= nc <= 64,
- * wavelet_levels J in [0,3] with, for the Haar transform, every spatial axis of size > 1
- * divisible by 2^J (J = 0 means T is the identity).  Anything else returns PRIOR_LS_ESHAPE. */
+ * wavelet_levels J in [0,3] with, for the Haar and Daubechies transforms, every spatial axis
+ * of size > 1 divisible by 2^J (J = 0 means T is the identity).  Anything else returns
+ * PRIOR_LS_ESHAPE. */
 typedef struct {
     size_t   struct_size;       /* = sizeof(prior_ls_dims) */
     int32_t  nx, ny, nz, nt, nc;
     int32_t  wavelet_levels;    /* J */
     int32_t  gram_mode;         /* PRIOR_LS_GRAM_* */
-    int32_t  transform;         /* sparsifying transform T: PRIOR_LS_T_HAAR (0) or
-                                   PRIOR_LS_T_TFFT (1) */
+    int32_t  transform;         /* sparsifying transform T: PRIOR_LS_T_HAAR (0),
+                                   PRIOR_LS_T_TFFT (1) or PRIOR_LS_T_DB4 (2) */
     uint64_t hbm_budget;        /* bytes of device memory the handle may own; 0 = unlimited */
 } prior_ls_dims;
 

@@ -126,6 +126,8 @@ struct SparseArgs {
                            // (0 = one per tile)
     int blocks;            // this problem's workgroups (= partial sums); set by the launcher
                            // for one problem, by the batch for each of its problems
+    int levels;            // Daubechies transform: J
+    float2* Z;             // Daubechies transform: scratch image array (coefficients)
 };
 // returns number of blocks
 int launch_sparse(int levels, const SparseArgs& a, hipStream_t s);
@@ -133,6 +135,12 @@ int launch_sparse(int levels, const SparseArgs& a, hipStream_t s);
 int sparse_haar_blocks(int levels, int nx, int ny, int nz, int nt, int max_grid);
 int launch_sparse_tfft(const SparseArgs& a, hipStream_t s);
 int sparse_tfft_blocks(int N, int nt);   // workgroups (= partial sums) of the temporal update
+// Daubechies-4 update (three passes: x lines, (y, z) planes, x lines; a.Z the scratch array,
+// a.levels J): returns the partial sums written (nt * nx, one per plane).
+int launch_sparse_db4(const SparseArgs& a, hipStream_t s);
+int sparse_db4_blocks(int nx, int nt);
+int sparse_db4_line_blocks(int ny, int nz, int nt);   // workgroups of each x-line pass
+bool db4_supported(int nx, int ny, int nz);
 
 // Change of the iterate for the stopping test: per block, sum |Y - Yold|^2 and sum |Yold|^2
 // over its elements (Y = L + S, Yold = Lold + Sold, each formed in FP32, summed in FP64).
@@ -205,6 +213,7 @@ struct Batched {
     const int* active;
     long rec_off;
     int grid;
+    int grid2 = 0;         // a second pass's grid where a launcher runs two (0: its own)
     ArgBatch<A> src() const { return ArgBatch<A>{args, active, rec_off}; }
 };
 
@@ -239,6 +248,7 @@ void launch_bp_batched(const BpArgs& a0, const Batched<BpArgs>* bt, hipStream_t 
 int launch_sparse_batched(int levels, const SparseArgs& a0, const Batched<SparseArgs>* bt,
                           hipStream_t s);
 int launch_sparse_tfft_batched(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s);
+int launch_sparse_db4_batched(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s);
 void launch_stats_batched(const StatsArgs& a0, const Batched<StatsArgs>* bt, hipStream_t s);
 void launch_change_batched(const ChangeArgs& a0, const Batched<ChangeArgs>* bt, hipStream_t s);
 int launch_dc_batched(int ny, int nz, const DcArgs& a0, const Batched<DcArgs>* bt, hipStream_t s);

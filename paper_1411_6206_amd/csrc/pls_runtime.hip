@@ -57,7 +57,8 @@ int check_dims(const prior_ls_dims* d, std::string& msg) {
         msg = "dims.struct_size mismatch";
         return PRIOR_LS_EINVAL;
     }
-    if (d->transform != PRIOR_LS_T_HAAR && d->transform != PRIOR_LS_T_TFFT) {
+    if (d->transform != PRIOR_LS_T_HAAR && d->transform != PRIOR_LS_T_TFFT &&
+        d->transform != PRIOR_LS_T_DB4) {
         msg = "unknown transform";
         return PRIOR_LS_EINVAL;
     }
@@ -91,6 +92,10 @@ int check_dims(const prior_ls_dims* d, std::string& msg) {
         return PRIOR_LS_ESHAPE;
     }
     if (d->transform == PRIOR_LS_T_TFFT) return PRIOR_LS_OK;   // J is not used
+    if (d->transform == PRIOR_LS_T_DB4 && !pls::db4_supported(d->nx, d->ny, d->nz)) {
+        msg = "unsupported shape for the Daubechies transform";
+        return PRIOR_LS_ESHAPE;
+    }
     if (!is_pow2_div(d->nx, J) || !is_pow2_div(d->ny, J) || !is_pow2_div(d->nz, J)) {
         msg = "every spatial axis of size > 1 must be divisible by 2^wavelet_levels";
         return PRIOR_LS_ESHAPE;
@@ -112,12 +117,14 @@ struct Sizes {
 // Workgroups (= partial sums) of one sparse update under a tuning.
 int sparse_launch_blocks(const prior_ls_dims& d, const prior_ls_tuning& t) {
     if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz, d.nt);
+    if (d.transform == PRIOR_LS_T_DB4) return pls::sparse_db4_blocks(d.nx, d.nt);
     return pls::sparse_haar_blocks(d.wavelet_levels, d.nx, d.ny, d.nz, d.nt, t.sparse_grid);
 }
 
 // Workgroups of the sparse update at most (any tuning): the size of its partial sums.
 int sparse_blocks(const prior_ls_dims& d) {
     if (d.transform == PRIOR_LS_T_TFFT) return pls::sparse_tfft_blocks(d.nx * d.ny * d.nz, d.nt);
+    if (d.transform == PRIOR_LS_T_DB4) return pls::sparse_db4_blocks(d.nx, d.nt);
     const int J = d.wavelet_levels;
     const int B = 1 << J;
     const int ZW = d.nz > 1 ? B : 1;
@@ -145,6 +152,7 @@ Sizes sizes_of(const prior_ls_dims& d) {
     b += (uint64_t)s.gblocks * s.gentries * 8 + s.gentries * 8;
     b += 64 * 64 * 4 + 2 * 32 * 32 * 16 + 64 * 8;
     if (d.transform == PRIOR_LS_T_TFFT) b += 2 * 64 * 64 * 4;
+    if (d.transform == PRIOR_LS_T_DB4) b += s.I * 8;      // coefficient scratch
     b += (uint64_t)s.dcb * 32 + (uint64_t)s.spb * 8 + (uint64_t)kMaxChunk * kStatRec * 8;
     s.base_bytes = b;
     return s;
@@ -173,6 +181,7 @@ struct prior_ls_handle {
     float2* sens = nullptr;
     float2* ones = nullptr;          // the unit coil of a single-coil problem (nc == 1)
     float *Wtf = nullptr, *Wti = nullptr;   // temporal transform: forward / inverse operands
+    float2* dz = nullptr;                   // Daubechies transform: coefficient scratch
     uint8_t* w = nullptr;
     bool has_w = false, has_sens = false;
     float2* dh = nullptr;
@@ -269,6 +278,12 @@ bool is_device_ptr(const void* p) {
 // Step (3) with the handle's sparsifying transform.
 int launch_sparse_any(const prior_ls_handle* h, const pls::SparseArgs& sa, hipStream_t s) {
     if (h->d.transform == PRIOR_LS_T_TFFT) return pls::launch_sparse_tfft(sa, s);
+    if (h->d.transform == PRIOR_LS_T_DB4) {
+        pls::SparseArgs a = sa;
+        a.levels = h->d.wavelet_levels;
+        a.Z = h->dz;
+        return pls::launch_sparse_db4(a, s);
+    }
     return pls::launch_sparse(h->d.wavelet_levels, sa, s);
 }
 
@@ -641,7 +656,7 @@ int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_p
     h->has_w = in->prior_w != nullptr;
     if (h->has_w)
         pls::launch_pack_weights(in->prior_w, h->w, d.nt, d.nx, d.ny, d.nz,
-                                 d.transform == PRIOR_LS_T_TFFT ? 0 : d.wavelet_levels, s);
+                                 d.transform == PRIOR_LS_T_HAAR ? d.wavelet_levels : 0, s);
     std::vector<double> sp(d.nt, 0.0);
     if (p->lambda_p > 0 && in->sigma_prev) {
         for (int i = 0; i < d.nt; ++i) sp[i] = in->sigma_prev[i];
@@ -1012,6 +1027,7 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
             h->Wtf = h->alloc<float>(64 * 64 * sizeof(float));
             h->Wti = h->alloc<float>(64 * 64 * sizeof(float));
         }
+        if (d.transform == PRIOR_LS_T_DB4) h->dz = h->alloc<float2>(sz.I * sizeof(float2));
         PLS_HIP(hipHostMalloc((void**)&h->stats_h, kStatRec * sizeof(double), hipHostMallocDefault));
         upload_twiddles(h->twx, d.nx, h->stream);
         upload_twiddles(h->twy, d.ny, h->stream);
@@ -1404,7 +1420,8 @@ struct prior_ls_batch {
     char* host = nullptr;      // pinned staging of the same layout
     size_t bytes = 0;
     size_t off[9] = {0};       // gram, reduce, eig, bp, sparse, dc, stats, change, active
-    int grid[8] = {0};         // launch grid per kernel (as off): the largest problem's
+    int grid[9] = {0};         // launch grid per kernel (as off; [8]: the Daubechies x-line
+                               // passes): the largest problem's
     std::vector<int> staged_cur;   // every problem's iterate index when the arguments were staged
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_objs;
@@ -1441,7 +1458,7 @@ T* barr(prior_ls_batch* b, char* base, int k, int phase) {
 void batch_upload_args(prior_ls_batch* b) {
     const int n = (int)b->hs.size();
     b->staged_cur.resize(n);
-    for (int k = 0; k < 8; ++k) b->grid[k] = 1;
+    for (int k = 0; k < 9; ++k) b->grid[k] = 1;
     for (int ph = 0; ph < 2; ++ph) {
         for (int i = 0; i < n; ++i) {
             prior_ls_handle* h = b->hs[i];
@@ -1488,6 +1505,8 @@ void batch_upload_args(prior_ls_batch* b) {
             sa.Wi = h->Wti;
             sa.max_grid = b->tuning.sparse_grid;
             sa.blocks = sparse_launch_blocks(d, b->tuning);
+            sa.levels = d.wavelet_levels;
+            sa.Z = h->dz;
             barr<pls::SparseArgs>(b, b->host, 4, ph)[i] = sa;
             barr<DcArgs>(b, b->host, 5, ph)[i] = dc_args(h, h->L[q], h->S[q], h->C);
             const int chb = pls::change_blocks((long)sz.I);
@@ -1497,9 +1516,11 @@ void batch_upload_args(prior_ls_batch* b) {
             barr<pls::ChangeArgs>(b, b->host, 7, ph)[i] =
                 pls::ChangeArgs{h->L[q], h->S[q], h->L[p], h->S[p], h->ch_part, (long)sz.I, chb};
             // launch grids: the largest problem's (per kernel, as the offsets)
-            const int own[8] = {gb, 0, 1, pls::bp_blocks((int)sz.N, b->tuning.bp_grid), sa.blocks,
-                                sz.dcb, 1, chb};
-            for (int k = 0; k < 8; ++k) b->grid[k] = std::max(b->grid[k], own[k]);
+            const int own[9] = {gb, 0, 1, pls::bp_blocks((int)sz.N, b->tuning.bp_grid), sa.blocks,
+                                sz.dcb, 1, chb,
+                                d.transform == PRIOR_LS_T_DB4
+                                    ? pls::sparse_db4_line_blocks(d.ny, d.nz, d.nt) : 0};
+            for (int k = 0; k < 9; ++k) b->grid[k] = std::max(b->grid[k], own[k]);
         }
     }
     PLS_HIP(hipMemcpyAsync(b->dev, b->host, b->off[8], hipMemcpyHostToDevice, b->stream));
@@ -1526,9 +1547,11 @@ void enqueue_batch_iteration(prior_ls_batch* b, int slot, bool stats, int p) {
         PLS_HIP(hipEventRecord(b->ev_fork, s));
         PLS_HIP(hipStreamWaitEvent(s2, b->ev_fork, 0));
     }
-    const pls::Batched<pls::SparseArgs> bs{n, barr<pls::SparseArgs>(b, b->dev, 4, p), act, 0, b->grid[4]};
+    const pls::Batched<pls::SparseArgs> bs{n, barr<pls::SparseArgs>(b, b->dev, 4, p), act, 0,
+                                           b->grid[4], b->grid[8]};
     const pls::SparseArgs& sa0 = barr<pls::SparseArgs>(b, b->host, 4, p)[0];
     if (d.transform == PRIOR_LS_T_TFFT) pls::launch_sparse_tfft_batched(sa0, &bs, s2);
+    else if (d.transform == PRIOR_LS_T_DB4) pls::launch_sparse_db4_batched(sa0, &bs, s2);
     else pls::launch_sparse_batched(d.wavelet_levels, sa0, &bs, s2);
     if (!serial) PLS_HIP(hipEventRecord(b->ev_join, s2));
     const pls::Batched<pls::ReduceArgs> br{n, barr<pls::ReduceArgs>(b, b->dev, 1, p), act, 0, 0};

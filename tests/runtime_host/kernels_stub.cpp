@@ -220,6 +220,27 @@ int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
     return blocks;
 }
 
+int sparse_db4_blocks(int nx, int nt) { return nx * nt; }
+int sparse_db4_line_blocks(int ny, int nz, int nt) { return nt * ((ny * nz + 31) / 32); }
+bool db4_supported(int nx, int ny, int nz) { return nx <= 256 && ny * nz <= 8192; }
+int launch_sparse_db4(const SparseArgs& a, hipStream_t s) {
+    SparseArgs c = a;
+    const int blocks = sparse_db4_blocks(c.nx, c.nt);
+    fh_stream(s)->push([c, blocks] {
+        const size_t I = (size_t)c.nx * c.ny * c.nz * c.nt;
+        look(c.C, I);
+        look(c.S, c.S ? I : 0);
+        look(c.Lp, I);
+        look(c.w, c.w ? I : 0);
+        touch(c.Z, I);
+        touch(c.Sout, I);
+        if (c.supp) touch(c.supp, I);
+        touch(c.part, (size_t)blocks);
+        work_us(40);
+    });
+    return blocks;
+}
+
 int change_blocks(long n) {
     const long b = ((n + 1) / 2 + 2047) / 2048;
     return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
@@ -284,6 +305,12 @@ int launch_sparse_batched(int levels, const SparseArgs& a0, const Batched<Sparse
     if (!bt) return launch_sparse(levels, a0, s);
     int r = 0;
     for (int b = 0; b < bt->count; ++b) r = launch_sparse(levels, bt->args[b], s);
+    return r;
+}
+int launch_sparse_db4_batched(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s) {
+    if (!bt) return launch_sparse_db4(a0, s);
+    int r = 0;
+    for (int b = 0; b < bt->count; ++b) r = launch_sparse_db4(bt->args[b], s);
     return r;
 }
 int launch_sparse_tfft_batched(const SparseArgs& a0, const Batched<SparseArgs>* bt, hipStream_t s) {
