@@ -222,16 +222,20 @@ struct Batched {
 // with argument block A by value, else for the batch *BT with the grid's z extent set to
 // the problem count.
 #define PLS_LAUNCH(GRID, BLOCK, STREAM, A, BT, KERN, ...)                                   \
+    PLS_LAUNCH_SHMEM(GRID, BLOCK, 0, STREAM, A, BT, KERN, __VA_ARGS__)
+
+// The same with SHMEM bytes of dynamic LDS.
+#define PLS_LAUNCH_SHMEM(GRID, BLOCK, SHMEM, STREAM, A, BT, KERN, ...)                      \
     do {                                                                                    \
         using PlsA_ = std::decay_t<decltype(A)>;                                            \
         if (BT) {                                                                           \
             dim3 g_ = (GRID);                                                               \
             g_.z = (unsigned)(BT)->count;                                                   \
-            hipLaunchKernelGGL((KERN<__VA_ARGS__, ::pls::ArgBatch<PlsA_>>), g_, (BLOCK), 0,  \
-                               (STREAM), (BT)->src());                                      \
+            hipLaunchKernelGGL((KERN<__VA_ARGS__, ::pls::ArgBatch<PlsA_>>), g_, (BLOCK),     \
+                               (SHMEM), (STREAM), (BT)->src());                              \
         } else {                                                                            \
             hipLaunchKernelGGL((KERN<__VA_ARGS__, ::pls::ArgOne<PlsA_>>), (GRID), (BLOCK),  \
-                               0, (STREAM), ::pls::ArgOne<PlsA_>{(A)});                      \
+                               (SHMEM), (STREAM), ::pls::ArgOne<PlsA_>{(A)});                \
         }                                                                                   \
     } while (0)
 
