@@ -76,16 +76,18 @@ extern "C" {
                                    (standard decomposition); coefficients in canonical Mallat
                                    order along each axis, [a_J | d_J | ... | d_1] */
 
-/* Frames per window at most.  The Gram tiles in registers, the one-block eigensolver's LDS
- * and the 64 x 64 back-projection operand are sized for 32 frames; larger nt is ESHAPE. */
-#define PRIOR_LS_MAX_NT 32
+/* Frames per window at most.  Windows of 33..64 frames take the wide Gram (its tiles split
+ * over the waves of a block), the 64-frame eigensolver (one LDS copy of the matrix) and the
+ * 128 x 128 back-projection operand; the temporal transform takes at most 32. */
+#define PRIOR_LS_MAX_NT 64
 
 typedef struct prior_ls_handle prior_ls_handle;   /* opaque; owns all device state */
 
 /* Problem geometry, fixed for the life of a handle.
  * Supported: ny in {16,24,32,48,64,96,128,192,256} with nz in {1,4,8,16,32} (nz = 1 is the
  * 2D case), or nz = 14 with ny in {16,32,64,128,256} (radix 7 along z);
- * nx in {16,24,32,48,64,96,128,192,256}, 1 <= nt <= 32, 1 <= nc <= 64,
+ * nx in {16,24,32,48,64,96,128,192,256}, 1 <= nt <= 64 (<= 32 with the temporal transform),
+ * 1 <= nc <= 64,
  * wavelet_levels J in [0,3] with, for the Haar and Daubechies transforms, every spatial axis
  * of size > 1 divisible by 2^J (J = 0 means T is the identity).  Anything else returns
  * PRIOR_LS_ESHAPE. */
@@ -306,7 +308,7 @@ int prior_ls_svt_noalloc(const void *C, int64_t n_vox, int32_t nt, int32_t gram_
  *
  * A batch groups `count` existing handles (1 ... 4096) that share the phase-encode plane
  * (ny, nz), transform, wavelet_levels (Haar), gram_mode, the Gram tile class (all nt <= 16,
- * or all nt in 17..32; with the temporal transform one nt) and device; nx, nt and nc may
+ * all in 17..32 or all in 33..64; with the temporal transform one nt) and device; nx, nt and nc may
  * differ from problem to problem.  It does not own them: they stay usable on their own, and
  * must outlive the batch.  Each kernel of an iteration of Algorithm 1 is launched once with
  * the problems along the grid's z axis and the largest problem's grid along x; a problem's

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(HERE, "libprior_ls.so")
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, ENONFINITE = 0, -1, -2, -3, -4, -5
 GRAM_MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 TRANSFORMS = {"haar": 0, "tfft": 1, "db4": 2}
-MAX_NT = 32
+MAX_NT = 64
 
 # every symbol include/prior_ls.h declares
 EXPORTS = ("prior_ls_create", "prior_ls_solve", "prior_ls_step", "prior_ls_destroy",

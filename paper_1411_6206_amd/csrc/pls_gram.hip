@@ -21,7 +21,7 @@ constexpr int kGramBlocks = 512;
 template <int NB>
 constexpr int npair() { return (2 * NB) * (2 * NB + 1) / 2; }
 
-int gram_tiles(int nt) { return nt <= 16 ? npair<1>() : npair<2>(); }
+int gram_tiles(int nt) { return nt <= 16 ? npair<1>() : (nt <= 32 ? npair<2>() : npair<4>()); }
 
 // Voxels per block for a target block count (0 = the default), a multiple of 128.
 int gram_vpb(int N, int target) {
@@ -290,6 +290,142 @@ __global__ void __launch_bounds__(256) pls_gram_bf16x3_kernel(SRC src) {
     gram_block_store<NP, false>(acc, red, a.part, lane, wave);
 }
 
+// ---------------------------------------------------------------- windows of 33..64 frames
+// 64 frames make 8 real-expanded column blocks and 36 tiles on and above the diagonal, too
+// many accumulators for one wave.  Here the 4 waves of a block split the tiles instead of
+// the voxels: wave w forms tiles 9 w .. 9 w + 8 (in the order of the other kernels) over every
+// voxel of the block, and writes them without a cross-wave reduction.  MODE: 0 FP64 MFMA,
+// 1 FP32 MFMA, 2 split BF16 (the lane mappings and operand splits of the kernels above).
+constexpr int kWideTiles = 36, kWideTilesPerWave = 9;
+
+struct WidePairs {
+    int I[kWideTiles], J[kWideTiles];
+};
+constexpr WidePairs wide_pairs() {
+    WidePairs t{{}, {}};
+    int p = 0;
+    for (int i = 0; i < 8; ++i)
+        for (int j = i; j < 8; ++j, ++p) {
+            t.I[p] = i;
+            t.J[p] = j;
+        }
+    return t;
+}
+constexpr WidePairs kWidePairs = wide_pairs();
+
+template <int MODE, int W>
+__device__ __forceinline__ void gram_wide_wave(const GramArgs& a, size_t vb, size_t ve, int lane) {
+    constexpr int NB = 4, NT4 = 8, PW = kWideTilesPerWave;
+    const int i16 = lane & 15, g = lane >> 4;
+    using Acc = typename std::conditional<MODE == 0, d4, f4>::type;
+    Acc acc[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) acc[q] = Acc{0, 0, 0, 0};
+    if constexpr (MODE != 2) {
+        using T = typename std::conditional<MODE == 0, double, float>::type;
+        for (size_t cb = vb; cb < ve; cb += 16) {
+            const size_t v = cb + 4 * g;
+            float2 x[NB][4];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int f = nb * 16 + i16;
+                if (f < a.nt && v < ve) {
+                    const float4* src = reinterpret_cast<const float4*>(a.C + (size_t)f * a.N + v);
+                    const float4 u0 = src[0], u1 = src[1];
+                    x[nb][0] = make_float2(u0.x, u0.y);
+                    x[nb][1] = make_float2(u0.z, u0.w);
+                    x[nb][2] = make_float2(u1.x, u1.y);
+                    x[nb][3] = make_float2(u1.z, u1.w);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) x[nb][k] = make_float2(0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                T op[NT4];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    op[nb] = (T)x[nb][k].x;
+                    op[NB + nb] = (T)x[nb][k].y;
+                }
+                sfor<PW>([&](auto qI) __attribute__((always_inline)) {
+                    constexpr int q = decltype(qI)::value;
+                    constexpr int I = kWidePairs.I[W * PW + q], J = kWidePairs.J[W * PW + q];
+                    if constexpr (MODE == 0)
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[I], op[J], acc[q], 0, 0, 0);
+                    else
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[I], op[J], acc[q], 0, 0, 0);
+                });
+            }
+        }
+    } else {
+        for (size_t cb = vb; cb < ve; cb += 32) {
+            const size_t v = cb + 8 * g;
+            bf8 hi[NT4], lo[NT4];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int f = nb * 16 + i16;
+                float re[8], im[8];
+                if (f < a.nt && v < ve) {
+                    const float4* src = reinterpret_cast<const float4*>(a.C + (size_t)f * a.N + v);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float4 u = src[k];
+                        re[2 * k] = u.x;
+                        im[2 * k] = u.y;
+                        re[2 * k + 1] = u.z;
+                        im[2 * k + 1] = u.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) re[k] = im[k] = 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const __bf16 hr = (__bf16)re[k], hm = (__bf16)im[k];
+                    hi[nb][k] = hr;
+                    lo[nb][k] = (__bf16)(re[k] - (float)hr);
+                    hi[NB + nb][k] = hm;
+                    lo[NB + nb][k] = (__bf16)(im[k] - (float)hm);
+                }
+            }
+            sfor<PW>([&](auto qI) __attribute__((always_inline)) {
+                constexpr int q = decltype(qI)::value;
+                constexpr int I = kWidePairs.I[W * PW + q], J = kWidePairs.J[W * PW + q];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], hi[J], acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], lo[J], acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[I], hi[J], acc[q], 0, 0, 0);
+            });
+        }
+    }
+    double* out = a.part + (size_t)blockIdx.x * kWideTiles * 256;
+#pragma unroll
+    for (int q = 0; q < PW; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            // FP64 MFMA output: register r holds row g + 4 r; FP32 / BF16: row 4 g + r
+            const int row = MODE == 0 ? g + 4 * r : 4 * g + r;
+            out[(W * PW + q) * 256 + row * 16 + i16] = (double)acc[q][r];
+        }
+}
+
+template <int MODE, class SRC>
+__global__ void __launch_bounds__(256) pls_gram_wide_kernel(SRC src) {
+    if (src.skip()) return;
+    GramArgs a = src.get();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t vb = (size_t)blockIdx.x * a.vox_per_block;
+    if (vb >= (size_t)a.N) return;             // beyond this problem's grid (batches)
+    const size_t ve = min((size_t)a.N, vb + a.vox_per_block);
+    switch (wave) {
+        case 0: gram_wide_wave<MODE, 0>(a, vb, ve, lane); break;
+        case 1: gram_wide_wave<MODE, 1>(a, vb, ve, lane); break;
+        case 2: gram_wide_wave<MODE, 2>(a, vb, ve, lane); break;
+        default: gram_wide_wave<MODE, 3>(a, vb, ve, lane); break;
+    }
+}
+
 // Batched: every argument block must already hold vox_per_block = gram_vpb(N, target_blocks)
 // (the kernel reads it from there); a0 is problem 0's block, for the launch shape.
 int launch_gram_batched(int mode, const GramArgs& a0, const Batched<GramArgs>* bt, hipStream_t s) {
@@ -299,7 +435,11 @@ int launch_gram_batched(int mode, const GramArgs& a0, const Batched<GramArgs>* b
     const int own = (a.N + vpb - 1) / vpb;
     const int grid = (bt && bt->grid > 0) ? bt->grid : own;
     const bool one = a.nt <= 16;
-    if (mode == PRIOR_LS_GRAM_FP32) {
+    if (a.nt > 32) {
+        if (mode == PRIOR_LS_GRAM_FP32) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_wide_kernel, 1);
+        else if (mode == PRIOR_LS_GRAM_BF16X3) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_wide_kernel, 2);
+        else PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_wide_kernel, 0);
+    } else if (mode == PRIOR_LS_GRAM_FP32) {
         if (one) PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f32_kernel, 1);
         else PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_gram_f32_kernel, 2);
     } else if (mode == PRIOR_LS_GRAM_BF16X3) {
@@ -370,7 +510,6 @@ void launch_gram_reduce(const double* part, int blocks, int entries, double* out
 // Cyclic complex Jacobi in FP64 with round-robin pair ordering (all n/2 disjoint
 // rotations of a round applied at once), warm-started from the previous iteration's
 // eigenvectors: A = V^H G V is then nearly diagonal and one or two sweeps suffice.
-constexpr int kNMax = 32;
 constexpr int kEigThreads = 512;    // one block of eight waves: it shares its CU with the sparse update
 constexpr int kMaxSweeps = 30;
 
@@ -441,25 +580,29 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double cr, do
     }
 }
 
-// One block of NT threads.  The rotated matrix is double-buffered (a round reads one copy
-// and writes the other) and every wave derives the round's rotations for itself, so a
-// round needs a single block barrier.
-template <int NT, class SRC>
+// One block of NT threads, for windows of at most NMAX frames.  With NMAX = 32 the rotated
+// matrix is double-buffered (a round reads one copy and writes the other) and every wave
+// derives the round's rotations for itself, so a round needs a single block barrier.  With
+// NMAX = 64 one copy of A and the eigenvectors fill most of the LDS: a round updates A in
+// place (each item owns one 2x2 block of it) after a second barrier that lets every wave
+// read the round's diagonal blocks first; the set-up products are staged in registers.
+template <int NT, int NMAX, class SRC>
 __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
     if (src.skip()) return;
     const EigArgs a = src.get();
     constexpr int NW = NT / 64;
+    constexpr bool DB = NMAX <= 32;
+    constexpr int NBUF = DB ? 2 : 1;
+    constexpr int NSTG = DB ? 1 : (NMAX * NMAX + NT - 1) / NT;   // staged set-up entries
     // Ab[0] / Ab[1]: the two copies of A (real, imaginary); Ab[1] holds T in the set-up
-    __shared__ double Ab[2][2][kNMax][kNMax + 1];
-    __shared__ double Vr[kNMax][kNMax + 1], Vi[kNMax][kNMax + 1];
-    __shared__ double rc[NW][kNMax / 2], rs[NW][kNMax / 2], rer[NW][kNMax / 2], rei[NW][kNMax / 2];
+    __shared__ double Ab[NBUF][2][NMAX][NMAX + 1];
+    __shared__ double Vr[NMAX][NMAX + 1], Vi[NMAX][NMAX + 1];
+    __shared__ double rc[NW][NMAX / 2], rs[NW][NMAX / 2], rer[NW][NMAX / 2], rei[NW][NMAX / 2];
     __shared__ double red[NW];
-    __shared__ double sig[kNMax], phi[kNMax];
-    __shared__ int rank_of[kNMax], by_rank[kNMax];
-    double (*Ar)[kNMax + 1] = Ab[0][0];
-    double (*Ai)[kNMax + 1] = Ab[0][1];
-    double (*Tr)[kNMax + 1] = Ab[1][0];
-    double (*Ti)[kNMax + 1] = Ab[1][1];
+    __shared__ double sig[NMAX], phi[NMAX];
+    __shared__ int rank_of[NMAX], by_rank[NMAX];
+    double (*Ar)[NMAX + 1] = Ab[0][0];
+    double (*Ai)[NMAX + 1] = Ab[0][1];
     // one block on the critical path while the sparse update fills the other CUs (and
     // possibly this one): its waves issue first
     __builtin_amdgcn_s_setprio(3);
@@ -467,10 +610,12 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
     const int lane = tid & 63, wv = tid >> 6;
     const int n = a.nt;
     const int ne = n + (n & 1);
-    const int NB = n <= 16 ? 1 : 2;
+    const int NB = n <= 16 ? 1 : (n <= 32 ? 2 : 4);
     const int NTP = 16 * NB;
 
-    // G (complex Hermitian, n x n; padded index decoupled)
+    // G (complex Hermitian, n x n; padded index decoupled): into T (NMAX = 32) or A
+    double (*Gr)[NMAX + 1] = DB ? Ab[NBUF - 1][0] : Ab[0][0];
+    double (*Gi)[NMAX + 1] = DB ? Ab[NBUF - 1][1] : Ab[0][1];
     for (int idx = tid; idx < ne * ne; idx += NT) {
         const int i = idx / ne, j = idx % ne;
         double gr = 0.0, gi = 0.0;
@@ -478,8 +623,8 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
             gr = gram_real(a.gram, NB, i, j) + gram_real(a.gram, NB, NTP + i, NTP + j);
             gi = gram_real(a.gram, NB, i, NTP + j) - gram_real(a.gram, NB, j, NTP + i);
         }
-        Tr[i][j] = gr;
-        Ti[i][j] = gi;
+        Gr[i][j] = gr;
+        Gi[i][j] = gi;
         double vr = (i == j) ? 1.0 : 0.0, vi = 0.0;
         if (a.warm && i < n && j < n) {
             vr = a.V[2 * (i * n + j)];
@@ -489,43 +634,116 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
         Vi[i][j] = vi;
     }
     __syncthreads();
-    // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
-    for (int idx = tid; idx < ne * ne; idx += NT) {
-        const int i = idx / ne, j = idx % ne;
-        double sr = 0.0, si = 0.0;
-        for (int k = 0; k < ne; ++k) {
-            sr += Tr[i][k] * Vr[k][j] - Ti[i][k] * Vi[k][j];
-            si += Tr[i][k] * Vi[k][j] + Ti[i][k] * Vr[k][j];
+    if constexpr (DB) {
+        double (*Tr)[NMAX + 1] = Ab[1][0];
+        double (*Ti)[NMAX + 1] = Ab[1][1];
+        // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
+        for (int idx = tid; idx < ne * ne; idx += NT) {
+            const int i = idx / ne, j = idx % ne;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < ne; ++k) {
+                sr += Tr[i][k] * Vr[k][j] - Ti[i][k] * Vi[k][j];
+                si += Tr[i][k] * Vi[k][j] + Ti[i][k] * Vr[k][j];
+            }
+            Ar[i][j] = sr;
+            Ai[i][j] = si;
         }
-        Ar[i][j] = sr;
-        Ai[i][j] = si;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < ne * ne; idx += NT) {
-        const int i = idx / ne, j = idx % ne;
-        double sr = 0.0, si = 0.0;
-        for (int k = 0; k < ne; ++k) {
-            // conj(V[k][i]) * (GV)[k][j]
-            sr += Vr[k][i] * Ar[k][j] + Vi[k][i] * Ai[k][j];
-            si += Vr[k][i] * Ai[k][j] - Vi[k][i] * Ar[k][j];
+        __syncthreads();
+        for (int idx = tid; idx < ne * ne; idx += NT) {
+            const int i = idx / ne, j = idx % ne;
+            double sr = 0.0, si = 0.0;
+            for (int k = 0; k < ne; ++k) {
+                // conj(V[k][i]) * (GV)[k][j]
+                sr += Vr[k][i] * Ar[k][j] + Vi[k][i] * Ai[k][j];
+                si += Vr[k][i] * Ai[k][j] - Vi[k][i] * Ar[k][j];
+            }
+            Tr[i][j] = sr;
+            Ti[i][j] = si;
         }
-        Tr[i][j] = sr;
-        Ti[i][j] = si;
+        __syncthreads();
+        for (int idx = tid; idx < ne * ne; idx += NT) {
+            const int i = idx / ne, j = idx % ne;
+            // symmetrise: A = (T + T^H) / 2
+            Ar[i][j] = 0.5 * (Tr[i][j] + Tr[j][i]);
+            Ai[i][j] = (i == j) ? 0.0 : 0.5 * (Ti[i][j] - Ti[j][i]);
+        }
+        __syncthreads();
+    } else {
+        // the same products with A as the only matrix buffer: each thread forms its entries
+        // in registers, and writes them after a barrier
+        double sr[NSTG], si[NSTG];
+#pragma unroll
+        for (int q = 0; q < NSTG; ++q) {
+            const int idx = tid + q * NT;
+            sr[q] = si[q] = 0.0;
+            if (idx < ne * ne) {
+                const int i = idx / ne, j = idx % ne;
+                for (int k = 0; k < ne; ++k) {   // (G V)[i][j]
+                    sr[q] += Ar[i][k] * Vr[k][j] - Ai[i][k] * Vi[k][j];
+                    si[q] += Ar[i][k] * Vi[k][j] + Ai[i][k] * Vr[k][j];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NSTG; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < ne * ne) {
+                Ar[idx / ne][idx % ne] = sr[q];
+                Ai[idx / ne][idx % ne] = si[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NSTG; ++q) {
+            const int idx = tid + q * NT;
+            sr[q] = si[q] = 0.0;
+            if (idx < ne * ne) {
+                const int i = idx / ne, j = idx % ne;
+                for (int k = 0; k < ne; ++k) {   // conj(V[k][i]) * (GV)[k][j]
+                    sr[q] += Vr[k][i] * Ar[k][j] + Vi[k][i] * Ai[k][j];
+                    si[q] += Vr[k][i] * Ai[k][j] - Vi[k][i] * Ar[k][j];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NSTG; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < ne * ne) {
+                Ar[idx / ne][idx % ne] = sr[q];
+                Ai[idx / ne][idx % ne] = si[q];
+            }
+        }
+        __syncthreads();
+        // symmetrise: A = (A + A^H) / 2, read before written
+#pragma unroll
+        for (int q = 0; q < NSTG; ++q) {
+            const int idx = tid + q * NT;
+            sr[q] = si[q] = 0.0;
+            if (idx < ne * ne) {
+                const int i = idx / ne, j = idx % ne;
+                sr[q] = 0.5 * (Ar[i][j] + Ar[j][i]);
+                si[q] = (i == j) ? 0.0 : 0.5 * (Ai[i][j] - Ai[j][i]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NSTG; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < ne * ne) {
+                Ar[idx / ne][idx % ne] = sr[q];
+                Ai[idx / ne][idx % ne] = si[q];
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int idx = tid; idx < ne * ne; idx += NT) {
-        const int i = idx / ne, j = idx % ne;
-        // symmetrise: A = (T + T^H) / 2
-        Ar[i][j] = 0.5 * (Tr[i][j] + Tr[j][i]);
-        Ai[i][j] = (i == j) ? 0.0 : 0.5 * (Ti[i][j] - Ti[j][i]);
-    }
-    __syncthreads();
 
     const int half = ne / 2;
     int sweeps = 0, cur = 0;
     for (; sweeps < kMaxSweeps && ne > 1; ++sweeps) {
-        double (*Cr)[kNMax + 1] = Ab[cur][0];
-        double (*Ci)[kNMax + 1] = Ab[cur][1];
+        double (*Cr)[NMAX + 1] = Ab[cur][0];
+        double (*Ci)[NMAX + 1] = Ab[cur][1];
         double off = 0.0, dg = 0.0;
         for (int idx = tid; idx < ne * ne; idx += NT) {
             const int i = idx / ne, j = idx % ne;
@@ -538,10 +756,10 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
         // the inverse gap) are far below the FP32 resolution of W
         if (!(off > 1e-16 * dg)) break;   // also stops on NaN
         for (int r = 0; r < ne - 1; ++r) {
-            double (*Sr)[kNMax + 1] = Ab[cur][0];
-            double (*Si)[kNMax + 1] = Ab[cur][1];
-            double (*Dr)[kNMax + 1] = Ab[cur ^ 1][0];
-            double (*Di)[kNMax + 1] = Ab[cur ^ 1][1];
+            double (*Sr)[NMAX + 1] = Ab[cur][0];
+            double (*Si)[NMAX + 1] = Ab[cur][1];
+            double (*Dr)[NMAX + 1] = Ab[DB ? cur ^ 1 : cur][0];
+            double (*Di)[NMAX + 1] = Ab[DB ? cur ^ 1 : cur][1];
             // this wave's copy of the round's rotations (every wave computes the same ones)
             if (lane < half) {
                 int p, q;
@@ -558,6 +776,9 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // one copy of A: every wave has read the diagonal blocks it needs before any
+            // item overwrites them
+            if constexpr (!DB) __syncthreads();
             // D = J^H S J on every 2x2 block; J = [[cs, sn e], [-sn conj(e), cs]].  An A item
             // (al, be) < (half, half) rotates one 2x2 block of S into D; a V item (i, be)
             // rotates two entries of row i of V in place.  Each item's reads come first and
@@ -630,7 +851,7 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
                 Vr[x.i][x.w] = x.s2 * (x.v0r * x.e2r - x.v0i * x.e2i) + x.c2 * x.v1r;
                 Vi[x.i][x.w] = x.s2 * (x.v0r * x.e2i + x.v0i * x.e2r) + x.c2 * x.v1i;
             };
-            if constexpr (NT >= kNMax * kNMax / 2) {
+            if constexpr (NT >= NMAX * NMAX / 2) {
                 // every thread takes at most one A item (half^2 <= 256) and one V item
                 // (ne half <= 512), both loaded before either is written (absent items load
                 // item 0 and write nothing), so their LDS reads overlap
@@ -648,10 +869,10 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
             // every entry of D was written (the pairs partition the indices); the next round
             // reads D and overwrites S, whose last readers are behind this barrier
             __syncthreads();
-            cur ^= 1;
+            if constexpr (DB) cur ^= 1;
         }
     }
-    double (*Acur)[kNMax + 1] = Ab[cur][0];
+    double (*Acur)[NMAX + 1] = Ab[cur][0];
 
     // spectrum, descending ranks (ties broken by index), thresholds
     if (tid < n) sig[tid] = sqrt(fmax(Acur[tid][tid], 0.0));
@@ -724,7 +945,8 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
 }
 
 void launch_eig_batched(const EigArgs& a, const Batched<EigArgs>* bt, hipStream_t s) {
-    PLS_LAUNCH(dim3(1), dim3(kEigThreads), s, a, bt, pls_eig_kernel, kEigThreads);
+    if (a.nt <= 32) PLS_LAUNCH(dim3(1), dim3(kEigThreads), s, a, bt, pls_eig_kernel, kEigThreads, 32);
+    else PLS_LAUNCH(dim3(1), dim3(kEigThreads), s, a, bt, pls_eig_kernel, kEigThreads, 64);
 }
 
 void launch_eig(const EigArgs& a, hipStream_t s) {

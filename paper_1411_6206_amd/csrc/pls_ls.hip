@@ -125,8 +125,10 @@ void launch_bp_batched(const BpArgs& a, const Batched<BpArgs>* bt, hipStream_t s
     const int grid = (bt && bt->grid > 0) ? bt->grid : bp_blocks(a.N, a.max_grid);
     if (a.nt <= 16)
         PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_bp_kernel, 1);
-    else
+    else if (a.nt <= 32)
         PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_bp_kernel, 2);
+    else
+        PLS_LAUNCH(dim3(grid), dim3(256), s, a, bt, pls_bp_kernel, 4);
 }
 
 void launch_bp(const BpArgs& a, hipStream_t s) { launch_bp_batched(a, nullptr, s); }
@@ -548,7 +550,7 @@ int launch_sparse_tfft(const SparseArgs& a, hipStream_t s) {
 
 // ---------------------------------------------------------------- statistics
 // stat record (doubles): [0] ||r||^2, [1] ||Y - Yold||^2, [2] ||Yold||^2, [3] weighted l1,
-// [4] nuclear norm, [5] tau_L, [6] Jacobi sweeps, [7] non-finite flag, [16..48) sigma
+// [4] nuclear norm, [5] tau_L, [6] Jacobi sweeps, [7] non-finite flag, [16, 16 + nt) sigma
 template <int NTH, class SRC>
 __global__ void __launch_bounds__(NTH) pls_stats_kernel(SRC src) {
     static_assert(NTH == 256, "one block of 256 threads");

@@ -31,7 +31,9 @@ void set_thread_error(const std::string& m) { g_create_error = m; }
 
 namespace {
 
-constexpr int kStatRec = 64;          // doubles per iteration record
+constexpr int kStatRec = 128;         // doubles per iteration record ([16, 16 + nt): sigma)
+constexpr int kMatDoubles = 64 * 64;   // an nt x nt matrix (V, W) at the largest nt
+constexpr int kOpFloats = 128 * 128;   // the real-expanded back-projection operand
 constexpr int kMaxChunk = 1024;
 constexpr int kMaxGramBlocks = 2048;  // largest Gram split the tuner tries
 
@@ -71,7 +73,7 @@ int check_dims(const prior_ls_dims* d, std::string& msg) {
         return PRIOR_LS_ESHAPE;
     }
     if (d->nt > PRIOR_LS_MAX_NT) {
-        msg = "nt > 32 is not supported";
+        msg = "nt > 64 is not supported";
         return PRIOR_LS_ESHAPE;
     }
     if (d->nc > 64) {
@@ -91,7 +93,13 @@ int check_dims(const prior_ls_dims* d, std::string& msg) {
         msg = "wavelet_levels must be in [0, 3]";
         return PRIOR_LS_ESHAPE;
     }
-    if (d->transform == PRIOR_LS_T_TFFT) return PRIOR_LS_OK;   // J is not used
+    if (d->transform == PRIOR_LS_T_TFFT) {                     // J is not used
+        if (d->nt > 32) {
+            msg = "the temporal transform takes at most 32 frames";
+            return PRIOR_LS_ESHAPE;
+        }
+        return PRIOR_LS_OK;
+    }
     if (d->transform == PRIOR_LS_T_DB4 && !pls::db4_supported(d->nx, d->ny, d->nz)) {
         msg = "unsupported shape for the Daubechies transform";
         return PRIOR_LS_ESHAPE;
@@ -150,7 +158,7 @@ Sizes sizes_of(const prior_ls_dims& d) {
     b += (uint64_t)d.nt * s.P * (2 + 4) + 3 * (d.nt + 1) * 4;  // sidx, plist, ns, offsets
     b += (uint64_t)(d.nx + d.ny + d.nz) * 8;            // twiddles
     b += (uint64_t)s.gblocks * s.gentries * 8 + s.gentries * 8;
-    b += 64 * 64 * 4 + 2 * 32 * 32 * 16 + 64 * 8;
+    b += kOpFloats * 4 + 2 * kMatDoubles * 16 + 64 * 8;   // W operand, V and W, sigma
     if (d.transform == PRIOR_LS_T_TFFT) b += 2 * 64 * 64 * 4;
     if (d.transform == PRIOR_LS_T_DB4) b += s.I * 8;      // coefficient scratch
     b += (uint64_t)s.dcb * 32 + (uint64_t)s.spb * 8 + (uint64_t)kMaxChunk * kStatRec * 8;
@@ -691,9 +699,9 @@ void ensure_op_scratch(prior_ls_handle* h) {
     const Sizes& sz = h->sz;
     if (!h->T1) h->T1 = h->alloc<float2>(sz.I * sizeof(float2));
     if (!h->T2) h->T2 = h->alloc<float2>(sz.I * sizeof(float2));
-    if (!h->Vop) h->Vop = h->alloc<double>(2 * 32 * 32 * sizeof(double));
-    if (!h->Wdop) h->Wdop = h->alloc<double>(2 * 32 * 32 * sizeof(double));
-    if (!h->Wopop) h->Wopop = h->alloc<float>(64 * 64 * sizeof(float));
+    if (!h->Vop) h->Vop = h->alloc<double>(2 * kMatDoubles * sizeof(double));
+    if (!h->Wdop) h->Wdop = h->alloc<double>(2 * kMatDoubles * sizeof(double));
+    if (!h->Wopop) h->Wopop = h->alloc<float>(kOpFloats * sizeof(float));
 }
 
 // Work of a call runs on the handle's stream, after everything already queued on the
@@ -1015,9 +1023,9 @@ int prior_ls_create(const prior_ls_dims* dims, void* stream, prior_ls_handle** o
         h->twz = h->alloc<float2>(d.nz * sizeof(float2));
         h->gpart = h->alloc<double>((size_t)sz.gblocks * sz.gentries * sizeof(double));
         h->gred = h->alloc<double>(sz.gentries * sizeof(double));
-        h->V = h->alloc<double>(2 * 32 * 32 * sizeof(double));
-        h->Wd = h->alloc<double>(2 * 32 * 32 * sizeof(double));
-        h->Wop = h->alloc<float>(64 * 64 * sizeof(float));
+        h->V = h->alloc<double>(2 * kMatDoubles * sizeof(double));
+        h->Wd = h->alloc<double>(2 * kMatDoubles * sizeof(double));
+        h->Wop = h->alloc<float>(kOpFloats * sizeof(float));
         h->sigma_prev = h->alloc<double>(64 * sizeof(double));
         h->dc_part = h->alloc<double>((size_t)sz.dcb * sizeof(double));
         h->ch_part = h->alloc<double>((size_t)pls::change_blocks((long)sz.I) * 2 * sizeof(double));
@@ -1400,7 +1408,7 @@ int prior_ls_op_sparse(prior_ls_handle* h, const void* Xm, const void* Lp, void*
 // A batch advances several loaded handles together: every kernel of an iteration is launched
 // once for all of them (grid z = problem), each problem's blocks reading its argument block
 // from device memory.  The problems share the phase-encode plane (ny, nz), the sparsifying
-// transform and its depth, the Gram mode and the Gram tile class (nt <= 16 or 17..32), which
+// transform and its depth, the Gram mode and the Gram tile class (nt <= 16, 17..32 or 33..64), which
 // fix the kernel instances; nx, nt and nc may differ.  Each launch takes the largest of the
 // problems' grids; a problem's blocks beyond its own grid return at once and its blocks
 // stride over its work by its own grid, so it computes exactly what it computes alone.
@@ -1737,7 +1745,8 @@ namespace pls {
 bool batch_compatible(const prior_ls_dims& a, const prior_ls_dims& b) {
     if (a.ny != b.ny || a.nz != b.nz || a.gram_mode != b.gram_mode || a.transform != b.transform)
         return false;
-    if ((a.nt <= 16) != (b.nt <= 16)) return false;
+    auto tile_class = [](int nt) { return nt <= 16 ? 0 : (nt <= 32 ? 1 : 2); };
+    if (tile_class(a.nt) != tile_class(b.nt)) return false;
     if (a.transform == PRIOR_LS_T_TFFT) return a.nt == b.nt;
     return a.wavelet_levels == b.wavelet_levels;
 }
@@ -1778,8 +1787,8 @@ int prior_ls_batch_create(prior_ls_handle* const* handles, int32_t count, prior_
             }
         if (!pls::batch_compatible(handles[i]->d, handles[0]->d) || handles[i]->device != handles[0]->device) {
             pls::set_thread_error("the handles of a batch need one phase-encode plane (ny, nz), "
-                                  "transform and depth, Gram mode, Gram tile class (nt <= 16 or "
-                                  "17..32; the temporal transform: one nt) and device");
+                                  "transform and depth, Gram mode, Gram tile class (nt <= 16, "
+                                  "17..32 or 33..64; the temporal transform: one nt) and device");
             return PRIOR_LS_EINVAL;
         }
     }

@@ -33,8 +33,8 @@ void phase_stats(prior_ls_handle* h, prior_ls_stats* st, int converged, double m
 int phase_max_iter(const prior_ls_handle* h);
 
 // Problems that can share one batch (prior_ls_batch_create accepts them together): the same
-// phase-encode plane, transform and depth, Gram mode and Gram tile class (nt <= 16 or 17..32;
-// the temporal transform: one nt).  nx, nt and nc may differ.
+// phase-encode plane, transform and depth, Gram mode and Gram tile class (nt <= 16, 17..32 or
+// 33..64; the temporal transform: one nt).  nx, nt and nc may differ.
 bool batch_compatible(const prior_ls_dims& a, const prior_ls_dims& b);
 
 // Runs the loaded windows of a batch's handles together: handle i does up to target[i]

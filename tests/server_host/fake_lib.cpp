@@ -57,7 +57,8 @@ void phase_stats(prior_ls_handle* h, prior_ls_stats* st, int conv, double ms) { 
 int phase_max_iter(const prior_ls_handle* h) { return h->p.max_iter; }
 bool batch_compatible(const prior_ls_dims& a, const prior_ls_dims& b) {
   return a.ny == b.ny && a.nz == b.nz && a.gram_mode == b.gram_mode && a.transform == b.transform &&
-         (a.nt <= 16) == (b.nt <= 16) && a.wavelet_levels == b.wavelet_levels; }
+         (a.nt <= 16 ? 0 : a.nt <= 32 ? 1 : 2) == (b.nt <= 16 ? 0 : b.nt <= 32 ? 1 : 2) &&
+         a.wavelet_levels == b.wavelet_levels; }
 int batch_run(prior_ls_batch* b, const std::vector<int>& target, std::vector<char>& conv,
               std::vector<int>& status, std::vector<Clk::time_point>& done_at) {
   const size_t n = b->hs.size();

@@ -37,7 +37,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(pls.Params) == 56
     assert C.sizeof(pls.Inputs) == 56
     assert C.sizeof(pls.Outputs) == 32
-    assert C.sizeof(pls.Stats) == 8 + 24 + 6 * 8 + 32 * 8 + 8
+    assert C.sizeof(pls.Stats) == 8 + 24 + 6 * 8 + 64 * 8 + 8
 
 
 def test_struct_layouts_match_a_c_compiler(tmp_path):
@@ -123,7 +123,8 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(nt=33), pls.ESHAPE),
+    (dict(nt=65), pls.ESHAPE),
+    (dict(nt=33, transform="tfft"), pls.ESHAPE),   # the temporal transform takes <= 32 frames
     (dict(nt=0), pls.ESHAPE),
     (dict(ny=20), pls.ESHAPE),            # not in the FFT length set
     (dict(ny=512), pls.ESHAPE),
@@ -169,7 +170,16 @@ def test_temporal_transform_ignores_the_haar_divisibility():
 
 
 def test_plan_bytes_zero_for_invalid():
-    assert pls.plan_bytes(64, 64, 1, 40, 1) == 0
+    assert pls.plan_bytes(64, 64, 1, 65, 1) == 0
+    assert pls.plan_bytes(64, 64, 1, 40, 1, transform="tfft") == 0
+
+
+def test_windows_of_up_to_64_frames_are_accepted():
+    # the wide Gram, the 64-frame eigensolver and back-projection operand: every transform
+    # but the temporal one
+    for nt in (33, 48, 64):
+        assert pls.plan_bytes(64, 64, 1, nt, 1) > pls.plan_bytes(64, 64, 1, 32, 1)
+        assert pls.plan_bytes(32, 32, 8, nt, 2, transform="db4") > 0
 
 
 def test_null_handle_calls():
