@@ -21,7 +21,7 @@
  * plain L+S threshold).
  *
  * Memory.  Every array argument is DEVICE memory owned by the caller, except
- * `sigma_prev` (host memory, nt doubles, copied during the call).  Complex
+ * `sigma_prev` (host or device memory, nt doubles, read during the call).  Complex
  * arrays are interleaved complex64 (float re, float im), C order, x fastest:
  *     images (L0, S0, L, S, X, M)   [nt][nz][ny][nx]
  *     k-space                       [nc][nt][nz][ny][nx]  (kz, ky, kx; unshifted, DC at 0)
@@ -123,9 +123,10 @@ typedef struct {
     const uint8_t *mask;        /* uint8 [nt][nz][ny], required */
     const void    *sens;        /* complex64 [nc][nz][ny][nx]; NULL only when nc == 1 */
     const uint8_t *prior_w;     /* uint8 [nt][nz][ny][nx] canonical Haar layout, or NULL */
-    const double  *sigma_prev;  /* HOST, nt doubles (singular values of L^(t-1), any order),
-                                   copied during the call (it is sorted and padded on the
-                                   host); required when lambda_p > 0, else ignored */
+    const double  *sigma_prev;  /* host or device memory, nt doubles (singular values of
+                                   L^(t-1), any order), read during the call (it is sorted
+                                   and padded on the host); required when lambda_p > 0, else
+                                   ignored */
     const void    *L0, *S0;     /* complex64 [nt][nz][ny][nx] warm start: both or neither.
                                    Cold: L = X_0 = A^H d, S = 0.  Warm: L = L0, S = S0 and
                                    X_0 = Y - A^H(A Y - d) with Y = L0 + S0 */

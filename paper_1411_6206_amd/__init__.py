@@ -203,6 +203,21 @@ def lib():
     return L
 
 
+def _sigma_prev_ptr(sigma_prev):
+    """(pointer, keep-alive) for sigma_prev: a float64 CUDA tensor is passed as device memory,
+    anything else is copied into a host array."""
+    if sigma_prev is None:
+        return None, None
+    if hasattr(sigma_prev, "is_cuda") and sigma_prev.is_cuda:
+        import torch
+        if sigma_prev.dtype != torch.float64 or not sigma_prev.is_contiguous():
+            raise ValueError("a device sigma_prev must be a contiguous float64 tensor")
+        return C.cast(C.c_void_p(sigma_prev.data_ptr()), C.POINTER(C.c_double)), sigma_prev
+    vals = [float(v) for v in sigma_prev]
+    arr = (C.c_double * len(vals))(*vals)
+    return C.cast(arr, C.POINTER(C.c_double)), arr
+
+
 def make_dims(nx, ny, nz, nt, nc, wavelet_levels=2, gram_mode="fp64", hbm_budget=0,
               transform="haar"):
     gm = GRAM_MODES[gram_mode] if isinstance(gram_mode, str) else int(gram_mode)
@@ -262,12 +277,8 @@ class PriorLS:
               tol=0.0, check_every=10, use_graph=True, outputs=("L", "S", "X", "M")):
         """prior_ls_solve.  Tensors: complex64 / uint8 CUDA tensors in the ABI layouts."""
         import torch
-        sp = None
-        if sigma_prev is not None:
-            vals = [float(v) for v in sigma_prev]
-            sp = (C.c_double * len(vals))(*vals)
-        ins = Inputs(_ptr(kspace), _ptr(mask), _ptr(sens), _ptr(prior_w),
-                     C.cast(sp, C.POINTER(C.c_double)) if sp is not None else None,
+        sp = _sigma_prev_ptr(sigma_prev)
+        ins = Inputs(_ptr(kspace), _ptr(mask), _ptr(sens), _ptr(prior_w), sp[0],
                      _ptr(L0), _ptr(S0))
         prm = Params(C.sizeof(Params), float(lambda_L), float(lambda_S), float(lambda_p),
                      float(tol), 1 if lambda_L_relative else 0, int(max_iter), int(check_every),
@@ -325,12 +336,8 @@ class PriorLS:
                        lambda_S=lambda_S, lambda_p=lambda_p, lambda_L_relative=lambda_L_relative,
                        max_iter=0, check_every=check_every, outputs=())
             return dict(t.as_dict(), cached=True)
-        sp = None
-        if sigma_prev is not None:
-            vals = [float(v) for v in sigma_prev]
-            sp = (C.c_double * len(vals))(*vals)
-        ins = Inputs(_ptr(kspace), _ptr(mask), _ptr(sens), _ptr(prior_w),
-                     C.cast(sp, C.POINTER(C.c_double)) if sp is not None else None, None, None)
+        sp = _sigma_prev_ptr(sigma_prev)
+        ins = Inputs(_ptr(kspace), _ptr(mask), _ptr(sens), _ptr(prior_w), sp[0], None, None)
         prm = Params(C.sizeof(Params), float(lambda_L), float(lambda_S), float(lambda_p), 0.0,
                      1 if lambda_L_relative else 0, 0, int(check_every), 1)
         t = Tuning()
@@ -456,14 +463,10 @@ class Batch:
         prms = list(params) if isinstance(params, (list, tuple)) else [params] * n
         keep, ins = [], []
         for p in problems:
-            sp = None
-            if p.get("sigma_prev") is not None:
-                vals = [float(v) for v in p["sigma_prev"]]
-                sp = (C.c_double * len(vals))(*vals)
-                keep.append(sp)
+            sp = _sigma_prev_ptr(p.get("sigma_prev"))
+            keep.append(sp)
             ins.append(Inputs(_ptr(p["kspace"]), _ptr(p["mask"]), _ptr(p.get("sens")),
-                              _ptr(p.get("prior_w")),
-                              C.cast(sp, C.POINTER(C.c_double)) if sp is not None else None,
+                              _ptr(p.get("prior_w")), sp[0],
                               _ptr(p.get("L0")), _ptr(p.get("S0"))))
         in_arr = (Inputs * n)(*ins)
         prm_arr = (Params * n)(*prms)

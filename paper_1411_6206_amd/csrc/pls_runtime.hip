@@ -667,7 +667,14 @@ int load_problem(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_p
                                  d.transform == PRIOR_LS_T_HAAR ? d.wavelet_levels : 0, s);
     std::vector<double> sp(d.nt, 0.0);
     if (p->lambda_p > 0 && in->sigma_prev) {
-        for (int i = 0; i < d.nt; ++i) sp[i] = in->sigma_prev[i];
+        // host or device memory: read once per solve, sorted on the host
+        if (is_device_ptr(in->sigma_prev)) {
+            PLS_HIP(hipMemcpyAsync(sp.data(), in->sigma_prev, d.nt * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+            PLS_HIP(hipStreamSynchronize(s));
+        } else {
+            for (int i = 0; i < d.nt; ++i) sp[i] = in->sigma_prev[i];
+        }
         std::sort(sp.begin(), sp.end(), [](double a, double b) { return a > b; });
     }
     PLS_HIP(hipMemcpyAsync(h->sigma_prev, sp.data(), d.nt * sizeof(double), hipMemcpyHostToDevice, s));

@@ -188,6 +188,19 @@ def test_solve_with_sigma_prior_and_warm_start(case):
         assert e < TOL, (k, e)
 
 
+def test_sigma_prev_in_device_memory(case):
+    # sigma_prev may be host or device memory: the same bits either way (in any order)
+    p, J = case
+    rng = np.random.default_rng(10)
+    prev = rng.uniform(0, 3, p.nt)
+    with handle(p, J) as h:
+        a, _ = load(h, p, max_iter=4, lambda_p=0.5, sigma_prev=list(prev))
+        b, _ = load(h, p, max_iter=4, lambda_p=0.5,
+                    sigma_prev=torch.from_numpy(prev[::-1].copy()).cuda())
+    for k in ("L", "S", "X", "M"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_determinism_resume_and_graphs(case):
     p, J = case
     with handle(p, J) as h:
