@@ -580,6 +580,29 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double cr, do
     }
 }
 
+// The sums of a and b over the block, each in the fixed order of block_sum, with one pair
+// of barriers for both.  red holds 2 (NT / 64) doubles.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[w] = a;
+        red[NT / kWave + w] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / kWave; ++i) {
+        sa += red[i];
+        sb += red[NT / kWave + i];
+    }
+    a = sa;
+    b = sb;
+}
+
 // One block of NT threads, for windows of at most NMAX frames.  With NMAX = 32 the rotated
 // matrix is double-buffered (a round reads one copy and writes the other) and every wave
 // derives the round's rotations for itself, so a round needs a single block barrier.  With
@@ -598,9 +621,9 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
     __shared__ double Ab[NBUF][2][NMAX][NMAX + 1];
     __shared__ double Vr[NMAX][NMAX + 1], Vi[NMAX][NMAX + 1];
     __shared__ double rc[NW][NMAX / 2], rs[NW][NMAX / 2], rer[NW][NMAX / 2], rei[NW][NMAX / 2];
-    __shared__ double red[NW];
-    __shared__ double sig[NMAX], phi[NMAX];
-    __shared__ int rank_of[NMAX], by_rank[NMAX];
+    __shared__ double red[2 * NW];
+    __shared__ double sig[NMAX], phi[NMAX], phi_r[NMAX], sig_r[NMAX];
+    __shared__ int rank_of[NMAX];
     double (*Ar)[NMAX + 1] = Ab[0][0];
     double (*Ai)[NMAX + 1] = Ab[0][1];
     // one block on the critical path while the sparse update fills the other CUs (and
@@ -637,28 +660,55 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
     if constexpr (DB) {
         double (*Tr)[NMAX + 1] = Ab[1][0];
         double (*Ti)[NMAX + 1] = Ab[1][1];
-        // A = V^H (G V): first G V into Ar, then V^H (.) into Tr
-        for (int idx = tid; idx < ne * ne; idx += NT) {
-            const int i = idx / ne, j = idx % ne;
-            double sr = 0.0, si = 0.0;
+        // A = V^H (G V): first G V into Ar, then V^H (.) into Tr.  A thread forms a 2 x 2
+        // block of entries (ne is even), so that each operand it reads from LDS serves two
+        // entries; every entry is summed over k in order, as one entry per thread would.
+        const int hb = ne / 2;
+        for (int b = tid; b < hb * hb; b += NT) {
+            const int i0 = 2 * (b / hb), j0 = 2 * (b % hb);
+            double sr[2][2] = {}, si[2][2] = {};
             for (int k = 0; k < ne; ++k) {
-                sr += Tr[i][k] * Vr[k][j] - Ti[i][k] * Vi[k][j];
-                si += Tr[i][k] * Vi[k][j] + Ti[i][k] * Vr[k][j];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const double tr = Tr[i0 + a][k], ti = Ti[i0 + a][k];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        sr[a][c] += tr * Vr[k][j0 + c] - ti * Vi[k][j0 + c];
+                        si[a][c] += tr * Vi[k][j0 + c] + ti * Vr[k][j0 + c];
+                    }
+                }
             }
-            Ar[i][j] = sr;
-            Ai[i][j] = si;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    Ar[i0 + a][j0 + c] = sr[a][c];
+                    Ai[i0 + a][j0 + c] = si[a][c];
+                }
         }
         __syncthreads();
-        for (int idx = tid; idx < ne * ne; idx += NT) {
-            const int i = idx / ne, j = idx % ne;
-            double sr = 0.0, si = 0.0;
+        for (int b = tid; b < hb * hb; b += NT) {
+            const int i0 = 2 * (b / hb), j0 = 2 * (b % hb);
+            double sr[2][2] = {}, si[2][2] = {};
             for (int k = 0; k < ne; ++k) {
-                // conj(V[k][i]) * (GV)[k][j]
-                sr += Vr[k][i] * Ar[k][j] + Vi[k][i] * Ai[k][j];
-                si += Vr[k][i] * Ai[k][j] - Vi[k][i] * Ar[k][j];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const double vr = Vr[k][i0 + a], vi = Vi[k][i0 + a];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        // conj(V[k][i]) * (GV)[k][j]
+                        sr[a][c] += vr * Ar[k][j0 + c] + vi * Ai[k][j0 + c];
+                        si[a][c] += vr * Ai[k][j0 + c] - vi * Ar[k][j0 + c];
+                    }
+                }
             }
-            Tr[i][j] = sr;
-            Ti[i][j] = si;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    Tr[i0 + a][j0 + c] = sr[a][c];
+                    Ti[i0 + a][j0 + c] = si[a][c];
+                }
         }
         __syncthreads();
         for (int idx = tid; idx < ne * ne; idx += NT) {
@@ -750,8 +800,7 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
             if (i == j) dg += Cr[i][i] * Cr[i][i];
             else off += Cr[i][j] * Cr[i][j] + Ci[i][j] * Ci[i][j];
         }
-        off = block_sum<NT>(off, red);
-        dg = block_sum<NT>(dg, red);
+        block_sum2<NT>(off, dg, red);
         // relative off-diagonal norm below 1e-8: eigenvector errors of that order (times
         // the inverse gap) are far below the FP32 resolution of W
         if (!(off > 1e-16 * dg)) break;   // also stops on NaN
@@ -760,12 +809,36 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
             double (*Si)[NMAX + 1] = Ab[cur][1];
             double (*Dr)[NMAX + 1] = Ab[DB ? cur ^ 1 : cur][0];
             double (*Di)[NMAX + 1] = Ab[DB ? cur ^ 1 : cur][1];
-            // this wave's copy of the round's rotations (every wave computes the same ones)
+            // this wave's copy of the round's rotations (every wave computes the same ones).
+            // Their inputs are read first (every lane reads a valid pair), then, with
+            // NMAX = 32, this thread's item entries, which arrive while the rotations'
+            // dependent arithmetic runs (the LDS returns a wave's reads in issue order)
+            int rp, rq;
+            rr_pair(ne, r, lane < half ? lane : 0, rp, rq);
+            const double rapp = Sr[rp][rp], raqq = Sr[rq][rq], rcr = Sr[rp][rq], rci = Si[rp][rq];
+            const bool has_a = DB && tid < half * half, has_v = DB && tid < ne * half;
+            int ip = 0, iq = 0, iu = 0, iw = 0, ial = 0, ibe = 0, vi = 0, vu = 0, vw = 0, vbe = 0;
+            double e00r = 0, e00i = 0, e01r = 0, e01i = 0, e10r = 0, e10i = 0, e11r = 0, e11i = 0;
+            double w0r = 0, w0i = 0, w1r = 0, w1i = 0;
+            if constexpr (DB) {
+                // S is read-only this round and a V entry belongs to one item: the entries
+                // do not depend on the rotations.  Absent items read item 0.
+                const int ia = has_a ? tid : 0;
+                ial = ia / half;
+                ibe = ia % half;
+                rr_pair(ne, r, ial, ip, iq);
+                rr_pair(ne, r, ibe, iu, iw);
+                e00r = Sr[ip][iu]; e00i = Si[ip][iu]; e01r = Sr[ip][iw]; e01i = Si[ip][iw];
+                e10r = Sr[iq][iu]; e10i = Si[iq][iu]; e11r = Sr[iq][iw]; e11i = Si[iq][iw];
+                const int iv = has_v ? tid : 0;
+                vi = iv / half;
+                vbe = iv % half;
+                rr_pair(ne, r, vbe, vu, vw);
+                w0r = Vr[vi][vu]; w0i = Vi[vi][vu]; w1r = Vr[vi][vw]; w1i = Vi[vi][vw];
+            }
             if (lane < half) {
-                int p, q;
-                rr_pair(ne, r, lane, p, q);
                 double cs, sn, er, ei;
-                jacobi_rot(Sr[p][p], Sr[q][q], Sr[p][q], Si[p][q], cs, sn, er, ei);
+                jacobi_rot(rapp, raqq, rcr, rci, cs, sn, er, ei);
                 rc[wv][lane] = cs;
                 rs[wv][lane] = sn;
                 rer[wv][lane] = er;
@@ -851,13 +924,22 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
                 Vr[x.i][x.w] = x.s2 * (x.v0r * x.e2r - x.v0i * x.e2i) + x.c2 * x.v1r;
                 Vi[x.i][x.w] = x.s2 * (x.v0r * x.e2i + x.v0i * x.e2r) + x.c2 * x.v1i;
             };
-            if constexpr (NT >= NMAX * NMAX / 2) {
+            if constexpr (DB) {
                 // every thread takes at most one A item (half^2 <= 256) and one V item
-                // (ne half <= 512), both loaded before either is written (absent items load
-                // item 0 and write nothing), so their LDS reads overlap
-                const bool has_a = tid < half * half, has_v = tid < ne * half;
-                const AItem xa = a_load(has_a ? tid : 0);
-                const VItem xv = v_load(has_v ? tid : 0);
+                // (ne half <= 512), their entries loaded above; only the rotations are read
+                // here
+                static_assert(NT >= NMAX * NMAX / 2, "one A and one V item per thread");
+                AItem xa;
+                xa.p = ip; xa.q = iq; xa.u = iu; xa.w = iw;
+                xa.diag = ial == ibe;
+                xa.c1 = rc[wv][ial]; xa.s1 = rs[wv][ial]; xa.e1r = rer[wv][ial]; xa.e1i = rei[wv][ial];
+                xa.c2 = rc[wv][ibe]; xa.s2 = rs[wv][ibe]; xa.e2r = rer[wv][ibe]; xa.e2i = rei[wv][ibe];
+                xa.b00r = e00r; xa.b00i = e00i; xa.b01r = e01r; xa.b01i = e01i;
+                xa.b10r = e10r; xa.b10i = e10i; xa.b11r = e11r; xa.b11i = e11i;
+                VItem xv;
+                xv.i = vi; xv.u = vu; xv.w = vw;
+                xv.c2 = rc[wv][vbe]; xv.s2 = rs[wv][vbe]; xv.e2r = rer[wv][vbe]; xv.e2i = rei[wv][vbe];
+                xv.v0r = w0r; xv.v0i = w0i; xv.v1r = w1r; xv.v1i = w1i;
                 if (has_a) a_finish(xa);
                 if (has_v) v_finish(xv);
             } else {
@@ -894,48 +976,64 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
         const double prev = a.sigma_prev ? a.sigma_prev[rank_of[tid]] : 0.0;
         double tgt = hat - a.lambda_p * (hat - prev);
         if (sg <= 1e-3 * s1) tgt = 0.0;
-        phi[tid] = sg > 0.0 ? tgt / sg : 0.0;
+        const double ph = sg > 0.0 ? tgt / sg : 0.0;
+        phi[tid] = ph;
         nuc_part = tgt;
+        // this frame's factors of the nuclear norm, at its rank
+        phi_r[rank_of[tid]] = ph;
+        sig_r[rank_of[tid]] = sg;
         a.stat[16 + rank_of[tid]] = sg;
         if (a.sigL) a.sigL[rank_of[tid]] = tgt;
     }
     __syncthreads();
-    // nuclear norm summed in rank order for determinism
-    if (tid < n) by_rank[rank_of[tid]] = tid;
-    __syncthreads();
+    // nuclear norm summed in rank order for determinism (the terms are independent loads)
     if (tid == 0) {
         double nuc = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const int j = by_rank[k];
-            nuc += phi[j] * sig[j];
-        }
+        for (int k = 0; k < n; ++k) nuc += phi_r[k] * sig_r[k];
         a.stat[4] = nuc;
         a.stat[5] = tau;
         a.stat[6] = (double)sweeps;
     }
     (void)nuc_part;
-    // W = V diag(phi) V^H and its real-expanded MFMA operand
+    // W = V diag(phi) V^H and its real-expanded MFMA operand.  A thread forms a 2 x 2 block
+    // of entries (NTP is even), each summed over k in order.
     const int K2 = 2 * NTP;
-    for (int idx = tid; idx < NTP * NTP; idx += NT) {
-        const int t = idx / NTP, j = idx % NTP;
-        double wr = 0.0, wi = 0.0;
-        if (t < n && j < n) {
-            for (int k = 0; k < n; ++k) {
-                // V[t][k] phi_k conj(V[j][k])
-                const double pr = Vr[t][k] * phi[k], pi = Vi[t][k] * phi[k];
-                wr += pr * Vr[j][k] + pi * Vi[j][k];
-                wi += pi * Vr[j][k] - pr * Vi[j][k];
+    const int hw = NTP / 2;
+    for (int b = tid; b < hw * hw; b += NT) {
+        const int t0 = 2 * (b / hw), j0 = 2 * (b % hw);
+        double wr[2][2] = {}, wi[2][2] = {};
+        for (int k = 0; k < n; ++k) {
+            const double pk = phi[k];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                // V[t][k] phi_k conj(V[j][k]); rows at or beyond n hold zeros of W
+                const double pr = Vr[t0 + e][k] * pk, pi = Vi[t0 + e][k] * pk;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    wr[e][c] += pr * Vr[j0 + c][k] + pi * Vi[j0 + c][k];
+                    wi[e][c] += pi * Vr[j0 + c][k] - pr * Vi[j0 + c][k];
+                }
             }
-            a.Wd[2 * (t * n + j)] = wr;
-            a.Wd[2 * (t * n + j) + 1] = wi;
         }
-        // Wr[k][o]: k = input (Re frames 0..NTP-1, Im frames NTP..), o = output likewise.
-        // A operand = Wr^T: Aop[o][k]
-        const float fr = (float)wr, fi = (float)wi;
-        a.Wop[(j)*K2 + t] = fr;               // Wr[t][j]         =  Re W
-        a.Wop[(j)*K2 + NTP + t] = -fi;        // Wr[NTP+t][j]     = -Im W
-        a.Wop[(NTP + j) * K2 + t] = fi;       // Wr[t][NTP+j]     =  Im W
-        a.Wop[(NTP + j) * K2 + NTP + t] = fr; // Wr[NTP+t][NTP+j] =  Re W
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int t = t0 + e, j = j0 + c;
+                const bool in = t < n && j < n;
+                const double vr = in ? wr[e][c] : 0.0, vi = in ? wi[e][c] : 0.0;
+                if (in) {
+                    a.Wd[2 * (t * n + j)] = vr;
+                    a.Wd[2 * (t * n + j) + 1] = vi;
+                }
+                // Wr[k][o]: k = input (Re frames 0..NTP-1, Im frames NTP..), o = output
+                // likewise.  A operand = Wr^T: Aop[o][k]
+                const float fr = (float)vr, fi = (float)vi;
+                a.Wop[(j)*K2 + t] = fr;               // Wr[t][j]         =  Re W
+                a.Wop[(j)*K2 + NTP + t] = -fi;        // Wr[NTP+t][j]     = -Im W
+                a.Wop[(NTP + j) * K2 + t] = fi;       // Wr[t][NTP+j]     =  Im W
+                a.Wop[(NTP + j) * K2 + NTP + t] = fr; // Wr[NTP+t][NTP+j] =  Re W
+            }
     }
     for (int idx = tid; idx < n * n; idx += NT) {
         const int i = idx / n, j = idx % n;
