@@ -41,7 +41,12 @@ struct DcCfg {
     // PADY points longer still where that spreads the row-to-row lanes of a pass further.
     static constexpr int YSW = (kHas7 || (NY == 192 && Q == 12)) ? 0 : 16;
     static constexpr int PADY = YSW == 0 ? 0 : (Q == 24 ? 12 : (NY == 48 ? 4 : (NY == 96 ? 2 : 0)));
-    using G = Geom<NY, NZ, PB, Q, PADY, 32, 2, YSW>;
+    // waves per SIMD the register allocation must allow: 2, except the 28-point tiles of
+    // nz = 14 with rows of 16 or 32 (8 and 16 planes per block), which spill to scratch at
+    // 2 and measured faster at 1 with the overflow in AGPRs (same outputs bit for bit): 16x14
+    // -4%, 32x14 -24%; 64x14 and 128x14 measured 18-40% slower that way and keep 2
+    static constexpr int MINW = (kHas7 && NY <= 32) ? 1 : 2;
+    using G = Geom<NY, NZ, PB, Q, PADY, 32, MINW, YSW>;
 };
 
 // Register distribution of a first pass of radix R along axis AX: element (i, r) of a
