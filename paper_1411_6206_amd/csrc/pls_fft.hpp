@@ -19,6 +19,29 @@
 namespace pls {
 
 // ---------------------------------------------------------------- in-register DFTs
+// The largest prime-power factor of R when it is a proper factor (then R / it is coprime to
+// it), else 1.
+constexpr int pfa_n1(int R) {
+    int best = 1;
+    int r = R;
+    for (int p = 2; p <= r; ++p) {
+        if (r % p != 0) continue;
+        int q = 1;
+        while (r % p == 0) {
+            r /= p;
+            q *= p;
+        }
+        if (q > best) best = q;
+    }
+    return best < R ? best : 1;
+}
+// x with a x = 1 mod m (m > 1, gcd(a, m) = 1)
+constexpr int modinv_c(int a, int m) {
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 1;
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2* x) {
     if constexpr (R == 1) {
@@ -77,6 +100,35 @@ __device__ __forceinline__ void dft(float2* x) {
             out[R - k] = INV ? mib : pib;
         });
         sfor<R>([&](auto iI) __attribute__((always_inline)) { x[decltype(iI)::value] = out[decltype(iI)::value]; });
+    } else if constexpr (pfa_n1(R) > 1) {
+        // R = N1 N2 with N1, N2 coprime (Good-Thomas): with n = (N2 n1 + N1 n2) mod R and
+        // k = (N2 E1 k1 + N1 E2 k2) mod R, E1 = N2^-1 mod N1, E2 = N1^-1 mod N2, the kernel
+        // w_R^{nk} splits into w_N1^{n1 k1} w_N2^{n2 k2}: N1 DFTs of length N2, then N2 of
+        // length N1, with no twiddle factors between them (the index maps are register
+        // renamings)
+        constexpr int N1 = pfa_n1(R), N2 = R / N1;
+        constexpr int E1 = modinv_c(N2 % N1, N1), E2 = modinv_c(N1 % N2, N2);
+        float2 t[R];
+        sfor<N1>([&](auto aI) __attribute__((always_inline)) {
+            constexpr int n1 = decltype(aI)::value;
+            float2 y[N2];
+            sfor<N2>([&](auto bI) __attribute__((always_inline)) {
+                constexpr int n2 = decltype(bI)::value;
+                y[n2] = x[(N2 * n1 + N1 * n2) % R];
+            });
+            dft<N2, INV>(y);
+            sfor<N2>([&](auto kI) __attribute__((always_inline)) { t[n1 * N2 + decltype(kI)::value] = y[decltype(kI)::value]; });
+        });
+        sfor<N2>([&](auto kI) __attribute__((always_inline)) {
+            constexpr int k2 = decltype(kI)::value;
+            float2 z[N1];
+            sfor<N1>([&](auto aI) __attribute__((always_inline)) { z[decltype(aI)::value] = t[decltype(aI)::value * N2 + k2]; });
+            dft<N1, INV>(z);
+            sfor<N1>([&](auto cI) __attribute__((always_inline)) {
+                constexpr int k1 = decltype(cI)::value;
+                x[(N2 * E1 * k1 + N1 * E2 * k2) % R] = z[k1];
+            });
+        });
     } else {
         // R = A B:  X[c + A d] = sum_b w_B^{bd} w_R^{bc} sum_a x[B a + b] w_A^{ac}
         constexpr int A = (R % 4 == 0) ? 4 : ((R % 2 == 0) ? 2 : ((R % 3 == 0) ? 3 : ((R % 5 == 0) ? 5 : 7)));
