@@ -257,7 +257,11 @@ __global__ void __launch_bounds__(G::T, G::MINW) pls_dc_kernel(SRC src) {
         }
         fft2_inv<G, 2>(v, lds, twt, tidc);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] = cadd(acc[q], cmulc(v[q], sacc[q]));
+        for (int q = 0; q < Q; ++q) {
+            // acc += v conj(s), four FMAs
+            acc[q].x = fmaf(v[q].x, sacc[q].x, fmaf(v[q].y, sacc[q].y, acc[q].x));
+            acc[q].y = fmaf(v[q].y, sacc[q].x, fmaf(-v[q].x, sacc[q].y, acc[q].y));
+        }
     }
 #pragma unroll
     for (int i = 0; i < D0::NB; ++i) {
