@@ -18,11 +18,12 @@ import paper_1411_6206_amd as pls  # noqa: E402
 
 TOL, TOL_OP = 1e-4, 1e-5
 # (nx, ny, nz, nt, nc, J): P = ny nz not a multiple of the 32-line tile (16 x 1), radix-3
-# lengths (24, 48, 96), every depth, nz = 1 (2D), the largest line (nx = 256) and plane
+# lengths (24, 48, 96), every depth, nz = 1 (2D), the largest line (nx = 256) and plane, and
+# the 192 x 192 x 32 benchmark volume's plane (6144 points) and line (192)
 STEP_CASES = [
     (16, 16, 1, 3, 1, 1), (32, 16, 4, 4, 2, 2), (24, 48, 8, 3, 2, 3), (48, 32, 8, 5, 1, 2),
     (16, 96, 16, 2, 2, 1), (256, 16, 8, 2, 1, 3), (16, 256, 32, 2, 1, 2), (64, 24, 4, 3, 1, 2),
-    (32, 32, 14, 3, 1, 1),
+    (32, 32, 14, 3, 1, 1), (16, 192, 32, 2, 1, 2), (192, 16, 8, 2, 1, 3),
 ]
 
 
