@@ -209,8 +209,8 @@ typedef struct {
     int32_t sparse_fork;        /* 0: the sparse update runs beside the reduction / eigensolve
                                    / back-projection (forked after the Gram pass); 1: beside
                                    the whole chain (forked before the Gram pass); 2: on the
-                                   main stream after the Gram pass, every kernel alone (not
-                                   tried by the autotuner; for per-kernel timing) */
+                                   main stream after the Gram pass, every kernel alone (the
+                                   serial schedule, also used for per-kernel timing) */
     int32_t sparse_grid;        /* Haar sparse update: workgroups at most, each looping over
                                    tiles (fewer leave more bandwidth to the chain it runs
                                    beside): 0 (one per tile) or 64..65536 */

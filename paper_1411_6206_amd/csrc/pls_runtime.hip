@@ -1147,7 +1147,9 @@ int prior_ls_tune(prior_ls_handle* h, const prior_ls_inputs* in, const prior_ls_
         double best_ms = time_choice(h, in, &p, e0, e1);
         if (best_ms < 0) return fail(h, PRIOR_LS_EINVAL, "cannot load the problem");
         // one knob at a time, each from the best choice so far
-        const int forks[] = {0, 1};
+        // the serial schedule (2) can win for small problems, where the second stream's
+        // fork and join cost more than the overlap saves
+        const int forks[] = {0, 1, 2};
         const int grams[] = {256, 512, 1024, 2048};
         const int grids[] = {1024, 2048, 4096, 8192};
         // fewer sparse-update workgroups leave more bandwidth to the chain it runs beside
