@@ -250,10 +250,10 @@ def serving_bench(budget_gib, forms):
     return out
 
 
-def batching_bench(steps, warmup):
+def batching_bench(steps, warmup, gram_mode):
     """Batched iterations (prior_ls_batch_*) of the small configurations: B problems of one
     geometry advanced with one launch per kernel, against one problem alone (tuned by its
-    autotuner first)."""
+    autotuner first), all with the given Gram mode."""
     import torch
     import synth
     import paper_1411_6206_amd as pls
@@ -264,7 +264,7 @@ def batching_bench(steps, warmup):
         J = 2
         kw = dict(lambda_L=p.lambda_L, lambda_S=p.lambda_S)
         # one problem on its own handle (hipGraph chunks of 10 iterations)
-        with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) as h:
+        with pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J, gram_mode=gram_mode) as h:
             single = h.tune(t["kspace"], t["mask"], t["sens"], t["prior_w"], check_every=10, **kw)
             h.step(warmup, outputs=())
             torch.cuda.synchronize()
@@ -272,15 +272,14 @@ def batching_bench(steps, warmup):
             h.step(steps, outputs=())
             torch.cuda.synchronize()
             alone = steps / (time.perf_counter() - a0)
-        rec = {"workload": f"{p.nx}x{p.ny}x{p.nz} voxels x {p.nt} frames x {p.nc} coil(s)",
+        rec = {"workload": f"{p.nx}x{p.ny}x{p.nz} voxels x {p.nt} frames x {p.nc} coil(s), "
+                           f"{gram_mode.upper()} Gram",
                "alone_iterations_per_s": alone, "batches": {}}
-        for B in sizes:
-            hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J) for _ in range(B)]
-            # launch shapes of the batch (taken from its first handle): one problem keeps the
-            # autotuner's choice; several fork the sparse update before the Gram and cap it
-            # at about 512 workgroups in all (measured best for B = 4-32 at both sizes)
-            tb = dict(single) if B == 1 else dict(single, sparse_fork=1,
-                                                  sparse_grid=max(64, 512 // B))
+        def run_batch(B, tb, n):
+            """B copies of the problem as one batch with launch shapes tb: batched
+            iterations/s over n iterations after the warm-up."""
+            hs = [pls.PriorLS(p.nx, p.ny, p.nz, p.nt, p.nc, wavelet_levels=J, gram_mode=gram_mode)
+                  for _ in range(B)]
             for hh in hs:
                 hh.set_tuning(tb["gram_blocks"], tb["bp_grid"], tb["sparse_fork"],
                               tb["sparse_grid"])
@@ -289,14 +288,31 @@ def batching_bench(steps, warmup):
                     b.solve([t] * B, pls.make_params(max_iter=warmup, **kw), outputs=())
                     torch.cuda.synchronize()
                     a0 = time.perf_counter()
-                    b.step(steps, outputs=())
+                    b.step(n, outputs=())
                     torch.cuda.synchronize()
                     el = time.perf_counter() - a0
             finally:
                 for hh in hs:
                     hh.close()
-            rec["batches"][str(B)] = {"iterations_per_s": B * steps / el,
-                                      "speedup_vs_alone": B * steps / el / alone,
+            return B * n / el
+
+        for B in sizes:
+            # launch shapes of the batch (taken from its first handle): one problem keeps the
+            # autotuner's choice; several take the fastest of a few sparse-update schedules
+            # (fork after or before the Gram, about 512 workgroups in all, 256 per problem,
+            # or one per tile), each timed over 20 iterations of a batch of its own
+            if B == 1:
+                tb = dict(single)
+            else:
+                cands = [(1, max(64, 512 // B)), (0, max(64, 512 // B)), (0, 256), (1, 256),
+                         (1, 0)]
+                trial = {c: run_batch(B, dict(single, sparse_fork=c[0], sparse_grid=c[1]),
+                                      min(steps, 20)) for c in cands}
+                fork, grid = max(trial, key=trial.get)
+                tb = dict(single, sparse_fork=fork, sparse_grid=grid)
+            rate = run_batch(B, tb, steps)
+            rec["batches"][str(B)] = {"iterations_per_s": rate,
+                                      "speedup_vs_alone": rate / alone,
                                       "tuning": {k: tb[k] for k in ("sparse_fork", "sparse_grid")}}
         res[f"c{cfg}"] = rec
         del t, p
@@ -638,7 +654,7 @@ def main():
     del t
     torch.cuda.empty_cache()
     if not args.no_batching:
-        out["batching"] = batching_bench(args.steps, args.warmup)
+        out["batching"] = batching_bench(args.steps, args.warmup, args.gram_mode)
     if not args.no_serving:
         # one sequence at a time against groups of up to 8 sequences of one geometry
         # advanced as batches, and the split-BF16 Gram form grouped
