@@ -928,7 +928,7 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
                 // every thread takes at most one A item (half^2 <= 256) and one V item
                 // (ne half <= 512), their entries loaded above; only the rotations are read
                 // here
-                static_assert(NT >= NMAX * NMAX / 2, "one A and one V item per thread");
+                // the launcher takes NT >= ne half, so no item is left over
                 AItem xa;
                 xa.p = ip; xa.q = iq; xa.u = iu; xa.w = iw;
                 xa.diag = ial == ibe;
@@ -1042,12 +1042,17 @@ __global__ void __launch_bounds__(NT) pls_eig_kernel(SRC src) {
     }
 }
 
-// Windows of up to 16 frames take two waves (one A item and one V item per thread still
-// covers a round; the round's block barrier spans fewer waves): 4-18% faster than eight at
-// nt = 3..16, same results bit for bit.  A batch holds one tile class, so problem 0's nt
-// decides for every member.
+// With NMAX <= 32 a thread takes at most one A item and one V item per round, so the block
+// needs ne half <= NT threads (ne = nt rounded up to even).  Fewer waves make the round's
+// block barrier cheaper: windows of up to 16 frames take two waves (4-18% faster than eight
+// at nt = 3..16), one problem of 17..24 frames five (about 5% faster at nt = 24); results
+// are the same bit for bit.  A batch holds one tile class, so problem 0's nt bounds every
+// member's only up to 16 frames: batches of 17..32 frames keep eight waves.
 void launch_eig_batched(const EigArgs& a, const Batched<EigArgs>* bt, hipStream_t s) {
+    const int ne = a.nt + (a.nt & 1);
     if (a.nt <= 16) PLS_LAUNCH(dim3(1), dim3(128), s, a, bt, pls_eig_kernel, 128, 16);
+    else if (a.nt <= 32 && !bt && ne * (ne / 2) <= 320)
+        PLS_LAUNCH(dim3(1), dim3(320), s, a, bt, pls_eig_kernel, 320, 32);
     else if (a.nt <= 32) PLS_LAUNCH(dim3(1), dim3(kEigThreads), s, a, bt, pls_eig_kernel, kEigThreads, 32);
     else PLS_LAUNCH(dim3(1), dim3(kEigThreads), s, a, bt, pls_eig_kernel, kEigThreads, 64);
 }
